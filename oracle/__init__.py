@@ -1,0 +1,131 @@
+"""CPU oracle for the assignment and transportation problems (ctypes wrapper).
+
+TEST INFRASTRUCTURE ONLY: imported by the test suite, the smoke check and the
+CPU-baseline leg of the benchmark, never by the product package.  The C
+source (``oracle.c``) is compiled with gcc on first use (or by ``build()``)
+into ``liboracle.so`` next to it.
+
+Functions (all exact, int64 results):
+
+* ``assign(C)``             -> (plan, cost, u, v)   shortest-augmenting-path KM, O(n^3)
+* ``brute_force(C)``        -> (best, num_optimal)  all n! permutations, n <= 10
+* ``certify_assign(C, plan, u, v)``   -> 0 if the LP-duality certificate holds
+* ``transport(C, r, c)``    -> (X, cost, u, v)      unit expansion + ``assign``
+* ``certify_transport(C, r, c, X, u, v)`` -> 0 if the certificate holds
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+import threading
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lock = threading.Lock()
+_lib = None
+
+_I32P = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
+_I64P = np.ctypeslib.ndpointer(dtype=np.int64, flags="C_CONTIGUOUS")
+
+
+def build(force: bool = True, extra_flags=()) -> str:
+    """Compile oracle.c into liboracle.so (plain C, -O2, single-threaded)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-Wall", "-Wextra", *extra_flags, _SRC, "-o", tmp]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    with _lock:
+        if _lib is None:
+            build(force=False)
+            lib = ctypes.CDLL(_LIB)
+            i32, i64p = ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)
+            lib.oracle_assign.argtypes = [_I32P, i32, _I32P, _I64P, _I64P, i64p]
+            lib.oracle_brute_force.argtypes = [_I32P, i32, i64p, i64p]
+            lib.oracle_certify_assign.argtypes = [_I32P, i32, _I32P, _I64P, _I64P]
+            lib.oracle_transport.argtypes = [_I32P, _I32P, _I32P, i32, i32, _I32P, _I64P, _I64P, i64p]
+            lib.oracle_certify_transport.argtypes = [_I32P, _I32P, _I32P, i32, i32, _I32P, _I64P, _I64P]
+            for f in (lib.oracle_assign, lib.oracle_brute_force, lib.oracle_certify_assign,
+                      lib.oracle_transport, lib.oracle_certify_transport):
+                f.restype = ctypes.c_int
+            _lib = lib
+    return _lib
+
+
+def _square(C) -> np.ndarray:
+    C = np.ascontiguousarray(C, dtype=np.int32)
+    if C.ndim != 2 or C.shape[0] != C.shape[1] or C.shape[0] == 0:
+        raise ValueError("cost matrix must be square and non-empty")
+    return C
+
+
+def assign(C):
+    """Exact assignment: returns (plan int32[n], cost int, u int64[n], v int64[n])."""
+    C = _square(C)
+    n = C.shape[0]
+    plan = np.empty(n, np.int32)
+    u = np.empty(n, np.int64)
+    v = np.empty(n, np.int64)
+    cost = ctypes.c_int64(0)
+    rc = _load().oracle_assign(C, n, plan, u, v, ctypes.byref(cost))
+    if rc:
+        raise RuntimeError("oracle_assign failed: %d" % rc)
+    return plan, int(cost.value), u, v
+
+
+def brute_force(C):
+    """Minimum cost over all permutations and the number of optimal ones (n <= 10)."""
+    C = _square(C)
+    best = ctypes.c_int64(0)
+    cnt = ctypes.c_int64(0)
+    rc = _load().oracle_brute_force(C, C.shape[0], ctypes.byref(best), ctypes.byref(cnt))
+    if rc:
+        raise RuntimeError("oracle_brute_force failed: %d" % rc)
+    return int(best.value), int(cnt.value)
+
+
+def certify_assign(C, plan, u, v) -> int:
+    """0 when (plan, u, v) certifies optimality; else the failing condition (1-4)."""
+    C = _square(C)
+    n = C.shape[0]
+    plan = np.ascontiguousarray(plan, dtype=np.int32)
+    u = np.ascontiguousarray(u, dtype=np.int64)
+    v = np.ascontiguousarray(v, dtype=np.int64)
+    if plan.shape != (n,) or u.shape != (n,) or v.shape != (n,):
+        return 1
+    return int(_load().oracle_certify_assign(C, n, plan, u, v))
+
+
+def transport(C, r, c):
+    """Exact integer transport: returns (X int32[n,m], cost int, u int64[n], v int64[m])."""
+    C = np.ascontiguousarray(C, dtype=np.int32)
+    r = np.ascontiguousarray(r, dtype=np.int32)
+    c = np.ascontiguousarray(c, dtype=np.int32)
+    n, m = C.shape
+    X = np.empty((n, m), np.int32)
+    u = np.empty(n, np.int64)
+    v = np.empty(m, np.int64)
+    cost = ctypes.c_int64(0)
+    rc = _load().oracle_transport(C, r, c, n, m, X, u, v, ctypes.byref(cost))
+    if rc:
+        raise RuntimeError("oracle_transport failed: %d" % rc)
+    return X, int(cost.value), u, v
+
+
+def certify_transport(C, r, c, X, u, v) -> int:
+    """0 when (X, u, v) certifies an optimal transport plan; else the failing condition (1-5)."""
+    C = np.ascontiguousarray(C, dtype=np.int32)
+    n, m = C.shape
+    return int(_load().oracle_certify_transport(
+        C, np.ascontiguousarray(r, dtype=np.int32), np.ascontiguousarray(c, dtype=np.int32), n, m,
+        np.ascontiguousarray(X, dtype=np.int32), np.ascontiguousarray(u, dtype=np.int64),
+        np.ascontiguousarray(v, dtype=np.int64)))

@@ -1,0 +1,280 @@
+"""Pins for the CPU oracle: values fixed by the mathematics, not by the oracle itself.
+
+Problem statement: Eq. (1) of the paper (min <C, X> with X 1 = r, X^T 1 = c);
+assignment is its r = c = 1 special case.  The paper prints no objective value
+for any instance, so the pins are brute force, closed forms, LP duality,
+independent library solvers (scipy's Jonker-Volgenant, HiGHS LP, networkx
+network simplex) and metamorphic invariants.
+"""
+import itertools
+import json
+import os
+
+import numpy as np
+import pytest
+from scipy.optimize import linear_sum_assignment, linprog
+
+import oracle
+from paper_2005_01182_amd import workloads as wl
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def py_brute(C):
+    """Plain Python enumeration of all permutations: (min cost, #optimal)."""
+    n = C.shape[0]
+    best, cnt = None, 0
+    for p in itertools.permutations(range(n)):
+        s = int(sum(int(C[i, p[i]]) for i in range(n)))
+        if best is None or s < best:
+            best, cnt = s, 1
+        elif s == best:
+            cnt += 1
+    return best, cnt
+
+
+def check_assign(C):
+    plan, cost, u, v = oracle.assign(C)
+    assert oracle.certify_assign(C, plan, u, v) == 0
+    assert cost == int(C[np.arange(C.shape[0]), plan].astype(np.int64).sum())
+    return plan, cost, u, v
+
+
+# ----------------------------------------------------------------------------- brute force
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 6, 7])
+@pytest.mark.parametrize("kind", ["ties", "wide", "negative"])
+def test_brute_force_small(n, kind):
+    rng = np.random.default_rng(1000 * n + len(kind))
+    for _ in range(6 if n <= 6 else 2):
+        if kind == "ties":
+            C = rng.integers(0, 3, (n, n), endpoint=True)
+        elif kind == "wide":
+            C = rng.integers(0, 1_000_000, (n, n))
+        else:
+            C = rng.integers(-500, 500, (n, n))
+        C = C.astype(np.int32)
+        best, cnt = py_brute(C)
+        _, cost, _, _ = check_assign(C)
+        assert cost == best
+        cb, cc = oracle.brute_force(C)
+        assert (cb, cc) == (best, cnt)
+
+
+def test_brute_force_n8_extreme_values():
+    rng = np.random.default_rng(8)
+    C = rng.integers(-(2**30), 2**30, (8, 8)).astype(np.int32)
+    cb, _ = oracle.brute_force(C)
+    _, cost, _, _ = check_assign(C)
+    assert cost == cb
+
+
+# ----------------------------------------------------------------------------- closed forms
+def test_additive_costs_every_plan_optimal():
+    rng = np.random.default_rng(3)
+    a = rng.integers(-1000, 1000, 40)
+    b = rng.integers(-1000, 1000, 40)
+    C = (a[:, None] + b[None, :]).astype(np.int32)
+    _, cost, u, v = check_assign(C)
+    assert cost == int(a.sum() + b.sum())
+    # (a, b) is itself an optimal dual
+    assert oracle.certify_assign(C, np.arange(40, dtype=np.int32), a, b) == 0
+
+
+def test_planted_zero_permutation_unique():
+    rng = np.random.default_rng(4)
+    n = 50
+    p = rng.permutation(n)
+    C = rng.integers(1, 100, (n, n)).astype(np.int32)
+    C[np.arange(n), p] = 0
+    plan, cost, _, _ = check_assign(C)
+    assert cost == 0
+    assert np.array_equal(plan, p)
+
+
+def test_constant_and_single():
+    C = np.full((17, 17), 42, np.int32)
+    assert check_assign(C)[1] == 17 * 42
+    assert check_assign(np.array([[-7]], np.int32))[1] == -7
+
+
+@pytest.mark.parametrize("power", [1, 2])
+def test_monge_line_sorted_matching(power):
+    # For C_ij = h(x_i - y_j) with h convex, matching sorted x to sorted y is optimal.
+    rng = np.random.default_rng(5 + power)
+    x = np.sort(rng.integers(0, 300, 60))
+    y = np.sort(rng.integers(0, 300, 60))
+    C = (np.abs(x[:, None] - y[None, :]) ** power).astype(np.int32)
+    _, cost, _, _ = check_assign(C)
+    assert cost == int(np.abs(x - y).astype(np.int64).__pow__(power).sum())
+
+
+# ----------------------------------------------------------------------------- library cross-check
+@pytest.mark.parametrize("n,kind", [(50, "uniform"), (120, "geo"), (200, "uniform"), (256, "geo"), (96, "emb")])
+def test_against_scipy(n, kind):
+    if kind == "uniform":
+        C = wl.uniform_assignment(n, seed=n)
+    elif kind == "geo":
+        C = wl.geometric_assignment(n, seed=n)
+    else:
+        C = wl.embedding_problem(n, seed=0, k=n)
+    _, cost, _, _ = check_assign(C)
+    r, c = linear_sum_assignment(C.astype(np.float64))
+    assert cost == int(C[r, c].astype(np.int64).sum())
+
+
+# ----------------------------------------------------------------------------- metamorphic
+def test_metamorphic_invariants():
+    rng = np.random.default_rng(9)
+    n = 70
+    C = rng.integers(0, 50, (n, n)).astype(np.int32)
+    base = check_assign(C)[1]
+    P, Q = rng.permutation(n), rng.permutation(n)
+    assert check_assign(np.ascontiguousarray(C[P][:, Q]))[1] == base
+    a, b = rng.integers(-100, 100, n), rng.integers(-100, 100, n)
+    assert check_assign((C + a[:, None] + b[None, :]).astype(np.int32))[1] == base + int(a.sum() + b.sum())
+    assert check_assign(np.ascontiguousarray(C.T))[1] == base
+    assert check_assign(C * 7)[1] == 7 * base
+
+
+# ----------------------------------------------------------------------------- certificate
+def test_certificate_rejects_mutations():
+    C = wl.uniform_assignment(30, seed=11)
+    plan, cost, u, v = oracle.assign(C)
+    assert oracle.certify_assign(C, plan, u, v) == 0
+    bad = plan.copy(); bad[0] = bad[1]
+    assert oracle.certify_assign(C, bad, u, v) == 1
+    uu = u.copy(); uu[3] += 1
+    assert oracle.certify_assign(C, plan, uu, v) in (2, 3)
+    vv = v.copy(); vv[5] -= 1
+    assert oracle.certify_assign(C, plan, u, vv) == 3
+    swapped = plan.copy(); swapped[[0, 1]] = swapped[[1, 0]]
+    if int(C[np.arange(30), swapped].sum()) != cost:
+        assert oracle.certify_assign(C, swapped, u, v) != 0
+
+
+# ----------------------------------------------------------------------------- transport
+def lp_transport_cost(C, r, c):
+    n, m = C.shape
+    A_eq = np.zeros((n + m, n * m))
+    for i in range(n):
+        A_eq[i, i * m:(i + 1) * m] = 1
+    for j in range(m):
+        A_eq[n + j, j::m] = 1
+    res = linprog(C.reshape(-1).astype(np.float64), A_eq=A_eq, b_eq=np.concatenate([r, c]).astype(np.float64),
+                  bounds=(0, None), method="highs")
+    assert res.status == 0
+    return res.fun
+
+
+def test_transport_line_closed_form():
+    rng = np.random.default_rng(12)
+    for trial in range(5):
+        n = 12
+        r = rng.integers(0, 6, n); c = rng.integers(0, 6, n)
+        d = r.sum() - c.sum()
+        if d > 0: c[0] += d
+        else: r[0] -= d
+        if r.sum() == 0:
+            continue
+        C = np.abs(np.arange(n)[:, None] - np.arange(n)[None, :]).astype(np.int32)
+        X, cost, u, v = oracle.transport(C, r, c)
+        assert oracle.certify_transport(C, r, c, X, u, v) == 0
+        R, S = np.cumsum(r), np.cumsum(c)
+        assert cost == int(np.abs(R - S)[:-1].sum())
+
+
+def test_transport_vs_lp_and_network_flow():
+    import networkx as nx
+    C, r, c = wl.pixel_histogram_pair(side=8, seeds=(3, 4), total=40)
+    X, cost, u, v = oracle.transport(C, r, c)
+    assert oracle.certify_transport(C, r, c, X, u, v) == 0
+    assert abs(lp_transport_cost(C, r, c) - cost) < 1e-6
+    G = nx.DiGraph()
+    n, m = C.shape
+    for i in range(n):
+        G.add_node(("r", i), demand=-int(r[i]))
+    for j in range(m):
+        G.add_node(("c", j), demand=int(c[j]))
+    for i in range(n):
+        for j in range(m):
+            G.add_edge(("r", i), ("c", j), weight=int(C[i, j]))
+    assert nx.min_cost_flow_cost(G) == cost
+
+
+def test_transport_unit_masses_equal_assignment():
+    C = wl.uniform_assignment(25, seed=13)
+    one = np.ones(25, np.int32)
+    X, cost, u, v = oracle.transport(C, one, one)
+    assert cost == oracle.assign(C)[1]
+    assert (X.sum(0) == 1).all() and (X.sum(1) == 1).all()
+
+
+def test_transport_rectangular_and_zero_bins():
+    rng = np.random.default_rng(14)
+    C = rng.integers(0, 30, (6, 9)).astype(np.int32)
+    r = np.array([3, 0, 2, 0, 4, 1], np.int32)
+    c = np.array([0, 2, 2, 0, 3, 1, 0, 1, 1], np.int32)
+    X, cost, u, v = oracle.transport(C, r, c)
+    assert oracle.certify_transport(C, r, c, X, u, v) == 0
+    assert abs(lp_transport_cost(C, r, c) - cost) < 1e-6
+
+
+def test_transport_zero_mass_dual_convention():
+    # Zero-mass bins carry no mass, so any feasible value certifies; the convention
+    # fixes the tightest one: a zero-mass row is tight on some column with mass,
+    # a zero-mass column is tight on some row.
+    C, r, c = wl.pixel_histogram_pair(side=7, seeds=(7, 8), total=30)
+    X, cost, u, v = oracle.transport(C, r, c)
+    assert oracle.certify_transport(C, r, c, X, u, v) == 0
+    red = C.astype(np.int64) - u[:, None] - v[None, :]
+    assert (r == 0).any() and (c == 0).any()
+    for i in np.nonzero(r == 0)[0]:
+        assert red[i, c > 0].min() == 0
+    for j in np.nonzero(c == 0)[0]:
+        assert red[:, j].min() == 0
+
+
+def test_transport_certificate_rejects_mutations():
+    C, r, c = wl.pixel_histogram_pair(side=6, seeds=(5, 6), total=20)
+    X, cost, u, v = oracle.transport(C, r, c)
+    assert oracle.certify_transport(C, r, c, X, u, v) == 0
+    Xb = X.copy(); i, j = np.argwhere(X > 0)[0]; Xb[i, j] -= 1
+    assert oracle.certify_transport(C, r, c, Xb, u, v) == 2
+    ub = u.copy(); ub[np.argmax(r)] += 1
+    assert oracle.certify_transport(C, r, c, X, ub, v) in (3, 4, 5)
+
+
+def test_transport_rejects_bad_masses():
+    C = np.zeros((3, 3), np.int32)
+    with pytest.raises(RuntimeError):
+        oracle.transport(C, np.array([1, 1, 1], np.int32), np.array([1, 1, 0], np.int32))
+    with pytest.raises(RuntimeError):
+        oracle.transport(C, np.array([2, -1, 1], np.int32), np.array([1, 1, 0], np.int32))
+
+
+# ----------------------------------------------------------------------------- golden fixtures
+def test_golden_fixtures():
+    with open(os.path.join(GOLDEN, "hand_examples.json")) as f:
+        cases = json.load(f)
+    for case in cases["assign"]:
+        C = np.array(case["C"], np.int32)
+        plan, cost, u, v = check_assign(C)
+        assert cost == case["cost"], case["name"]
+        if case.get("unique_plan"):
+            assert plan.tolist() == case["plan"], case["name"]
+    for case in cases["transport"]:
+        C = np.array(case["C"], np.int32)
+        r = np.array(case["r"], np.int32); c = np.array(case["c"], np.int32)
+        X, cost, u, v = oracle.transport(C, r, c)
+        assert oracle.certify_transport(C, r, c, X, u, v) == 0
+        assert cost == case["cost"], case["name"]
+
+
+def test_golden_generated_costs_match():
+    """Optimal costs stored by tests/golden/make_golden.py (oracle only) still reproduce."""
+    with open(os.path.join(GOLDEN, "oracle_costs.json")) as f:
+        stored = json.load(f)
+    C = wl.uniform_assignment(64, seed=0)
+    assert oracle.assign(C)[1] == stored["uniform_n64_seed0"]
+    C = wl.geometric_assignment(128, seed=0)
+    assert oracle.assign(C)[1] == stored["geometric_n128_seed0"]
