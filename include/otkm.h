@@ -1,0 +1,200 @@
+/*
+ * otkm.h -- C-ABI of the MI355X (gfx950) batched Kuhn-Munkres solver.
+ *
+ * Problem (Eq. (1) of "A Study of Performance of Optimal Transport",
+ * Section 1):
+ *     minimise <C, X>  subject to  X 1 = r,  X^T 1 = c,  X >= 0,
+ * with integer supplies r and demands c (the Hitchcock-Koopmans case); the
+ * assignment problem is the case r = c = 1, n = m.
+ *
+ * Method (Section 2.3.1, "Batched KM"): a Kuhn-Munkres variant that grows
+ * alternating trees from all free rows at once, augments the matching along
+ * every vertex-disjoint augmenting path it finds among tight edges, and only
+ * when none exists adjusts the dual potentials across the cut between the
+ * reached and unreached vertices, by the smallest slack, as KM does.
+ * Integer transport is reduced to assignment by giving each unit of supply and
+ * demand its own vertex (the S = sum r unit expansion of Section 2.3.1).
+ *
+ * Arithmetic is exact: int32 costs and masses, int64 duals and totals.
+ * Every result is optimal; when several optimal plans exist any one of them
+ * may be returned (the solver is deterministic for a given input).  The
+ * duals always form an LP certificate:
+ *     u_i + v_j <= C_ij  for all i, j,
+ *     u_i + v_j == C_ij  wherever the plan is positive,
+ *     sum_i r_i u_i + sum_j c_j v_j == cost.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  * Matrices are row-major; row i is a supply (left) vertex, column j a
+ *    demand (right) vertex; entry (i, j) sits at C[i * ld + j] (ld = n or m
+ *    unless stated).
+ *  * Cost range: max(C) - min(C) must be <= 2^31 - 1 (OT_ERANGE otherwise);
+ *    this bounds every reduced cost the solver stores by 2^32.
+ *  * Size limit: the on-chip solver holds one instance's row and column state
+ *    in a workgroup's LDS, so n (or S = sum r for transport) must be
+ *    <= OT_MAX_N (OT_ETOOBIG otherwise).
+ *  * Ownership: the caller allocates and owns every input and output buffer.
+ *    The library never keeps a caller pointer after a synchronous call
+ *    returns; asynchronous (_dev) calls read and write caller buffers until
+ *    the work queued on the given stream completes.  Device scratch is owned
+ *    by the library (a per-process, per-device pool, freed at exit).
+ *  * Errors: every call returns OT_OK (0) or a negative ot_status.  On error,
+ *    host outputs are left untouched.  ot_strerror() names a code.
+ *  * Threads: calls from several host threads are allowed; each synchronous
+ *    call serialises on the library's own stream for the current device.
+ */
+#ifndef OTKM_H
+#define OTKM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define OT_MAX_N 4096
+
+typedef enum ot_status {
+    OT_OK = 0,
+    OT_EINVAL = -1,       /* null pointer, n <= 0, m <= 0, count < 0, bad option */
+    OT_ERANGE = -2,       /* max(C) - min(C) > 2^31 - 1 */
+    OT_EUNBALANCED = -3,  /* sum r != sum c, or sum r == 0 */
+    OT_ENEGMASS = -4,     /* some r_i < 0 or c_j < 0 */
+    OT_ETOOBIG = -5,      /* n (or sum r) > OT_MAX_N, or over the device budget */
+    OT_ENOMEM = -6,       /* host or device allocation failed */
+    OT_EDEVICE = -7,      /* a HIP runtime call failed */
+    OT_ENODEV = -8,       /* no usable gfx950 device */
+    OT_EINTERNAL = -9     /* solver watchdog or invariant check tripped */
+} ot_status;
+
+/* Per-solve counters (written when a stats pointer is given).  A "level" is
+ * one step of the solver: sweep the rows that just joined the forest, take
+ * the smallest reduced cost over unreached columns, and settle every column
+ * at that value. */
+typedef struct ot_stats {
+    int64_t levels;        /* solver steps */
+    int64_t dual_adjusts;  /* steps that raised the duals across the cut (Section 2.3.1) */
+    int64_t aug_events;    /* steps that augmented along at least one path */
+    int64_t paths;         /* augmenting paths applied (== n for assignment) */
+    int64_t rows_swept;    /* full cost rows read: 2n at initialisation + frontier + re-sweeps */
+    int64_t gathers;       /* single cost entries re-read to refresh stale column minima */
+    int64_t resweeps;      /* full re-sweeps of the forest */
+    int64_t status;        /* device-side ot_status of this solve */
+    int64_t t_sweep_ns;    /* device time in each phase of the level loop, */
+    int64_t t_select_ns;   /*   measured by the workgroup's first wavefront  */
+    int64_t t_settle_ns;   /*   (sweep / minimum selection incl. refreshes /  */
+    int64_t t_augment_ns;  /*   settling / augmenting); OT_FLAG_PHASE_TIMERS  */
+    int64_t refreshes;     /* steps that recomputed stale column minima */
+    int64_t refresh_cols;  /* stale columns recomputed, summed over those steps */
+    int64_t t_refresh_ns;  /* part of t_select_ns spent recomputing stale minima */
+} ot_stats;
+
+/* Collect the per-phase device times (t_*_ns) in ot_stats; off by default
+ * because reading the device clock adds latency to every level. */
+#define OT_FLAG_PHASE_TIMERS 1
+
+/* Solver options; pass NULL for the defaults (all zero). */
+typedef struct ot_options {
+    int32_t max_paths;     /* trees grown at once: 0 = every free row (Batched KM),
+                              1 = one tree at a time (classical KM), k = at most k */
+    int32_t block;         /* workgroup width: 0 = automatic, else 64, 256, 512 or 1024 */
+    int32_t flags;         /* OT_FLAG_* bits */
+    int32_t reserved[5];   /* must be zero */
+} ot_options;
+
+/* Status text for a code; never NULL. */
+const char *ot_strerror(int status);
+
+/* Device check: 0 when a gfx950 device is usable, else OT_ENODEV / OT_EDEVICE. */
+int ot_init(void);
+
+/* ------------------------------------------------------------------------ */
+/* Host-buffer calls (synchronous)                                           */
+/* ------------------------------------------------------------------------ */
+
+/* Assignment (Eq. (1) with r = c = 1).
+ *   C    [n*n]  int32 costs (row-major, ld = n)
+ *   plan [n]    out: plan[i] = column assigned to row i (a permutation)
+ *   cost        out: sum_i C[i, plan[i]]
+ *   u [n], v [n] out: optimal duals (may be NULL to skip)
+ */
+int ot_assign(const int32_t *C, int32_t n, int32_t *plan, int64_t *cost, int64_t *u, int64_t *v);
+
+/* ot_assign with options and counters (opt and stats may be NULL). */
+int ot_assign_ex(const int32_t *C, int32_t n, const ot_options *opt, int32_t *plan, int64_t *cost,
+                 int64_t *u, int64_t *v, ot_stats *stats);
+
+/* Integer transport (Eq. (1), Hitchcock-Koopmans case).
+ *   C [n*m] int32 costs (ld = m); r [n], c [m] int32 masses, >= 0, equal sums S >= 1.
+ *   X [n*m] out: int32 optimal plan.   cost out: <C, X>.
+ *   u [n], v [m] out: optimal bin duals (may be NULL).  Bins of zero mass get
+ *   the tightest feasible dual: a zero-mass row takes min over columns with
+ *   mass of C_ij - v_j, then a zero-mass column takes min over rows of C_ij - u_i.
+ * Solved by unit expansion (S x S assignment), so S <= OT_MAX_N.
+ */
+int ot_transport(const int32_t *C, const int32_t *r, const int32_t *c, int32_t n, int32_t m,
+                 int32_t *X, int64_t *cost, int64_t *u, int64_t *v);
+
+/* Many independent assignments in one persistent launch.
+ *   C[k] [n[k]*n[k]], plan[k] [n[k]], u[k], v[k] [n[k]] (u, v arrays or their
+ *   entries may be NULL); cost [count]; status [count] per-instance ot_status.
+ * Returns OT_OK when the batch ran (check status[] per instance), or an error
+ * for the whole call.  Instances are scheduled longest-first over persistent
+ * workgroups; the workgroup width per instance comes from the size-class
+ * schedule (see ot_schedule_*).
+ */
+int ot_assign_batch(int32_t count, const int32_t *const *C, const int32_t *n, int32_t *const *plan,
+                    int64_t *cost, int64_t *const *u, int64_t *const *v, int32_t *status);
+
+/* ------------------------------------------------------------------------ */
+/* Device-buffer calls (asynchronous on `stream`, a hipStream_t or NULL for  */
+/* the library stream).  All pointers are device pointers; the call only     */
+/* validates scalars on the host and reports data-dependent errors (cost    */
+/* range, watchdog) in stats->status / status[k] on the device.             */
+/* ------------------------------------------------------------------------ */
+
+/* Assignment on device memory.  dC [n*ld] (ld >= n), dplan [n], dcost [1],
+ * du [n], dv [n] (du/dv may be NULL), dstats [1] (may be NULL). */
+int ot_assign_dev(const int32_t *dC, int32_t n, int32_t ld, const ot_options *opt, int32_t *dplan,
+                  int64_t *dcost, int64_t *du, int64_t *dv, ot_stats *dstats, void *stream);
+
+/* Batch on device memory.  Instance k: cost matrix at dC + coff[k] (dense,
+ * ld = n[k]), plan/u/v at dplan/du/dv + voff[k]; dcost [count];
+ * dstats [count] (may be NULL).  coff, voff, n are DEVICE arrays [count];
+ * order is a device array [count] giving the processing order (longest
+ * first is best; NULL = index order).  block selects the workgroup width
+ * (64, 256 or 1024; 0 = from max_n via the schedule); max_n bounds every n[k].
+ * The launch uses a device queue head that the call resets with a kernel, so
+ * the call may be captured into a hipGraph and replayed. */
+int ot_assign_batch_dev(int32_t count, int32_t max_n, const int32_t *dC, const int64_t *coff,
+                        const int32_t *n, const int64_t *voff, const int32_t *order, int32_t block,
+                        int32_t *dplan, int64_t *dcost, int64_t *du, int64_t *dv, ot_stats *dstats,
+                        void *stream);
+
+/* Integer transport on device memory (same semantics as ot_transport).
+ * dC [n*m], dr [n], dc [m]; dX [n*m]; dcost [1]; du [n]; dv [m];
+ * dstats [1] may be NULL.  S = sum r must be passed (the host knows it when
+ * it built r) and must equal sum r = sum c; the device checks the masses and
+ * reports OT_EUNBALANCED / OT_ENEGMASS in dstats->status. */
+int ot_transport_dev(const int32_t *dC, const int32_t *dr, const int32_t *dc, int32_t n, int32_t m,
+                     int32_t S, int32_t *dX, int64_t *dcost, int64_t *du, int64_t *dv,
+                     ot_stats *dstats, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Size-class schedule (autotuner)                                           */
+/* ------------------------------------------------------------------------ */
+
+/* The batch path picks a workgroup width per size class: n <= t64 uses one
+ * wavefront (64 lanes), n <= t256 uses 256 lanes, larger n uses 1024 lanes.
+ * ot_schedule_get returns the thresholds in force; ot_schedule_set overrides
+ * them (0 restores the default); ot_schedule_tune times synthetic instances
+ * on the device and sets them (returns OT_OK or an error). */
+int ot_schedule_get(int32_t *t64, int32_t *t256);
+int ot_schedule_set(int32_t t64, int32_t t256);
+int ot_schedule_tune(int32_t reps);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* OTKM_H */

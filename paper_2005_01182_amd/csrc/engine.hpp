@@ -1,0 +1,768 @@
+// engine.hpp -- batched Kuhn-Munkres on one workgroup (gfx950).
+//
+// Method: "Batched KM" (Section 2.3.1 of the paper).  Alternating trees grow
+// from every free row at once inside the tight-edge subgraph; every
+// vertex-disjoint augmenting path found is applied (one per tree that reached
+// a free column); when no tree can grow and none has reached a free column,
+// the duals move across the cut (reached rows up, reached columns down) by
+// the smallest slack, exactly as in KM.  The loop stops when every row is
+// matched.
+//
+// Organisation on the device (one workgroup = one instance):
+//   * Column j is owned by thread j % BLOCK (CPT columns per thread, strided
+//     so that a cost-row read is one coalesced sweep across the workgroup).
+//     The owner keeps in registers: its dual v_j, the level at which the
+//     column was reached, and the column's two smallest reduced costs from
+//     distinct trees ("top-2 keys", each packed as value << 24 | row).
+//   * Row state lives in LDS: match arrays, the tree a row belongs to, the
+//     forest row list, and h_i = u_i - D_i (the row dual relative to the
+//     level D_i at which the row joined; non-forest rows store u_i).  Dual
+//     changes across the cut are therefore lazy: raising every reached row by
+//     delta is just raising the running level D (Dijkstra-style potentials),
+//     and a key stores reduced cost + D, which stays valid while the forest
+//     grows.
+//   * When a tree augments, its rows and columns leave the forest and their
+//     duals are materialised.  A column whose best key came from a dead tree
+//     falls back to its second key (best from another tree); keys that are
+//     still unknown are kept as lower bounds ("stale") and recomputed
+//     ("gathered") only when they could be the next minimum.  This avoids
+//     re-reading the whole forest after every augmentation.
+//   * Workgroup minima use DPP row rotations inside a wavefront and one LDS
+//     atomic per wavefront; the level loop needs two barriers per level.
+//
+// Integer ranges (int32 costs with max - min = R <= 2^31 - 1): u only rises,
+// v only falls, free columns keep v >= 0, so u_i <= max C and v_j >= -R; a
+// reduced cost is in [0, 2R] and the running level D is at most R.  A key
+// value (reduced cost + D) is therefore below 3 * 2^31 < 2^40 and fits with a
+// 24-bit row index in 64 bits.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "otkm.h"
+
+namespace otkm {
+
+constexpr int kRowBits = 24;
+constexpr uint64_t kRowMask = (1ull << kRowBits) - 1;
+constexpr uint64_t kInf = ~0ull;
+constexpr int kNoEnd = 0x7fffffff;
+
+// int control words in LDS
+enum Ctl { CNT0 = 0, CNT1 = 1, NAUG = 2, GCNT = 3, ERR = 4, FCNT = 5, ERRA0 = 6, ERRA1 = 7, ERRB0 = 8, ERRB1 = 9,
+           NCTL = 12 };
+
+__host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~size_t(15); }
+__host__ __device__ inline int gather_cap(int n) { return n / 16 < 32 ? 32 : n / 16; }
+
+struct LdsLayout {
+  size_t hrow, mrow, mcol, rtree, fst, fl0, fl1, alive, gcol, gv, gk1, gk2, gt1, gt2, red, ctl, total;
+};
+
+// Byte offsets of every LDS array for an instance of size n (host and device).
+__host__ __device__ inline LdsLayout lds_layout(int n) {
+  LdsLayout L;
+  const size_t N = (size_t)n, G = (size_t)gather_cap(n);
+  size_t o = 0;
+  L.hrow = o;  o = align16(o + 8 * N);
+  L.mrow = o;  o = align16(o + 4 * N);
+  L.mcol = o;  o = align16(o + 4 * N);
+  L.rtree = o; o = align16(o + 4 * N);
+  L.fst = o;   o = align16(o + 4 * N);
+  L.fl0 = o;   o = align16(o + 4 * N);
+  L.fl1 = o;   o = align16(o + 4 * N);
+  L.alive = o; o = align16(o + N);
+  L.gcol = o;  o = align16(o + 4 * G);
+  L.gv = o;    o = align16(o + 8 * G);
+  L.gk1 = o;   o = align16(o + 8 * G);
+  L.gk2 = o;   o = align16(o + 8 * G);
+  L.gt1 = o;   o = align16(o + 4 * G);
+  L.gt2 = o;   o = align16(o + 4 * G);
+  L.red = o;   o = align16(o + 8 * 128);
+  L.ctl = o;   o = align16(o + 4 * NCTL);
+  L.total = o;
+  return L;
+}
+
+// Global scratch per workgroup: parent row of each reached column, list of
+// trees that augment this step, smallest free column reached per tree.
+__host__ __device__ inline size_t ws_ints(int n) { return 3 * (size_t)n; }
+
+struct Problem {
+  const int32_t *C;   // n x n, row stride ld
+  int n, ld;
+  int max_paths;      // 0 = all free rows
+  int flags;          // OT_FLAG_* bits
+  int32_t *plan;      // [n]
+  int64_t *cost;      // [1]
+  int64_t *u, *v;     // [n] or null
+  ot_stats *stats;    // [1] or null
+  int32_t *ws;        // [ws_ints(n)]
+};
+
+__device__ __forceinline__ uint64_t pack(int64_t val, int row) {
+  return ((uint64_t)val << kRowBits) | (uint32_t)row;
+}
+__device__ __forceinline__ int64_t kval(uint64_t k) { return (int64_t)(k >> kRowBits); }
+__device__ __forceinline__ int krow(uint64_t k) { return (int)(k & kRowMask); }
+
+__device__ __forceinline__ uint64_t umin64(uint64_t a, uint64_t b) { return b < a ? b : a; }
+
+template <int CTRL>
+__device__ __forceinline__ uint64_t dpp64(uint64_t x) {
+  const int lo = __builtin_amdgcn_mov_dpp((int)(uint32_t)x, CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(uint32_t)(x >> 32), CTRL, 0xf, 0xf, false);
+  return ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
+}
+__device__ __forceinline__ uint64_t readlane64(uint64_t x, int lane) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, lane);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(x >> 32), lane);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// Minimum over a full wavefront (all 64 lanes active): rotations inside each
+// 16-lane row, then the four row results through scalar reads.  The result is
+// wave-uniform.
+__device__ __forceinline__ uint64_t wave_min_u64(uint64_t x) {
+  x = umin64(x, dpp64<0x121>(x));  // row_ror:1
+  x = umin64(x, dpp64<0x122>(x));  // row_ror:2
+  x = umin64(x, dpp64<0x124>(x));  // row_ror:4
+  x = umin64(x, dpp64<0x128>(x));  // row_ror:8
+  return umin64(umin64(readlane64(x, 0), readlane64(x, 16)), umin64(readlane64(x, 32), readlane64(x, 48)));
+}
+__device__ __forceinline__ int wave_min_i32(int x) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) x = min(x, __shfl_xor(x, off, 64));
+  return x;
+}
+__device__ __forceinline__ int wave_max_i32(int x) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) x = max(x, __shfl_xor(x, off, 64));
+  return x;
+}
+__device__ __forceinline__ int64_t wave_sum_i64(int64_t x) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+  return x;
+}
+
+// Insert candidate c (from a row of tree t >= 0) into a column's top-2:
+// a1 = best key overall (tree ta1), a2 = best key among trees != ta1.
+__device__ __forceinline__ void top2_push(uint64_t &a1, int &ta1, uint64_t &a2, int &ta2, uint64_t c, int t) {
+  // same tree as the best: only the best can improve; another tree: c may
+  // become the best (the old best moves to second) or the second.
+  const bool same = t == ta1, lt1 = c < a1, lt2 = c < a2;
+  const uint64_t n2 = same ? a2 : (lt1 ? a1 : (lt2 ? c : a2));
+  const int m2 = same ? ta2 : (lt1 ? ta1 : (lt2 ? t : ta2));
+  ta1 = (!same && lt1) ? t : ta1;
+  a1 = lt1 ? c : a1;
+  a2 = n2;
+  ta2 = m2;
+}
+
+// Merge two exact top-2 summaries (symmetric, so both butterfly partners agree).
+__device__ __forceinline__ void top2_merge(uint64_t &a1, int &ta1, uint64_t &a2, int &ta2, uint64_t b1, int tb1,
+                                           uint64_t b2, int tb2) {
+  if (b1 < a1) {
+    uint64_t x1 = a1, x2 = a2; int y1 = ta1, y2 = ta2;
+    a1 = b1; ta1 = tb1; a2 = b2; ta2 = tb2;
+    b1 = x1; tb1 = y1; b2 = x2; tb2 = y2;
+  }
+  uint64_t c = (tb1 != ta1) ? b1 : b2;
+  int tc = (tb1 != ta1) ? tb1 : tb2;
+  if (c < a2) { a2 = c; ta2 = tc; }
+}
+
+__device__ __forceinline__ int64_t now_ticks() { return (int64_t)wall_clock64(); }
+
+template <int BLOCK, int CPT>
+struct Engine {
+  static constexpr int NW = BLOCK / 64;
+
+  // problem
+  const int32_t *__restrict__ C;
+  int n, ld;
+  // LDS
+  int64_t *hrow;
+  int32_t *mrow, *mcol, *rtree, *fst, *fl0, *fl1, *gcol, *gt1, *gt2, *ctl;
+  uint8_t *alive;
+  int64_t *gv;
+  uint64_t *gk1, *gk2, *red;
+  int gcap;
+  // global scratch
+  int32_t *par, *auglist, *bend;
+  // per-column registers
+  uint64_t k1[CPT], k2[CPT];
+  int t1[CPT], t2[CPT], ctree[CPT];
+  // v_j lies in [-R, R] and the level at which a column is reached in [0, R]
+  // (R = max C - min C < 2^31), so both fit 32 bits.
+  int32_t vj[CPT], dcol[CPT];
+  uint32_t lim32[CPT];  // value of k2 saturated to 32 bits: a candidate above it cannot enter the top-2
+  bool narrow;          // cost range below 2^30
+  uint32_t vis;   // bit k: column k has been reached (is in a tree)
+  uint32_t stl;   // bit k: k1 is only a lower bound (its tree is gone)
+  int tid, lane, wid;
+  int err_local;  // this thread's first error (0 = none); reduced at every level
+
+  __device__ __forceinline__ int col(int k) const { return tid + k * BLOCK; }
+  // Always-valid column for loads: loads are issued unconditionally (a guarded
+  // load becomes a branch plus a full wait for memory), values of columns past
+  // n are ignored afterwards.
+  __device__ __forceinline__ int lcol(int k) const { return col(k) < n ? col(k) : n - 1; }
+  __device__ __forceinline__ bool stale(int k) const { return (stl >> k) & 1u; }
+  __device__ __forceinline__ void fail(int code) { if (err_local == 0) err_local = code; }
+
+  // exact iff the best key's tree is still alive (or there is no candidate at all)
+  __device__ __forceinline__ void recompute_stale(int k) {
+    const bool ok = k1[k] == kInf || (t1[k] >= 0 && alive[t1[k]]);
+    if (ok) stl &= ~(1u << k); else stl |= 1u << k;
+  }
+
+  __device__ __forceinline__ void sync_lim(int k) {
+    const int64_t v2 = kval(k2[k]);
+    lim32[k] = v2 > 0xffffffffll ? 0xffffffffu : (uint32_t)v2;
+  }
+
+  __device__ __forceinline__ void push(int k, uint64_t c, int t) {
+    top2_push(k1[k], t1[k], k2[k], t2[k], c, t);
+    if (t1[k] == t) stl &= ~(1u << k);  // best key now from a live tree
+    sync_lim(k);
+  }
+
+  // Offer reduced-cost value `val` from row r of tree t to owned column k.
+  // Nearly every candidate is rejected by the single compare against lim2.
+  __device__ __forceinline__ void offer(int k, int64_t val, int r, int t) {
+    if (val > kval(k2[k])) return;
+    if (val < 0) { fail(OT_EINTERNAL); val = 0; }
+    push(k, pack(val, r), t);
+  }
+
+  // Fold cost rows list[0..cnt) (forest rows; rows no longer in the forest
+  // are skipped) into every owned column's top-2 keys.  Rows go in chunks of U
+  // whose loads are all issued before any is used, so a short frontier costs
+  // one memory latency.  Each chunk first tests every (row, column) candidate
+  // against the column's second key without branching; only candidates that
+  // can enter a top-2 take the exact 64-bit path.  With NARROW (cost range
+  // below 2^30) every key value is below 2^32, so the test runs in 32-bit
+  // modular arithmetic, which is exact there.  Returns rows used.
+  static constexpr int U = CPT >= 8 ? 2 : 16 / CPT > 8 ? 8 : 16 / CPT;
+  template <bool NARROW>
+  __device__ __forceinline__ int sweep_t(const int32_t *list, int cnt) {
+    int used = 0;
+    for (int f = 0; f < cnt; f += U) {
+      int r[U], t[U];
+      int64_t h[U];
+      int32_t c[U][CPT];
+#pragma unroll
+      for (int q = 0; q < U; ++q) {
+        r[q] = f + q < cnt ? list[f + q] : 0;
+        if ((unsigned)r[q] >= (unsigned)n) { fail(OT_EINTERNAL); r[q] = 0; }
+        t[q] = f + q < cnt ? rtree[r[q]] : -1;
+        h[q] = hrow[r[q]];
+      }
+#pragma unroll
+      for (int q = 0; q < U; ++q) {
+        const int32_t *row = C + (size_t)r[q] * (size_t)ld;
+#pragma unroll
+        for (int k = 0; k < CPT; ++k) c[q][k] = row[lcol(k)];
+      }
+      uint32_t pass = 0;
+#pragma unroll
+      for (int q = 0; q < U; ++q) {
+        used += t[q] >= 0;
+#pragma unroll
+        for (int k = 0; k < CPT; ++k) {
+          bool p;
+          if (NARROW) {
+            const uint32_t v = (uint32_t)c[q][k] - ((uint32_t)h[q] + (uint32_t)vj[k]);
+            p = v <= lim32[k];
+          } else {
+            p = (int64_t)c[q][k] - h[q] - vj[k] <= kval(k2[k]);
+          }
+          pass |= (p && t[q] >= 0) ? (1u << (q * CPT + k)) : 0u;
+        }
+      }
+      // Slots nobody in the wavefront needs are skipped with one scalar branch.
+      if (__builtin_amdgcn_ballot_w64(pass != 0) != 0) {
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+#pragma unroll
+          for (int k = 0; k < CPT; ++k) {
+            const bool p = ((pass >> (q * CPT + k)) & 1u) && col(k) < n;
+            if (__builtin_amdgcn_ballot_w64(p) == 0) continue;
+            if (p) offer(k, (int64_t)c[q][k] - h[q] - vj[k], r[q], t[q]);
+          }
+        }
+      }
+    }
+    return used;
+  }
+  __device__ __forceinline__ int sweep(const int32_t *list, int cnt) {
+    return narrow ? sweep_t<true>(list, cnt) : sweep_t<false>(list, cnt);
+  }
+
+  // Workgroup minimum of valid / stale keys over unreached owned columns plus
+  // the error code, into slot set `s` (u64 pair at red[2s], int at ctl[es]).
+  // The slots must hold (kInf, kInf, 0) beforehand; the caller issues the barrier.
+  __device__ __forceinline__ void reduce_min(int s, int es) {
+    uint64_t a = kInf, b = kInf;
+#pragma unroll
+    for (int k = 0; k < CPT; ++k) {
+      if (col(k) >= n || ((vis >> k) & 1u)) continue;
+      if (stale(k)) b = umin64(b, k1[k]);
+      else a = umin64(a, k1[k]);
+    }
+    a = wave_min_u64(a);
+    b = wave_min_u64(b);
+    if (lane == 0) {
+      if (a != kInf) atomicMin((unsigned long long *)&red[2 * s], (unsigned long long)a);
+      if (b != kInf) atomicMin((unsigned long long *)&red[2 * s + 1], (unsigned long long)b);
+    }
+    if (err_local != 0) atomicMin(&ctl[es], err_local);  // rare: only lanes that saw an error
+  }
+  __device__ __forceinline__ void reset_slots(int s, int es) {
+    red[2 * s] = kInf;
+    red[2 * s + 1] = kInf;
+    ctl[es] = 0;
+  }
+
+  // Recompute stale keys that could be the next minimum.  Returns cost
+  // entries read; sets `resweep` when a full re-sweep of the forest was used.
+  __device__ __forceinline__ int64_t refresh_stale(uint64_t mv, bool &resweep, int &swept) {
+    const int64_t lim = (mv == kInf) ? INT64_MAX : kval(mv);
+    uint32_t req = 0;
+    int slot[CPT];
+#pragma unroll
+    for (int k = 0; k < CPT; ++k) {
+      slot[k] = -1;
+      if (col(k) >= n || ((vis >> k) & 1u) || !stale(k)) continue;
+      if (kval(k1[k]) > lim) continue;
+      int s = atomicAdd(&ctl[GCNT], 1);
+      slot[k] = s;
+      req |= 1u << k;
+      if (s < gcap) { gcol[s] = col(k); gv[s] = vj[k]; }
+    }
+    __syncthreads();
+    const int g = ctl[GCNT];
+    const int nf = ctl[FCNT];
+    resweep = false;
+    swept = 0;
+    if (g > gcap) {
+      // too many: one coalesced re-sweep of every forest row fixes all keys
+#pragma unroll
+      for (int k = 0; k < CPT; ++k) { k1[k] = kInf; k2[k] = kInf; t1[k] = -1; t2[k] = -1; sync_lim(k); }
+      stl = 0;
+      swept = sweep(fst, nf);
+      resweep = true;
+      return 0;
+    }
+    // Each stale column gets wpc wavefronts that split the forest rows; partial
+    // top-2 summaries meet in LDS and one thread per column merges them.
+    const int wpc = g >= NW ? 1 : NW / g;
+    const int per_round = NW / wpc;
+    uint64_t *pk1 = red + 64, *pk2 = red + 64 + NW;
+    int32_t *pt = (int32_t *)(red + 64 + 2 * NW);
+    for (int base = 0; base < g; base += per_round) {
+      const int s = base + wid / wpc;
+      const int slice = wid % wpc;
+      if (s < g) {
+        const int j = gcol[s];
+        const int64_t v = gv[s];
+        uint64_t a1 = kInf, a2 = kInf;
+        int ta1 = -1, ta2 = -1;
+        const int stride = 64 * wpc;
+        for (int f0 = slice * 64 + lane; f0 < nf; f0 += 4 * stride) {
+          int i[4], t[4];
+          int64_t h[4];
+          int32_t c[4];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int f = f0 + q * stride;
+            i[q] = f < nf ? fst[f] : 0;
+            if ((unsigned)i[q] >= (unsigned)n) { fail(OT_EINTERNAL); i[q] = 0; }
+            t[q] = f < nf ? rtree[i[q]] : -1;
+            h[q] = hrow[i[q]];
+          }
+#pragma unroll
+          for (int q = 0; q < 4; ++q) c[q] = C[(size_t)i[q] * (size_t)ld + j];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            if (t[q] < 0) continue;
+            int64_t val = (int64_t)c[q] - h[q] - v;
+            if (val < 0) { fail(OT_EINTERNAL); val = 0; }
+            top2_push(a1, ta1, a2, ta2, pack(val, i[q]), t[q]);
+          }
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+          uint64_t b1 = __shfl_xor(a1, off, 64), b2 = __shfl_xor(a2, off, 64);
+          int tb1 = __shfl_xor(ta1, off, 64), tb2 = __shfl_xor(ta2, off, 64);
+          top2_merge(a1, ta1, a2, ta2, b1, tb1, b2, tb2);
+        }
+        if (lane == 0) {
+          if (wpc == 1) { gk1[s] = a1; gt1[s] = ta1; gk2[s] = a2; gt2[s] = ta2; }
+          else { pk1[wid] = a1; pk2[wid] = a2; pt[2 * wid] = ta1; pt[2 * wid + 1] = ta2; }
+        }
+      }
+      __syncthreads();
+      if (wpc > 1 && tid < per_round && base + tid < g) {
+        const int w0 = tid * wpc;
+        uint64_t a1 = pk1[w0], a2 = pk2[w0];
+        int ta1 = pt[2 * w0], ta2 = pt[2 * w0 + 1];
+        for (int w = w0 + 1; w < w0 + wpc; ++w) top2_merge(a1, ta1, a2, ta2, pk1[w], pt[2 * w], pk2[w], pt[2 * w + 1]);
+        const int s = base + tid;
+        gk1[s] = a1; gt1[s] = ta1; gk2[s] = a2; gt2[s] = ta2;
+      }
+      if (wpc > 1) __syncthreads();
+    }
+#pragma unroll
+    for (int k = 0; k < CPT; ++k) {
+      if (!((req >> k) & 1u)) continue;
+      const int s = slot[k];
+      k1[k] = gk1[s]; t1[k] = gt1[s]; k2[k] = gk2[s]; t2[k] = gt2[s];
+      stl &= ~(1u << k);
+      sync_lim(k);
+    }
+    return (int64_t)g * (int64_t)nf;
+  }
+
+  __device__ __forceinline__ void run(const Problem &P, char *smem) {
+    C = P.C; n = P.n; ld = P.ld;
+    tid = threadIdx.x; lane = tid & 63; wid = tid >> 6;
+    err_local = 0;
+    const LdsLayout L = lds_layout(n);
+    hrow = (int64_t *)(smem + L.hrow);
+    mrow = (int32_t *)(smem + L.mrow);
+    mcol = (int32_t *)(smem + L.mcol);
+    rtree = (int32_t *)(smem + L.rtree);
+    fst = (int32_t *)(smem + L.fst);
+    fl0 = (int32_t *)(smem + L.fl0);
+    fl1 = (int32_t *)(smem + L.fl1);
+    alive = (uint8_t *)(smem + L.alive);
+    gcol = (int32_t *)(smem + L.gcol);
+    gv = (int64_t *)(smem + L.gv);
+    gk1 = (uint64_t *)(smem + L.gk1);
+    gk2 = (uint64_t *)(smem + L.gk2);
+    gt1 = (int32_t *)(smem + L.gt1);
+    gt2 = (int32_t *)(smem + L.gt2);
+    red = (uint64_t *)(smem + L.red);
+    ctl = (int32_t *)(smem + L.ctl);
+    gcap = gather_cap(n);
+    par = P.ws;
+    auglist = P.ws + n;
+    bend = P.ws + 2 * (size_t)n;
+
+    const int K = (P.max_paths <= 0 || P.max_paths > n) ? n : P.max_paths;
+    int64_t st_levels = 0, st_dual = 0, st_aug = 0, st_paths = 0, st_rows = 0, st_gath = 0, st_resw = 0;
+    int64_t st_refresh = 0, st_rcols = 0, tm_refresh = 0;
+    int64_t tm_sweep = 0, tm_select = 0, tm_settle = 0, tm_aug = 0;
+
+    if (tid < NCTL) ctl[tid] = 0;
+    if (tid < 8) red[tid] = kInf;
+
+    // ---- initialisation: u_i = min_j C_ij (one wavefront per row) and the cost range
+    int gmin = 0x7fffffff, gmax = (int)0x80000000;
+    for (int i = wid; i < n; i += NW) {
+      const int32_t *row = C + (size_t)i * (size_t)ld;
+      int mn = 0x7fffffff, mx = (int)0x80000000;
+      for (int j0 = 0; j0 < n; j0 += 64 * 16) {
+        int c[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+          const int j = j0 + lane + 64 * q;
+          c[q] = row[j < n ? j : n - 1];  // clamped: duplicates do not change min / max
+        }
+#pragma unroll
+        for (int q = 0; q < 16; ++q) { mn = min(mn, c[q]); mx = max(mx, c[q]); }
+      }
+      mn = wave_min_i32(mn);
+      mx = wave_max_i32(mx);
+      if (lane == 0) hrow[i] = mn;
+      gmin = min(gmin, mn);
+      gmax = max(gmax, mx);
+    }
+    for (int i = tid; i < n; i += BLOCK) {
+      mrow[i] = -1; mcol[i] = -1; bend[i] = kNoEnd;
+      const bool root = i < K;
+      alive[i] = root ? 1 : 0;
+      rtree[i] = root ? i : -1;
+      if (root) fst[i] = i;
+    }
+    gmin = wave_min_i32(gmin);
+    gmax = wave_max_i32(gmax);
+    int *ired = (int *)(red + 16);
+    if (lane == 0) { ired[wid] = gmin; ired[NW + wid] = gmax; }
+    __syncthreads();
+    gmin = 0x7fffffff; gmax = (int)0x80000000;
+    for (int w = 0; w < NW; ++w) { gmin = min(gmin, ired[w]); gmax = max(gmax, ired[NW + w]); }
+    narrow = (int64_t)gmax - (int64_t)gmin < (1ll << 30);
+    if ((int64_t)gmax - (int64_t)gmin > 0x7fffffffll) {
+      if (P.stats && tid == 0) { ot_stats s = {}; s.status = OT_ERANGE; *P.stats = s; }
+      return;
+    }
+
+    // ---- v_j = min_i (C_ij - u_i); with every row a root, keep the two best rows as keys
+    vis = 0;
+    stl = 0;
+#pragma unroll
+    for (int k = 0; k < CPT; ++k) {
+      k1[k] = kInf; k2[k] = kInf; t1[k] = -1; t2[k] = -1; vj[k] = 0; dcol[k] = 0; ctree[k] = -1;
+      lim32[k] = 0xffffffffu;
+    }
+    {
+      uint64_t b1[CPT], b2[CPT];
+#pragma unroll
+      for (int k = 0; k < CPT; ++k) { b1[k] = kInf; b2[k] = kInf; }
+      int i = 0;
+      for (; i + 4 <= n; i += 4) {
+        int32_t c[4][CPT];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int32_t *row = C + (size_t)(i + q) * (size_t)ld;
+#pragma unroll
+          for (int k = 0; k < CPT; ++k) c[q][k] = row[lcol(k)];
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int64_t h = hrow[i + q];
+#pragma unroll
+          for (int k = 0; k < CPT; ++k) {
+            uint64_t key = pack((int64_t)c[q][k] - h, i + q);
+            if (key < b1[k]) { b2[k] = b1[k]; b1[k] = key; }
+            else if (key < b2[k]) b2[k] = key;
+          }
+        }
+      }
+      for (; i < n; ++i) {
+        const int32_t *row = C + (size_t)i * (size_t)ld;
+        const int64_t h = hrow[i];
+        int32_t c[CPT];
+#pragma unroll
+        for (int k = 0; k < CPT; ++k) c[k] = row[lcol(k)];
+#pragma unroll
+        for (int k = 0; k < CPT; ++k) {
+          if (col(k) >= n) continue;
+          uint64_t key = pack((int64_t)c[k] - h, i);
+          if (key < b1[k]) { b2[k] = b1[k]; b1[k] = key; }
+          else if (key < b2[k]) b2[k] = key;
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < CPT; ++k) {
+        if (col(k) >= n) continue;
+        vj[k] = (int32_t)kval(b1[k]);
+        if (K == n) {
+          k1[k] = pack(0, krow(b1[k]));
+          t1[k] = krow(b1[k]);
+          if (b2[k] != kInf) { k2[k] = pack(kval(b2[k]) - vj[k], krow(b2[k])); t2[k] = krow(b2[k]); }
+          sync_lim(k);
+        }
+      }
+    }
+    st_rows = 2 * (int64_t)n;
+    int cur = 0;
+    if (tid == 0) {
+      ctl[CNT0] = 0; ctl[CNT1] = 0; ctl[FCNT] = K;
+    }
+    if (K < n) {
+      for (int i = tid; i < K; i += BLOCK) fl0[i] = i;
+      if (tid == 0) ctl[CNT0] = K;
+    }
+    __syncthreads();
+
+    int nfree = n, nalive = K, cursor = K;
+    int64_t D = 0;
+    const int64_t watchdog = (int64_t)(n + 2) * (int64_t)(n + 2) + 64;
+    const bool timers = (P.flags & OT_FLAG_PHASE_TIMERS) != 0;
+    int64_t tprev = timers ? now_ticks() : 0;
+
+    while (nfree > 0) {
+      const int ps = cur;  // slot parity of this level
+      // (1) fold the rows that joined last step into the keys
+      const int nf = ctl[cur == 0 ? CNT0 : CNT1];
+      st_rows += sweep(cur == 0 ? fl0 : fl1, nf);
+      const int64_t t0 = timers ? now_ticks() : 0;
+      tm_sweep += t0 - tprev;
+      // (2) smallest key over unreached columns
+      reduce_min(ps, ERRA0 + ps);
+      if (tid == 0) {
+        ctl[cur == 0 ? CNT1 : CNT0] = 0; ctl[NAUG] = 0; ctl[GCNT] = 0;
+        reset_slots(ps ^ 1, ERRA0 + (ps ^ 1));
+        reset_slots(2 + (ps ^ 1), ERRB0 + (ps ^ 1));
+      }
+      __syncthreads();
+      uint64_t mv = red[2 * ps], ms = red[2 * ps + 1];
+      int berr = ctl[ERRA0 + ps];
+      if (berr == 0 && ms != kInf && (mv == kInf || kval(ms) <= kval(mv))) {
+        bool resweep;
+        int swept;
+        const int64_t tr0 = timers ? now_ticks() : 0;
+        st_gath += refresh_stale(mv, resweep, swept);
+        ++st_refresh;
+        st_rcols += ctl[GCNT];
+        if (timers) tm_refresh += now_ticks() - tr0;
+        if (resweep) { ++st_resw; st_rows += swept; }
+        reduce_min(2 + ps, ERRB0 + ps);
+        __syncthreads();
+        mv = red[2 * (2 + ps)];
+        berr = ctl[ERRB0 + ps];
+      }
+      if (berr != 0) break;
+      if (mv == kInf) { fail(OT_EINTERNAL); break; }
+      const int64_t level = kval(mv);
+      if (level > D) { D = level; ++st_dual; }
+      if (++st_levels > watchdog) { fail(OT_EINTERNAL); break; }
+      const int64_t t1_ = timers ? now_ticks() : 0;
+      tm_select += t1_ - t0;
+
+      // (3) settle every unreached column at the current level
+      int32_t *nxt = cur == 0 ? fl1 : fl0;
+      int *nxtcnt = &ctl[cur == 0 ? CNT1 : CNT0];
+#pragma unroll
+      for (int k = 0; k < CPT; ++k) {
+        const int j = col(k);
+        if (j >= n || ((vis >> k) & 1u) || k1[k] == kInf || stale(k) || kval(k1[k]) != D) continue;
+        const int p = krow(k1[k]);
+        const int tr = t1[k];
+        vis |= 1u << k;
+        dcol[k] = (int32_t)D;
+        ctree[k] = tr;
+        par[j] = p;
+        const int mc = mcol[j];
+        if (mc < 0) {
+          if (atomicMin(&bend[tr], j) == kNoEnd) {
+            const int s = atomicAdd(&ctl[NAUG], 1);
+            auglist[s] = tr;
+          }
+        } else {
+          // the matched row joins the tree (undone below if the tree augments now)
+          rtree[mc] = tr;
+          hrow[mc] -= D;
+          nxt[atomicAdd(nxtcnt, 1)] = mc;
+          fst[atomicAdd(&ctl[FCNT], 1)] = mc;
+        }
+      }
+      __syncthreads();
+      const int naug = ctl[NAUG];
+      const int64_t t2_ = timers ? now_ticks() : 0;
+      tm_settle += t2_ - t1_;
+      if (naug > 0) {
+        // (4) flip one path per tree that reached a free column (trees are disjoint)
+        for (int a = tid; a < naug; a += BLOCK) {
+          const int tr = auglist[a];
+          int j = bend[tr];
+          bend[tr] = kNoEnd;
+          for (int steps = 0;; ++steps) {
+            if (steps > n || (unsigned)j >= (unsigned)n) { fail(OT_EINTERNAL); break; }
+            const int p = par[j];
+            if ((unsigned)p >= (unsigned)n) { fail(OT_EINTERNAL); break; }
+            const int before = mrow[p];
+            mrow[p] = j;
+            mcol[j] = p;
+            if (p == tr) break;
+            j = before;
+          }
+          alive[tr] = 0;
+        }
+        ++st_aug;
+        st_paths += naug;
+        nfree -= naug;
+        nalive -= naug;
+        __syncthreads();
+        // (5) rows and columns of finished trees leave the forest with their duals materialised
+        for (int i = tid; i < n; i += BLOCK) {
+          const int t = rtree[i];
+          if (t >= 0 && !alive[t]) { hrow[i] += D; rtree[i] = -1; }
+        }
+#pragma unroll
+        for (int k = 0; k < CPT; ++k) {
+          if (col(k) >= n) continue;
+          if (((vis >> k) & 1u) && !alive[ctree[k]]) {
+            const int64_t d = D - dcol[k];
+            vj[k] -= (int32_t)d;
+            const uint64_t sh = (uint64_t)d << kRowBits;
+            if (k1[k] != kInf) k1[k] += sh;
+            if (k2[k] != kInf) k2[k] += sh;
+            vis &= ~(1u << k);
+            ctree[k] = -1;
+          }
+          if (t1[k] >= 0 && !alive[t1[k]]) {
+            // best key came from a finished tree: fall back to the best other tree;
+            // what lies behind it is unknown, so keep it only as a lower bound
+            k1[k] = k2[k]; t1[k] = t2[k]; t2[k] = -1;
+          } else if (t2[k] >= 0 && !alive[t2[k]]) {
+            t2[k] = -1;
+          }
+          if (nalive == 0) { k1[k] = kInf; k2[k] = kInf; t1[k] = -1; t2[k] = -1; }
+          recompute_stale(k);
+          sync_lim(k);
+        }
+        if (tid == 0) ctl[FCNT] = 0;
+        __syncthreads();
+        // (6) rebuild the forest list; with a tree cap, start new trees from the next free rows
+        for (int i = tid; i < n; i += BLOCK)
+          if (rtree[i] >= 0) fst[atomicAdd(&ctl[FCNT], 1)] = i;
+        const int need = min(K - nalive, n - cursor);
+        if (need > 0) {
+          __syncthreads();  // the scan above must not see the new roots
+          for (int q = tid; q < need; q += BLOCK) {
+            const int r = cursor + q;
+            rtree[r] = r;
+            alive[r] = 1;
+            hrow[r] -= D;
+            nxt[atomicAdd(nxtcnt, 1)] = r;
+            fst[atomicAdd(&ctl[FCNT], 1)] = r;
+          }
+          cursor += need;
+          nalive += need;
+        }
+        __syncthreads();
+        tprev = timers ? now_ticks() : 0;
+        tm_aug += tprev - t2_;
+      } else {
+        tprev = t2_;
+      }
+      cur ^= 1;
+    }
+
+    __syncthreads();
+    if (err_local != 0) atomicMin(&ctl[ERR], err_local);
+    __syncthreads();
+    const int err = ctl[ERR];
+    if (err == 0) {
+      int64_t part = 0;
+      for (int i = tid; i < n; i += BLOCK) {
+        const int j = mrow[i];
+        P.plan[i] = j;
+        if (P.u) P.u[i] = hrow[i];
+        part += (j >= 0 && j < n) ? (int64_t)C[(size_t)i * (size_t)ld + j] : 0;
+      }
+      if (P.v) {
+#pragma unroll
+        for (int k = 0; k < CPT; ++k)
+          if (col(k) < n) P.v[col(k)] = vj[k];
+      }
+      part = wave_sum_i64(part);
+      int64_t *sred = (int64_t *)(red + 16);
+      if (lane == 0) sred[wid] = part;
+      __syncthreads();
+      if (tid == 0) {
+        int64_t tot = 0;
+        for (int w = 0; w < NW; ++w) tot += sred[w];
+        *P.cost = tot;
+      }
+    }
+    if (P.stats && tid == 0) {
+      ot_stats s;
+      s.levels = st_levels; s.dual_adjusts = st_dual; s.aug_events = st_aug; s.paths = st_paths;
+      s.rows_swept = st_rows; s.gathers = st_gath; s.resweeps = st_resw; s.status = err;
+      s.t_sweep_ns = 10 * tm_sweep; s.t_select_ns = 10 * tm_select;  // wall clock ticks are 10 ns
+      s.t_settle_ns = 10 * tm_settle; s.t_augment_ns = 10 * tm_aug;
+      s.refreshes = st_refresh; s.refresh_cols = st_rcols; s.t_refresh_ns = 10 * tm_refresh;
+      *P.stats = s;
+    }
+  }
+};
+
+}  // namespace otkm

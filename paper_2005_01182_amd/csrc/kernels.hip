@@ -1,0 +1,329 @@
+// kernels.hip -- gfx950 kernels around the batched-KM engine and their launchers.
+//
+//   k_assign_one      one instance, one workgroup (the whole solve on chip)
+//   k_assign_batch    persistent workgroups pull instances from a device queue
+//   k_fill_i32        queue/flag reset (a kernel, so launches stay graph-capturable)
+//   k_tr_prep         transport: check masses, unit -> bin maps (Eq. (1), r/c integer)
+//   k_tr_expand       transport: S x S unit cost matrix
+//   k_tr_aggregate    transport: unit plan -> bin plan X
+//   k_tr_duals_*      transport: bin duals from unit duals (+ zero-mass bins)
+//   k_grid_cost       serving: integer-point Euclidean costs, exactly rounded
+#include <hip/hip_runtime.h>
+
+#include "engine.hpp"
+#include "launch.hpp"
+
+namespace otkm {
+
+// ---------------------------------------------------------------------------
+// single instance
+// ---------------------------------------------------------------------------
+template <int BLOCK, int CPT>
+__global__ __launch_bounds__(BLOCK) void k_assign_one(Problem P, const int32_t *gate) {
+  extern __shared__ __align__(16) char smem[];
+  if (gate && *gate != 0) return;  // an earlier stage of this pipeline already failed
+  Engine<BLOCK, CPT> E;
+  E.run(P, smem);
+}
+
+// ---------------------------------------------------------------------------
+// persistent batch: each workgroup pops instance indices until the queue is empty
+// ---------------------------------------------------------------------------
+template <int BLOCK, int CPT>
+__global__ __launch_bounds__(BLOCK) void k_assign_batch(BatchArgs A) {
+  extern __shared__ __align__(16) char smem[];
+  __shared__ int s_idx;
+  int32_t *ws = A.ws + (size_t)blockIdx.x * ws_ints(A.max_n);
+  for (;;) {
+    if (threadIdx.x == 0) s_idx = atomicAdd(A.head, 1);
+    __syncthreads();
+    const int idx = s_idx;
+    __syncthreads();
+    if (idx >= A.nq) break;  // every workgroup reaches this exit once the queue drains
+    const int k = A.order ? A.order[idx] : idx;
+    if ((unsigned)k >= (unsigned)A.count) continue;
+    const int n = A.n[k];
+    if (n < 1 || n > A.max_n || n > BLOCK * CPT) {
+      if (A.stats && threadIdx.x == 0) { ot_stats s = {}; s.status = OT_EINVAL; A.stats[k] = s; }
+      continue;
+    }
+    Problem P;
+    P.C = A.C + A.coff[k];
+    P.n = n;
+    P.ld = n;
+    P.max_paths = A.max_paths;
+    P.flags = 0;
+    P.plan = A.plan + A.voff[k];
+    P.cost = A.cost + k;
+    P.u = A.u ? A.u + A.voff[k] : nullptr;
+    P.v = A.v ? A.v + A.voff[k] : nullptr;
+    P.stats = A.stats ? A.stats + k : nullptr;
+    P.ws = ws;
+    Engine<BLOCK, CPT> E;
+    E.run(P, smem);
+    __syncthreads();
+  }
+}
+
+__global__ void k_fill_i32(int32_t *p, int32_t value, int64_t count) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = value;
+}
+
+// ---------------------------------------------------------------------------
+// transport by unit expansion
+// ---------------------------------------------------------------------------
+// One workgroup: validate masses, then rowbin[a] / colbin[b] = bin of unit a / b
+// and rfirst[i] / cfirst[j] = first unit of bin (or -1 for zero mass).
+__global__ __launch_bounds__(1024) void k_tr_prep(const int32_t *r, const int32_t *c, int n, int m, int S,
+                                                  int32_t *rowbin, int32_t *colbin, int32_t *rfirst,
+                                                  int32_t *cfirst, int32_t *gate, ot_stats *stats) {
+  __shared__ unsigned long long s_sum[2];
+  __shared__ int s_neg;
+  __shared__ int s_off[1024];
+  if (threadIdx.x == 0) { s_sum[0] = 0; s_sum[1] = 0; s_neg = 0; }
+  __syncthreads();
+  long long a = 0, b = 0;
+  int neg = 0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) { int x = r[i]; neg |= x < 0; a += x; }
+  for (int j = threadIdx.x; j < m; j += blockDim.x) { int x = c[j]; neg |= x < 0; b += x; }
+  atomicAdd(&s_sum[0], (unsigned long long)a);  // two's complement: wraps to the signed sum
+  atomicAdd(&s_sum[1], (unsigned long long)b);
+  if (neg) atomicOr(&s_neg, 1);
+  __syncthreads();
+  const long long sr = (long long)s_sum[0], sc = (long long)s_sum[1];
+  int status = 0;
+  if (s_neg) status = OT_ENEGMASS;
+  else if (sr != sc || sr < 1 || sr != (long long)S) status = OT_EUNBALANCED;
+  if (status != 0) {
+    if (threadIdx.x == 0) {
+      *gate = status;
+      if (stats) { ot_stats s = {}; s.status = status; *stats = s; }
+    }
+    return;
+  }
+  // exclusive prefix sums, sequential over chunks of blockDim entries
+  for (int side = 0; side < 2; ++side) {
+    const int32_t *w = side == 0 ? r : c;
+    const int len = side == 0 ? n : m;
+    int32_t *bin = side == 0 ? rowbin : colbin;
+    int32_t *first = side == 0 ? rfirst : cfirst;
+    int base = 0;
+    for (int start = 0; start < len; start += blockDim.x) {
+      const int i = start + threadIdx.x;
+      const int x = i < len ? w[i] : 0;
+      s_off[threadIdx.x] = x;
+      __syncthreads();
+      // Hillis-Steele inclusive scan over the chunk
+      for (int d = 1; d < (int)blockDim.x; d <<= 1) {
+        int y = threadIdx.x >= (unsigned)d ? s_off[threadIdx.x - d] : 0;
+        __syncthreads();
+        s_off[threadIdx.x] += y;
+        __syncthreads();
+      }
+      const int incl = s_off[threadIdx.x];
+      const int excl = base + incl - x;
+      if (i < len) {
+        first[i] = x > 0 ? excl : -1;
+        for (int q = 0; q < x; ++q) bin[excl + q] = i;
+      }
+      const int total = s_off[blockDim.x - 1];
+      __syncthreads();
+      base += total;
+    }
+  }
+  if (threadIdx.x == 0) *gate = 0;
+}
+
+__global__ void k_tr_expand(const int32_t *C, int m, int S, const int32_t *rowbin, const int32_t *colbin,
+                            int32_t *Cx, const int32_t *gate) {
+  if (*gate != 0) return;
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  const int a = blockIdx.y;
+  if (b >= S || a >= S) return;
+  Cx[(size_t)a * S + b] = C[(size_t)rowbin[a] * m + colbin[b]];
+}
+
+__global__ void k_tr_aggregate(const int32_t *plan, int S, int m, const int32_t *rowbin, const int32_t *colbin,
+                               int32_t *X, const int32_t *gate, const ot_stats *stats) {
+  if (*gate != 0 || (stats && stats->status != 0)) return;
+  const int a = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= S) return;
+  const int b = plan[a];
+  if ((unsigned)b >= (unsigned)S) return;
+  atomicAdd(&X[(size_t)rowbin[a] * m + colbin[b]], 1);
+}
+
+// Bins with mass take the dual of their first unit (all units of a bin carry
+// the same dual in an optimal unit solution).
+__global__ void k_tr_duals_copy(const int64_t *U, const int64_t *V, int n, int m, const int32_t *rfirst,
+                                const int32_t *cfirst, int64_t *u, int64_t *v, const int32_t *gate,
+                                const ot_stats *stats) {
+  if (*gate != 0 || (stats && stats->status != 0)) return;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n && rfirst[i] >= 0) u[i] = U[rfirst[i]];
+  if (i < m && cfirst[i] >= 0) v[i] = V[cfirst[i]];
+}
+
+// Zero-mass row i: u_i = min over columns with mass of C_ij - v_j (one wavefront per row).
+__global__ __launch_bounds__(256) void k_tr_duals_zero_rows(const int32_t *C, const int32_t *r, const int32_t *c,
+                                                            int n, int m, int64_t *u, const int64_t *v,
+                                                            const int32_t *gate, const ot_stats *stats) {
+  if (*gate != 0 || (stats && stats->status != 0)) return;
+  const int lane = threadIdx.x & 63;
+  const int i = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+  if (i >= n || r[i] != 0) return;
+  int64_t best = INT64_MAX;
+  for (int j = lane; j < m; j += 64)
+    if (c[j] > 0) best = min(best, (int64_t)C[(size_t)i * m + j] - v[j]);
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) best = min(best, (int64_t)__shfl_xor(best, off, 64));
+  if (lane == 0) u[i] = best;
+}
+
+// Zero-mass column j: v_j = min over all rows of C_ij - u_i (one thread per column, coalesced rows).
+__global__ void k_tr_duals_zero_cols(const int32_t *C, const int32_t *c, int n, int m, const int64_t *u,
+                                     int64_t *v, const int32_t *gate, const ot_stats *stats) {
+  if (*gate != 0 || (stats && stats->status != 0)) return;
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= m || c[j] != 0) return;
+  int64_t best = INT64_MAX;
+  for (int i = 0; i < n; ++i) best = min(best, (int64_t)C[(size_t)i * m + j] - u[i]);
+  v[j] = best;
+}
+
+// ---------------------------------------------------------------------------
+// serving: C_ij = round(sqrt(|p_i - q_j|^2)) for integer points, exact
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int32_t isqrt_round(int64_t d) {
+  // floor(sqrt(d)) from the double estimate, corrected to the exact integer
+  int64_t k = (int64_t)sqrt((double)d);
+  while (k * k > d) --k;
+  while ((k + 1) * (k + 1) <= d) ++k;
+  return (int32_t)(k + ((d - k * k) > k ? 1 : 0));
+}
+
+__global__ void k_grid_cost(const int32_t *ps, const int32_t *pt, int n, int32_t *Cout) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = blockIdx.y;
+  if (j >= n || i >= n) return;
+  const int64_t dx = (int64_t)ps[2 * i] - pt[2 * j];
+  const int64_t dy = (int64_t)ps[2 * i + 1] - pt[2 * j + 1];
+  Cout[(size_t)i * n + j] = isqrt_round(dx * dx + dy * dy);
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+template <typename K>
+static hipError_t allow_lds(K kernel, size_t bytes) {
+  return hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+template <int B, int CPT>
+static hipError_t one(const Problem &P, const int32_t *gate, hipStream_t s) {
+  const size_t lds = lds_layout(P.n).total;
+  hipError_t e = allow_lds(k_assign_one<B, CPT>, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_assign_one<B, CPT>), dim3(1), dim3(B), lds, s, P, gate);
+  return hipGetLastError();
+}
+
+int cpt_for(int n, int block) {
+  const int need = (n + block - 1) / block;
+  return need <= 1 ? 1 : need <= 2 ? 2 : need <= 4 ? 4 : need <= 8 ? 8 : 0;
+}
+
+hipError_t launch_assign_one(const Problem &P, int block, const int32_t *gate, hipStream_t s) {
+  const int cpt = cpt_for(P.n, block);
+#define OTKM_ONE(B, K) if (block == B && cpt == K) return one<B, K>(P, gate, s);
+  OTKM_ONE(64, 1) OTKM_ONE(64, 2) OTKM_ONE(64, 4) OTKM_ONE(64, 8)
+  OTKM_ONE(256, 1) OTKM_ONE(256, 2) OTKM_ONE(256, 4) OTKM_ONE(256, 8)
+  OTKM_ONE(512, 1) OTKM_ONE(512, 2) OTKM_ONE(512, 4) OTKM_ONE(512, 8)
+  OTKM_ONE(1024, 1) OTKM_ONE(1024, 2) OTKM_ONE(1024, 4)
+#undef OTKM_ONE
+  return hipErrorInvalidValue;
+}
+
+template <int B, int CPT>
+static hipError_t batch(const BatchArgs &A, int grid, hipStream_t s) {
+  const size_t lds = lds_layout(A.max_n).total;
+  hipError_t e = allow_lds(k_assign_batch<B, CPT>, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_assign_batch<B, CPT>), dim3(grid), dim3(B), lds, s, A);
+  return hipGetLastError();
+}
+
+template <int B, int CPT>
+static int occ(int max_n) {
+  int blocks = 0;
+  const size_t lds = lds_layout(max_n).total;
+  if (allow_lds(k_assign_batch<B, CPT>, lds) != hipSuccess) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, (const void *)k_assign_batch<B, CPT>, B, lds) != hipSuccess)
+    return 0;
+  return blocks;
+}
+
+int batch_occupancy(int block, int max_n) {
+  const int cpt = cpt_for(max_n, block);
+#define OTKM_OCC(B, K) if (block == B && cpt == K) return occ<B, K>(max_n);
+  OTKM_OCC(64, 1) OTKM_OCC(64, 2) OTKM_OCC(64, 4) OTKM_OCC(64, 8)
+  OTKM_OCC(256, 1) OTKM_OCC(256, 2) OTKM_OCC(256, 4) OTKM_OCC(256, 8)
+  OTKM_OCC(512, 1) OTKM_OCC(512, 2) OTKM_OCC(512, 4) OTKM_OCC(512, 8)
+  OTKM_OCC(1024, 1) OTKM_OCC(1024, 2) OTKM_OCC(1024, 4)
+#undef OTKM_OCC
+  return 0;
+}
+
+hipError_t launch_assign_batch(const BatchArgs &A, int block, int grid, hipStream_t s) {
+  const int cpt = cpt_for(A.max_n, block);
+#define OTKM_BATCH(B, K) if (block == B && cpt == K) return batch<B, K>(A, grid, s);
+  OTKM_BATCH(64, 1) OTKM_BATCH(64, 2) OTKM_BATCH(64, 4) OTKM_BATCH(64, 8)
+  OTKM_BATCH(256, 1) OTKM_BATCH(256, 2) OTKM_BATCH(256, 4) OTKM_BATCH(256, 8)
+  OTKM_BATCH(512, 1) OTKM_BATCH(512, 2) OTKM_BATCH(512, 4) OTKM_BATCH(512, 8)
+  OTKM_BATCH(1024, 1) OTKM_BATCH(1024, 2) OTKM_BATCH(1024, 4)
+#undef OTKM_BATCH
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_fill_i32(int32_t *p, int32_t value, int64_t count, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  const int64_t blocks = (count + 255) / 256;
+  hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)(blocks < 1024 ? blocks : 1024)), dim3(256), 0, s, p, value, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_transport(const TransportArgs &T, int block, hipStream_t s) {
+  hipLaunchKernelGGL(k_tr_prep, dim3(1), dim3(1024), 0, s, T.r, T.c, T.n, T.m, T.S, T.rowbin, T.colbin, T.rfirst,
+                     T.cfirst, T.gate, T.stats);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_tr_expand, dim3((T.S + 255) / 256, T.S), dim3(256), 0, s, T.C, T.m, T.S, T.rowbin, T.colbin,
+                     T.Cx, T.gate);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  Problem P;
+  P.C = T.Cx; P.n = T.S; P.ld = T.S; P.max_paths = T.max_paths; P.flags = 0;
+  P.plan = T.plan; P.cost = T.cost; P.u = T.U; P.v = T.V; P.stats = T.stats; P.ws = T.ws;
+  if ((e = launch_assign_one(P, block, T.gate, s)) != hipSuccess) return e;
+  if ((e = launch_fill_i32(T.X, 0, (int64_t)T.n * T.m, s)) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_tr_aggregate, dim3((T.S + 255) / 256), dim3(256), 0, s, T.plan, T.S, T.m, T.rowbin, T.colbin,
+                     T.X, T.gate, T.stats);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  const int nm = T.n > T.m ? T.n : T.m;
+  hipLaunchKernelGGL(k_tr_duals_copy, dim3((nm + 255) / 256), dim3(256), 0, s, T.U, T.V, T.n, T.m, T.rfirst, T.cfirst,
+                     T.u, T.v, T.gate, T.stats);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_tr_duals_zero_rows, dim3((T.n + 3) / 4), dim3(256), 0, s, T.C, T.r, T.c, T.n, T.m, T.u, T.v,
+                     T.gate, T.stats);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_tr_duals_zero_cols, dim3((T.m + 255) / 256), dim3(256), 0, s, T.C, T.c, T.n, T.m, T.u, T.v,
+                     T.gate, T.stats);
+  return hipGetLastError();
+}
+
+hipError_t launch_grid_cost(const int32_t *ps, const int32_t *pt, int n, int32_t *Cout, hipStream_t s) {
+  hipLaunchKernelGGL(k_grid_cost, dim3((n + 255) / 256, n), dim3(256), 0, s, ps, pt, n, Cout);
+  return hipGetLastError();
+}
+
+}  // namespace otkm

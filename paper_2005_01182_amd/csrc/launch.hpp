@@ -1,0 +1,48 @@
+// launch.hpp -- host-side launch helpers shared by the runtime (internal).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "engine.hpp"
+
+namespace otkm {
+
+struct BatchArgs {
+  const int32_t *C;       // base of all cost matrices
+  const int64_t *coff;    // [count] element offset of instance k's matrix
+  const int32_t *n;       // [count]
+  const int64_t *voff;    // [count] element offset of instance k's plan/u/v
+  const int32_t *order;   // [count] processing order, or null
+  int count;             // instances (bound for indices in order[])
+  int nq;                // queue length: entries of order[] (or instances) this launch solves
+  int max_n, max_paths;
+  int32_t *plan;
+  int64_t *cost, *u, *v;
+  ot_stats *stats;
+  int32_t *ws;            // grid * ws_ints(max_n)
+  int32_t *head;          // queue head (reset to 0 before the launch)
+};
+
+struct TransportArgs {
+  const int32_t *C, *r, *c;
+  int n, m, S, max_paths;
+  int32_t *rowbin, *colbin, *rfirst, *cfirst, *gate;  // [S], [S], [n], [m], [1]
+  int32_t *Cx;                                        // [S*S]
+  int32_t *plan;                                      // [S]
+  int64_t *U, *V;                                     // [S] unit duals
+  int32_t *ws;                                        // ws_ints(S)
+  int32_t *X;                                         // [n*m]
+  int64_t *cost, *u, *v;                              // [1], [n], [m]
+  ot_stats *stats;                                    // [1]
+};
+
+int cpt_for(int n, int block);
+int batch_occupancy(int block, int max_n);
+hipError_t launch_assign_one(const Problem &P, int block, const int32_t *gate, hipStream_t s);
+hipError_t launch_assign_batch(const BatchArgs &A, int block, int grid, hipStream_t s);
+hipError_t launch_fill_i32(int32_t *p, int32_t value, int64_t count, hipStream_t s);
+hipError_t launch_transport(const TransportArgs &T, int block, hipStream_t s);
+hipError_t launch_grid_cost(const int32_t *ps, const int32_t *pt, int n, int32_t *Cout, hipStream_t s);
+
+}  // namespace otkm

@@ -1,0 +1,512 @@
+// runtime.hip -- host runtime and C-ABI of the batched Kuhn-Munkres solver.
+//
+// Device context (one per process, current device), a library stream for the
+// synchronous calls, grow-only device buffers, a per-stream workspace cache for
+// the asynchronous calls, host-side validation and error mapping.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <numeric>
+#include <vector>
+
+#include "launch.hpp"
+#include "otkm.h"
+#include "runtime.hpp"
+
+namespace otkm {
+
+namespace {
+
+std::mutex g_mu;          // guards the context, the pool and the schedule
+bool g_init_done = false;
+int g_init_status = OT_ENODEV;
+int g_dev = 0;
+int g_cus = 0;
+hipStream_t g_stream = nullptr;
+int g_t64 = 0, g_t256 = 0;  // 0 = defaults
+
+constexpr int kDefaultT64 = 128;
+constexpr int kDefaultT256 = 1024;
+
+struct Buf {
+  void *p = nullptr;
+  size_t bytes = 0;
+};
+std::map<int, Buf> g_pool;                      // synchronous calls (library stream)
+std::map<hipStream_t, std::map<int, Buf>> g_ws; // asynchronous calls, per stream
+
+}  // namespace
+
+int map_hip(hipError_t e) {
+  if (e == hipSuccess) return OT_OK;
+  if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) return OT_ENOMEM;
+  if (e == hipErrorNoDevice || e == hipErrorInvalidDevice) return OT_ENODEV;
+  return OT_EDEVICE;
+}
+
+int init_locked() {
+  if (g_init_done) return g_init_status;
+  g_init_done = true;
+  const char *env = std::getenv("OT_DEVICE");
+  if (env && std::strcmp(env, "none") == 0) return g_init_status = OT_ENODEV;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || count < 1) return g_init_status = OT_ENODEV;
+  if (hipGetDevice(&g_dev) != hipSuccess) return g_init_status = OT_ENODEV;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, g_dev) != hipSuccess) return g_init_status = OT_EDEVICE;
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return g_init_status = OT_ENODEV;
+  g_cus = prop.multiProcessorCount;
+  if (hipStreamCreateWithFlags(&g_stream, hipStreamNonBlocking) != hipSuccess) return g_init_status = OT_EDEVICE;
+  return g_init_status = OT_OK;
+}
+
+hipStream_t lib_stream() { return g_stream; }
+int device_cus() { return g_cus; }
+std::mutex &lib_mutex() { return g_mu; }
+
+// Grow-only buffer in slot `slot` of the synchronous pool (library stream).
+void *pool_get(int slot, size_t bytes, int *err) {
+  Buf &b = g_pool[slot];
+  if (bytes == 0) bytes = 16;
+  if (b.bytes < bytes) {
+    if (b.p) {
+      hipStreamSynchronize(g_stream);
+      hipFree(b.p);
+      b.p = nullptr;
+      b.bytes = 0;
+    }
+    hipError_t e = hipMalloc(&b.p, bytes);
+    if (e != hipSuccess) { *err = map_hip(e); b.p = nullptr; return nullptr; }
+    b.bytes = bytes;
+  }
+  return b.p;
+}
+
+// Grow-only workspace tied to a caller stream: work queued on one stream runs
+// in order, so reuse across calls on that stream is safe.  Growing
+// synchronises the stream first (not allowed during graph capture: the first
+// call on a stream, outside capture, should size it).
+void *stream_ws(hipStream_t s, int slot, size_t bytes, int *err) {
+  Buf &b = g_ws[s][slot];
+  if (bytes == 0) bytes = 16;
+  if (b.bytes < bytes) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone) {
+      *err = OT_EINVAL;
+      return nullptr;
+    }
+    if (b.p) {
+      hipStreamSynchronize(s);
+      hipFree(b.p);
+      b.p = nullptr;
+      b.bytes = 0;
+    }
+    hipError_t e = hipMalloc(&b.p, bytes);
+    if (e != hipSuccess) { *err = map_hip(e); b.p = nullptr; return nullptr; }
+    b.bytes = bytes;
+  }
+  return b.p;
+}
+
+void schedule_set_locked(int t64, int t256) {
+  g_t64 = t64;
+  g_t256 = t256;
+}
+
+// Single-instance width: one wavefront needs no workgroup barrier, so it wins
+// while its 8 columns per lane cover n; beyond that four or eight wavefronts.
+int default_block(int n) { return n <= 512 ? 64 : n <= 2048 ? 256 : 512; }
+
+int schedule_block(int n) {
+  const int t64 = g_t64 > 0 ? g_t64 : kDefaultT64;
+  const int t256 = g_t256 > 0 ? g_t256 : kDefaultT256;
+  if (n <= t64 && n <= 64 * 8) return 64;
+  if (n <= t256 && n <= 256 * 8) return 256;
+  return 512;
+}
+
+static bool block_ok(int block, int n) {
+  return (block == 64 || block == 256 || block == 512 || block == 1024) && cpt_for(n, block) != 0;
+}
+
+// Host range check: max - min over the given entries must fit 2^31 - 1.
+static bool range_ok(const int32_t *C, int64_t count) {
+  if (count <= 0) return true;
+  int32_t mn = C[0], mx = C[0];
+  for (int64_t k = 1; k < count; ++k) {
+    mn = std::min(mn, C[k]);
+    mx = std::max(mx, C[k]);
+  }
+  return (int64_t)mx - (int64_t)mn <= 0x7fffffffll;
+}
+
+static int check_options(const ot_options *opt, int n, int *block, int *max_paths, int *flags) {
+  *block = default_block(n);
+  *max_paths = 0;
+  *flags = 0;
+  if (!opt) return OT_OK;
+  for (int k = 0; k < 5; ++k)
+    if (opt->reserved[k] != 0) return OT_EINVAL;
+  if (opt->max_paths < 0 || (opt->flags & ~OT_FLAG_PHASE_TIMERS) != 0) return OT_EINVAL;
+  *max_paths = opt->max_paths;
+  *flags = opt->flags;
+  if (opt->block != 0) {
+    if (!block_ok(opt->block, n)) return OT_EINVAL;
+    *block = opt->block;
+  }
+  return OT_OK;
+}
+
+}  // namespace otkm
+
+using namespace otkm;
+
+// ---------------------------------------------------------------------------
+// C-ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+const char *ot_strerror(int status) {
+  switch (status) {
+    case OT_OK: return "ok";
+    case OT_EINVAL: return "invalid argument";
+    case OT_ERANGE: return "cost range exceeds 2^31 - 1";
+    case OT_EUNBALANCED: return "supplies and demands do not balance (or are all zero)";
+    case OT_ENEGMASS: return "negative supply or demand";
+    case OT_ETOOBIG: return "instance too large for the on-chip solver";
+    case OT_ENOMEM: return "out of memory";
+    case OT_EDEVICE: return "HIP runtime error";
+    case OT_ENODEV: return "no usable gfx950 device";
+    case OT_EINTERNAL: return "internal solver error (watchdog or invariant)";
+    default: return "unknown status";
+  }
+}
+
+int ot_init(void) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  return init_locked();
+}
+
+int ot_assign_ex(const int32_t *C, int32_t n, const ot_options *opt, int32_t *plan, int64_t *cost, int64_t *u,
+                 int64_t *v, ot_stats *stats) {
+  if (!C || !plan || !cost || n <= 0) return OT_EINVAL;
+  if (n > OT_MAX_N) return OT_ETOOBIG;
+  int block, max_paths, flags;
+  int rc = check_options(opt, n, &block, &max_paths, &flags);
+  if (rc) return rc;
+  if (!range_ok(C, (int64_t)n * n)) return OT_ERANGE;
+
+  std::lock_guard<std::mutex> lk(g_mu);
+  if ((rc = init_locked())) return rc;
+  int err = OT_OK;
+  const size_t N = (size_t)n;
+  auto *dC = (int32_t *)pool_get(0, 4 * N * N, &err);
+  auto *dplan = (int32_t *)pool_get(1, 4 * N, &err);
+  auto *du = (int64_t *)pool_get(2, 8 * N, &err);
+  auto *dv = (int64_t *)pool_get(3, 8 * N, &err);
+  auto *dcost = (int64_t *)pool_get(4, 8, &err);
+  auto *dstats = (ot_stats *)pool_get(5, sizeof(ot_stats), &err);
+  auto *dws = (int32_t *)pool_get(6, 4 * ws_ints(n), &err);
+  if (err) return err;
+  hipStream_t s = g_stream;
+  hipError_t e = hipMemcpyAsync(dC, C, 4 * N * N, hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return map_hip(e);
+  Problem P;
+  P.C = dC; P.n = n; P.ld = n; P.max_paths = max_paths; P.flags = flags;
+  P.plan = dplan; P.cost = dcost; P.u = du; P.v = dv; P.stats = dstats; P.ws = dws;
+  if ((e = launch_assign_one(P, block, nullptr, s)) != hipSuccess) return map_hip(e);
+  ot_stats hs;
+  std::vector<int32_t> hplan(N);
+  std::vector<int64_t> hu(N), hv(N);
+  int64_t hcost = 0;
+  if ((e = hipMemcpyAsync(&hs, dstats, sizeof hs, hipMemcpyDeviceToHost, s)) != hipSuccess) return map_hip(e);
+  if ((e = hipMemcpyAsync(hplan.data(), dplan, 4 * N, hipMemcpyDeviceToHost, s)) != hipSuccess) return map_hip(e);
+  if ((e = hipMemcpyAsync(hu.data(), du, 8 * N, hipMemcpyDeviceToHost, s)) != hipSuccess) return map_hip(e);
+  if ((e = hipMemcpyAsync(hv.data(), dv, 8 * N, hipMemcpyDeviceToHost, s)) != hipSuccess) return map_hip(e);
+  if ((e = hipMemcpyAsync(&hcost, dcost, 8, hipMemcpyDeviceToHost, s)) != hipSuccess) return map_hip(e);
+  if ((e = hipStreamSynchronize(s)) != hipSuccess) return map_hip(e);
+  if (hs.status != 0) return (int)hs.status;
+  std::memcpy(plan, hplan.data(), 4 * N);
+  *cost = hcost;
+  if (u) std::memcpy(u, hu.data(), 8 * N);
+  if (v) std::memcpy(v, hv.data(), 8 * N);
+  if (stats) *stats = hs;
+  return OT_OK;
+}
+
+int ot_assign(const int32_t *C, int32_t n, int32_t *plan, int64_t *cost, int64_t *u, int64_t *v) {
+  return ot_assign_ex(C, n, nullptr, plan, cost, u, v, nullptr);
+}
+
+int ot_assign_dev(const int32_t *dC, int32_t n, int32_t ld, const ot_options *opt, int32_t *dplan, int64_t *dcost,
+                  int64_t *du, int64_t *dv, ot_stats *dstats, void *stream) {
+  if (!dC || !dplan || !dcost || n <= 0 || ld < n) return OT_EINVAL;
+  if (n > OT_MAX_N) return OT_ETOOBIG;
+  int block, max_paths, flags;
+  int rc = check_options(opt, n, &block, &max_paths, &flags);
+  if (rc) return rc;
+  std::lock_guard<std::mutex> lk(g_mu);
+  if ((rc = init_locked())) return rc;
+  hipStream_t s = stream ? (hipStream_t)stream : g_stream;
+  int err = OT_OK;
+  auto *dws = (int32_t *)stream_ws(s, 0, 4 * ws_ints(n), &err);
+  if (err) return err;
+  Problem P;
+  P.C = dC; P.n = n; P.ld = ld; P.max_paths = max_paths; P.flags = flags;
+  P.plan = dplan; P.cost = dcost; P.u = du; P.v = dv; P.stats = dstats; P.ws = dws;
+  return map_hip(launch_assign_one(P, block, nullptr, s));
+}
+
+int ot_assign_batch_dev(int32_t count, int32_t max_n, const int32_t *dC, const int64_t *coff, const int32_t *n,
+                        const int64_t *voff, const int32_t *order, int32_t block, int32_t *dplan, int64_t *dcost,
+                        int64_t *du, int64_t *dv, ot_stats *dstats, void *stream) {
+  if (count < 0 || !dC || !coff || !n || !voff || !dplan || !dcost || max_n <= 0) return OT_EINVAL;
+  if (count == 0) return OT_OK;
+  if (max_n > OT_MAX_N) return OT_ETOOBIG;
+  std::lock_guard<std::mutex> lk(g_mu);
+  int rc = init_locked();
+  if (rc) return rc;
+  if (block == 0) block = schedule_block(max_n);
+  if (!block_ok(block, max_n)) return OT_EINVAL;
+  hipStream_t s = stream ? (hipStream_t)stream : g_stream;
+  const int occ = batch_occupancy(block, max_n);
+  if (occ <= 0) return OT_ETOOBIG;
+  const int grid = std::max(1, std::min<int>(count, occ * g_cus));
+  int err = OT_OK;
+  auto *head = (int32_t *)stream_ws(s, 1, 256, &err);
+  auto *dws = (int32_t *)stream_ws(s, 2, 4 * ws_ints(max_n) * (size_t)grid, &err);
+  if (err) return err;
+  hipError_t e = launch_fill_i32(head, 0, 1, s);
+  if (e != hipSuccess) return map_hip(e);
+  BatchArgs A;
+  A.C = dC; A.coff = coff; A.n = n; A.voff = voff; A.order = order;
+  A.count = count; A.nq = count; A.max_n = max_n; A.max_paths = 0;
+  A.plan = dplan; A.cost = dcost; A.u = du; A.v = dv; A.stats = dstats; A.ws = dws; A.head = head;
+  return map_hip(launch_assign_batch(A, block, grid, s));
+}
+
+int ot_assign_batch(int32_t count, const int32_t *const *C, const int32_t *n, int32_t *const *plan, int64_t *cost,
+                    int64_t *const *u, int64_t *const *v, int32_t *status) {
+  if (count < 0 || (count > 0 && (!C || !n || !plan || !cost || !status))) return OT_EINVAL;
+  if (count == 0) return OT_OK;
+  std::vector<int64_t> coff(count), voff(count);
+  int64_t ctot = 0, vtot = 0;
+  for (int k = 0; k < count; ++k) {
+    status[k] = OT_OK;
+    if (!C[k] || !plan[k] || n[k] <= 0) status[k] = OT_EINVAL;
+    else if (n[k] > OT_MAX_N) status[k] = OT_ETOOBIG;
+    else if (!range_ok(C[k], (int64_t)n[k] * n[k])) status[k] = OT_ERANGE;
+    coff[k] = ctot;
+    voff[k] = vtot;
+    if (status[k] == OT_OK) { ctot += (int64_t)n[k] * n[k]; vtot += n[k]; }
+  }
+  // size classes by workgroup width; each class runs longest-first
+  std::map<int, std::vector<int>> cls;
+  for (int k = 0; k < count; ++k)
+    if (status[k] == OT_OK) cls[schedule_block(n[k])].push_back(k);
+  if (cls.empty()) return OT_OK;
+
+  std::lock_guard<std::mutex> lk(g_mu);
+  int rc = init_locked();
+  if (rc) return rc;
+  int err = OT_OK;
+  hipStream_t s = g_stream;
+  auto *dC = (int32_t *)pool_get(10, 4 * (size_t)std::max<int64_t>(ctot, 1), &err);
+  auto *dplan = (int32_t *)pool_get(11, 4 * (size_t)std::max<int64_t>(vtot, 1), &err);
+  auto *du = (int64_t *)pool_get(12, 8 * (size_t)std::max<int64_t>(vtot, 1), &err);
+  auto *dv = (int64_t *)pool_get(13, 8 * (size_t)std::max<int64_t>(vtot, 1), &err);
+  auto *dcost = (int64_t *)pool_get(14, 8 * (size_t)count, &err);
+  auto *dstats = (ot_stats *)pool_get(15, sizeof(ot_stats) * (size_t)count, &err);
+  auto *dcoff = (int64_t *)pool_get(16, 8 * (size_t)count, &err);
+  auto *dvoff = (int64_t *)pool_get(17, 8 * (size_t)count, &err);
+  auto *dn = (int32_t *)pool_get(18, 4 * (size_t)count, &err);
+  auto *dorder = (int32_t *)pool_get(19, 4 * (size_t)count, &err);
+  auto *head = (int32_t *)pool_get(20, 4 * 8, &err);
+  if (err) return err;
+  hipError_t e;
+  for (int k = 0; k < count; ++k)
+    if (status[k] == OT_OK &&
+        (e = hipMemcpyAsync(dC + coff[k], C[k], 4 * (size_t)n[k] * n[k], hipMemcpyHostToDevice, s)) != hipSuccess)
+      return map_hip(e);
+  if ((e = hipMemcpyAsync(dcoff, coff.data(), 8 * (size_t)count, hipMemcpyHostToDevice, s)) != hipSuccess) return map_hip(e);
+  if ((e = hipMemcpyAsync(dvoff, voff.data(), 8 * (size_t)count, hipMemcpyHostToDevice, s)) != hipSuccess) return map_hip(e);
+  if ((e = hipMemcpyAsync(dn, n, 4 * (size_t)count, hipMemcpyHostToDevice, s)) != hipSuccess) return map_hip(e);
+  std::vector<int32_t> order;
+  std::vector<std::pair<int, int>> spans;  // (start in order, length) per class
+  for (auto &kv : cls) {
+    auto &v = kv.second;
+    std::stable_sort(v.begin(), v.end(), [&](int a, int b) { return n[a] > n[b]; });
+    spans.push_back({(int)order.size(), (int)v.size()});
+    order.insert(order.end(), v.begin(), v.end());
+  }
+  if ((e = hipMemcpyAsync(dorder, order.data(), 4 * order.size(), hipMemcpyHostToDevice, s)) != hipSuccess) return map_hip(e);
+  if ((e = launch_fill_i32(head, 0, 8, s)) != hipSuccess) return map_hip(e);
+  int ci = 0;
+  for (auto &kv : cls) {
+    const int block = kv.first;
+    const auto &v = kv.second;
+    int max_n = 0;
+    for (int k : v) max_n = std::max(max_n, n[k]);
+    const int occ = batch_occupancy(block, max_n);
+    if (occ <= 0) return OT_ETOOBIG;
+    const int grid = std::max(1, std::min<int>((int)v.size(), occ * g_cus));
+    auto *dws = (int32_t *)pool_get(30 + ci, 4 * ws_ints(max_n) * (size_t)grid, &err);
+    if (err) return err;
+    BatchArgs A;
+    A.C = dC; A.coff = dcoff; A.n = dn; A.voff = dvoff; A.order = dorder + spans[ci].first;
+    A.count = count; A.nq = spans[ci].second; A.max_n = max_n; A.max_paths = 0;
+    A.plan = dplan; A.cost = dcost; A.u = du; A.v = dv; A.stats = dstats; A.ws = dws; A.head = head + ci;
+    if ((e = launch_assign_batch(A, block, grid, s)) != hipSuccess) return map_hip(e);
+    ++ci;
+  }
+  std::vector<int32_t> hplan(std::max<int64_t>(vtot, 1));
+  std::vector<int64_t> hu(std::max<int64_t>(vtot, 1)), hv(std::max<int64_t>(vtot, 1)), hcost(count);
+  std::vector<ot_stats> hs(count);
+  if ((e = hipMemcpyAsync(hplan.data(), dplan, 4 * (size_t)vtot, hipMemcpyDeviceToHost, s)) != hipSuccess) return map_hip(e);
+  if ((e = hipMemcpyAsync(hu.data(), du, 8 * (size_t)vtot, hipMemcpyDeviceToHost, s)) != hipSuccess) return map_hip(e);
+  if ((e = hipMemcpyAsync(hv.data(), dv, 8 * (size_t)vtot, hipMemcpyDeviceToHost, s)) != hipSuccess) return map_hip(e);
+  if ((e = hipMemcpyAsync(hcost.data(), dcost, 8 * (size_t)count, hipMemcpyDeviceToHost, s)) != hipSuccess) return map_hip(e);
+  if ((e = hipMemcpyAsync(hs.data(), dstats, sizeof(ot_stats) * (size_t)count, hipMemcpyDeviceToHost, s)) != hipSuccess)
+    return map_hip(e);
+  if ((e = hipStreamSynchronize(s)) != hipSuccess) return map_hip(e);
+  for (int k = 0; k < count; ++k) {
+    if (status[k] != OT_OK) continue;
+    if (hs[k].status != 0) { status[k] = (int32_t)hs[k].status; continue; }
+    std::memcpy(plan[k], hplan.data() + voff[k], 4 * (size_t)n[k]);
+    cost[k] = hcost[k];
+    if (u && u[k]) std::memcpy(u[k], hu.data() + voff[k], 8 * (size_t)n[k]);
+    if (v && v[k]) std::memcpy(v[k], hv.data() + voff[k], 8 * (size_t)n[k]);
+  }
+  return OT_OK;
+}
+
+// Host-side mass and range checks shared by the transport entry points.
+static int transport_check(const int32_t *C, const int32_t *r, const int32_t *c, int32_t n, int32_t m, int64_t *S) {
+  int64_t sr = 0, sc = 0;
+  for (int i = 0; i < n; ++i) { if (r[i] < 0) return OT_ENEGMASS; sr += r[i]; }
+  for (int j = 0; j < m; ++j) { if (c[j] < 0) return OT_ENEGMASS; sc += c[j]; }
+  if (sr != sc || sr < 1) return OT_EUNBALANCED;
+  if (sr > OT_MAX_N) return OT_ETOOBIG;
+  // range over the entries the unit problem sees (rows and columns with mass)
+  bool any = false;
+  int32_t mn = 0, mx = 0;
+  for (int i = 0; i < n; ++i) {
+    if (r[i] == 0) continue;
+    for (int j = 0; j < m; ++j) {
+      if (c[j] == 0) continue;
+      const int32_t x = C[(size_t)i * m + j];
+      if (!any) { mn = mx = x; any = true; }
+      mn = std::min(mn, x);
+      mx = std::max(mx, x);
+    }
+  }
+  if ((int64_t)mx - (int64_t)mn > 0x7fffffffll) return OT_ERANGE;
+  *S = sr;
+  return OT_OK;
+}
+
+static int transport_buffers(TransportArgs &T, int n, int m, int S, bool async, hipStream_t s) {
+  int err = OT_OK;
+  const size_t SS = (size_t)S;
+  auto get = [&](int slot, size_t bytes) -> void * {
+    return async ? stream_ws(s, 10 + slot, bytes, &err) : pool_get(40 + slot, bytes, &err);
+  };
+  T.rowbin = (int32_t *)get(0, 4 * SS);
+  T.colbin = (int32_t *)get(1, 4 * SS);
+  T.rfirst = (int32_t *)get(2, 4 * (size_t)n);
+  T.cfirst = (int32_t *)get(3, 4 * (size_t)m);
+  T.gate = (int32_t *)get(4, 16);
+  T.Cx = (int32_t *)get(5, 4 * SS * SS);
+  T.plan = (int32_t *)get(6, 4 * SS);
+  T.U = (int64_t *)get(7, 8 * SS);
+  T.V = (int64_t *)get(8, 8 * SS);
+  T.ws = (int32_t *)get(9, 4 * ws_ints(S));
+  return err;
+}
+
+int ot_transport(const int32_t *C, const int32_t *r, const int32_t *c, int32_t n, int32_t m, int32_t *X,
+                 int64_t *cost, int64_t *u, int64_t *v) {
+  if (!C || !r || !c || !X || !cost || n <= 0 || m <= 0) return OT_EINVAL;
+  int64_t S64 = 0;
+  int rc = transport_check(C, r, c, n, m, &S64);
+  if (rc) return rc;
+  const int S = (int)S64;
+  std::lock_guard<std::mutex> lk(g_mu);
+  if ((rc = init_locked())) return rc;
+  hipStream_t s = g_stream;
+  int err = OT_OK;
+  const size_t NM = (size_t)n * m;
+  TransportArgs T;
+  T.n = n; T.m = m; T.S = S; T.max_paths = 0;
+  auto *dC = (int32_t *)pool_get(50, 4 * NM, &err);
+  auto *dr = (int32_t *)pool_get(51, 4 * (size_t)n, &err);
+  auto *dc = (int32_t *)pool_get(52, 4 * (size_t)m, &err);
+  T.X = (int32_t *)pool_get(53, 4 * NM, &err);
+  T.cost = (int64_t *)pool_get(54, 8, &err);
+  T.u = (int64_t *)pool_get(55, 8 * (size_t)n, &err);
+  T.v = (int64_t *)pool_get(56, 8 * (size_t)m, &err);
+  T.stats = (ot_stats *)pool_get(57, sizeof(ot_stats), &err);
+  if (err) return err;
+  if ((err = transport_buffers(T, n, m, S, false, s))) return err;
+  T.C = dC; T.r = dr; T.c = dc;
+  hipError_t e;
+  if ((e = hipMemcpyAsync(dC, C, 4 * NM, hipMemcpyHostToDevice, s)) != hipSuccess) return map_hip(e);
+  if ((e = hipMemcpyAsync(dr, r, 4 * (size_t)n, hipMemcpyHostToDevice, s)) != hipSuccess) return map_hip(e);
+  if ((e = hipMemcpyAsync(dc, c, 4 * (size_t)m, hipMemcpyHostToDevice, s)) != hipSuccess) return map_hip(e);
+  if ((e = launch_transport(T, default_block(S), s)) != hipSuccess) return map_hip(e);
+  ot_stats hs;
+  std::vector<int32_t> hX(NM);
+  std::vector<int64_t> hu(n), hv(m);
+  int64_t hcost = 0;
+  if ((e = hipMemcpyAsync(&hs, T.stats, sizeof hs, hipMemcpyDeviceToHost, s)) != hipSuccess) return map_hip(e);
+  if ((e = hipMemcpyAsync(hX.data(), T.X, 4 * NM, hipMemcpyDeviceToHost, s)) != hipSuccess) return map_hip(e);
+  if ((e = hipMemcpyAsync(hu.data(), T.u, 8 * (size_t)n, hipMemcpyDeviceToHost, s)) != hipSuccess) return map_hip(e);
+  if ((e = hipMemcpyAsync(hv.data(), T.v, 8 * (size_t)m, hipMemcpyDeviceToHost, s)) != hipSuccess) return map_hip(e);
+  if ((e = hipMemcpyAsync(&hcost, T.cost, 8, hipMemcpyDeviceToHost, s)) != hipSuccess) return map_hip(e);
+  if ((e = hipStreamSynchronize(s)) != hipSuccess) return map_hip(e);
+  if (hs.status != 0) return (int)hs.status;
+  std::memcpy(X, hX.data(), 4 * NM);
+  *cost = hcost;
+  if (u) std::memcpy(u, hu.data(), 8 * (size_t)n);
+  if (v) std::memcpy(v, hv.data(), 8 * (size_t)m);
+  return OT_OK;
+}
+
+int ot_transport_dev(const int32_t *dC, const int32_t *dr, const int32_t *dc, int32_t n, int32_t m, int32_t S,
+                     int32_t *dX, int64_t *dcost, int64_t *du, int64_t *dv, ot_stats *dstats, void *stream) {
+  if (!dC || !dr || !dc || !dX || !dcost || !du || !dv || n <= 0 || m <= 0 || S <= 0) return OT_EINVAL;
+  if (S > OT_MAX_N) return OT_ETOOBIG;
+  std::lock_guard<std::mutex> lk(g_mu);
+  int rc = init_locked();
+  if (rc) return rc;
+  hipStream_t s = stream ? (hipStream_t)stream : g_stream;
+  TransportArgs T;
+  T.C = dC; T.r = dr; T.c = dc; T.n = n; T.m = m; T.S = S; T.max_paths = 0;
+  T.X = dX; T.cost = dcost; T.u = du; T.v = dv;
+  int err = OT_OK;
+  T.stats = dstats ? dstats : (ot_stats *)stream_ws(s, 30, sizeof(ot_stats), &err);
+  if (err) return err;
+  if ((err = transport_buffers(T, n, m, S, true, s))) return err;
+  return map_hip(launch_transport(T, default_block(S), s));
+}
+
+int ot_schedule_get(int32_t *t64, int32_t *t256) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (t64) *t64 = g_t64 > 0 ? g_t64 : kDefaultT64;
+  if (t256) *t256 = g_t256 > 0 ? g_t256 : kDefaultT256;
+  return OT_OK;
+}
+
+int ot_schedule_set(int32_t t64, int32_t t256) {
+  if (t64 < 0 || t256 < 0) return OT_EINVAL;
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_t64 = t64;
+  g_t256 = t256;
+  return OT_OK;
+}
+
+}  // extern "C"

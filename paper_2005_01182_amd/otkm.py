@@ -1,0 +1,253 @@
+"""ctypes binding of libotkm.so (C-ABI in include/otkm.h).
+
+Argument marshalling only: every step of the solve runs in the HIP library.
+Names follow the C-ABI.  Host calls take numpy arrays; ``*_dev`` calls take
+torch device tensors (torch is used for device memory and streams only).
+
+If the library has not been built this module raises on load; there is no
+fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libotkm.so")
+
+OT_OK, OT_EINVAL, OT_ERANGE, OT_EUNBALANCED, OT_ENEGMASS = 0, -1, -2, -3, -4
+OT_ETOOBIG, OT_ENOMEM, OT_EDEVICE, OT_ENODEV, OT_EINTERNAL = -5, -6, -7, -8, -9
+OT_MAX_N = 4096
+
+EXPORTS = [
+    "ot_strerror", "ot_init", "ot_assign", "ot_assign_ex", "ot_transport", "ot_assign_batch",
+    "ot_assign_dev", "ot_assign_batch_dev", "ot_transport_dev",
+    "ot_schedule_get", "ot_schedule_set", "ot_schedule_tune",
+]
+
+
+class ot_stats(ctypes.Structure):
+    _fields_ = [(name, ctypes.c_int64) for name in
+                ("levels", "dual_adjusts", "aug_events", "paths", "rows_swept", "gathers", "resweeps", "status",
+                 "t_sweep_ns", "t_select_ns", "t_settle_ns", "t_augment_ns", "refreshes", "refresh_cols",
+                 "t_refresh_ns")]
+
+    def as_dict(self):
+        return {name: int(getattr(self, name)) for name, _ in self._fields_}
+
+
+STATS_FIELDS = [name for name, _ in ot_stats._fields_]
+
+
+class ot_options(ctypes.Structure):
+    _fields_ = [("max_paths", ctypes.c_int32), ("block", ctypes.c_int32), ("flags", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 5)]
+
+
+OT_FLAG_PHASE_TIMERS = 1
+
+
+class OtError(RuntimeError):
+    def __init__(self, code, where=""):
+        self.code = int(code)
+        super().__init__("%s: %s (%d)" % (where, strerror(code), code))
+
+
+_lib = None
+_I32P = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
+_I64P = np.ctypeslib.ndpointer(dtype=np.int64, flags="C_CONTIGUOUS")
+_VP = ctypes.c_void_p
+_I32 = ctypes.c_int32
+
+
+def load():
+    """Load libotkm.so (raises if it is missing: build it with paper_2005_01182_amd.build)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libotkm.so not built at %s (run python -m paper_2005_01182_amd.build)" % LIB_PATH)
+        # torch bundles its own HIP runtime under the same soname; load it first so the
+        # process holds a single runtime that both torch tensors and this library use
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
+        lib = ctypes.CDLL(LIB_PATH)
+        lib.ot_strerror.restype = ctypes.c_char_p
+        lib.ot_strerror.argtypes = [ctypes.c_int]
+        lib.ot_init.argtypes = []
+        lib.ot_assign.argtypes = [_VP, _I32, _VP, _VP, _VP, _VP]
+        lib.ot_assign_ex.argtypes = [_VP, _I32, _VP, _VP, _VP, _VP, _VP, _VP]
+        lib.ot_transport.argtypes = [_VP, _VP, _VP, _I32, _I32, _VP, _VP, _VP, _VP]
+        lib.ot_assign_batch.argtypes = [_I32, _VP, _VP, _VP, _VP, _VP, _VP, _VP]
+        lib.ot_assign_dev.argtypes = [_VP, _I32, _I32, _VP, _VP, _VP, _VP, _VP, _VP, _VP]
+        lib.ot_assign_batch_dev.argtypes = [_I32, _I32, _VP, _VP, _VP, _VP, _VP, _I32, _VP, _VP, _VP, _VP, _VP, _VP]
+        lib.ot_transport_dev.argtypes = [_VP, _VP, _VP, _I32, _I32, _I32, _VP, _VP, _VP, _VP, _VP, _VP]
+        lib.ot_schedule_get.argtypes = [_VP, _VP]
+        lib.ot_schedule_set.argtypes = [_I32, _I32]
+        lib.ot_schedule_tune.argtypes = [_I32]
+        for name in EXPORTS:
+            if name != "ot_strerror":
+                getattr(lib, name).restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def strerror(code) -> str:
+    return load().ot_strerror(int(code)).decode()
+
+
+def _check(rc, where):
+    if rc != OT_OK:
+        raise OtError(rc, where)
+
+
+def _p(a):
+    return ctypes.c_void_p(a.ctypes.data) if a is not None else None
+
+
+def ot_init() -> int:
+    return load().ot_init()
+
+
+def device_info() -> dict:
+    import torch
+    props = torch.cuda.get_device_properties(0)
+    return {"name": props.name, "arch": props.gcnArchName, "cus": props.multi_processor_count,
+            "mem_gb": props.total_memory / 2**30}
+
+
+def _options(max_paths=0, block=0, timers=False):
+    o = ot_options()
+    o.max_paths = int(max_paths)
+    o.block = int(block)
+    o.flags = OT_FLAG_PHASE_TIMERS if timers else 0
+    return o
+
+
+# ----------------------------------------------------------------------------- host calls
+def ot_assign(C, max_paths: int = 0, block: int = 0, with_stats: bool = False, timers: bool = False):
+    """Exact assignment of a square int32 cost matrix.
+
+    Returns (plan, cost, u, v) or (plan, cost, u, v, stats_dict).
+    """
+    C = np.ascontiguousarray(C, dtype=np.int32)
+    if C.ndim != 2 or C.shape[0] != C.shape[1]:
+        raise ValueError("square cost matrix required")
+    n = C.shape[0]
+    plan = np.empty(n, np.int32)
+    u = np.empty(n, np.int64)
+    v = np.empty(n, np.int64)
+    cost = ctypes.c_int64(0)
+    st = ot_stats()
+    opt = _options(max_paths, block, timers)
+    rc = load().ot_assign_ex(_p(C), n, ctypes.byref(opt), _p(plan), ctypes.byref(cost), _p(u), _p(v),
+                             ctypes.byref(st))
+    _check(rc, "ot_assign")
+    out = (plan, int(cost.value), u, v)
+    return out + (st.as_dict(),) if with_stats else out
+
+
+def ot_transport(C, r, c):
+    """Exact integer transport.  Returns (X, cost, u, v)."""
+    C = np.ascontiguousarray(C, dtype=np.int32)
+    r = np.ascontiguousarray(r, dtype=np.int32)
+    c = np.ascontiguousarray(c, dtype=np.int32)
+    n, m = C.shape
+    if r.shape != (n,) or c.shape != (m,):
+        raise ValueError("mass vectors must match the cost matrix")
+    X = np.empty((n, m), np.int32)
+    u = np.empty(n, np.int64)
+    v = np.empty(m, np.int64)
+    cost = ctypes.c_int64(0)
+    rc = load().ot_transport(_p(C), _p(r), _p(c), n, m, _p(X), ctypes.byref(cost), _p(u), _p(v))
+    _check(rc, "ot_transport")
+    return X, int(cost.value), u, v
+
+
+def ot_assign_batch(Cs):
+    """Many assignments in one persistent launch.
+
+    Returns a list of (plan, cost, u, v) or OtError per instance.
+    """
+    Cs = [np.ascontiguousarray(C, dtype=np.int32) for C in Cs]
+    k = len(Cs)
+    ns = np.array([C.shape[0] for C in Cs], np.int32)
+    plans = [np.empty(int(x), np.int32) for x in ns]
+    us = [np.empty(int(x), np.int64) for x in ns]
+    vs = [np.empty(int(x), np.int64) for x in ns]
+    cost = np.zeros(k, np.int64)
+    status = np.zeros(k, np.int32)
+    P = ctypes.c_void_p * k
+    cp = P(*[C.ctypes.data for C in Cs])
+    pp = P(*[a.ctypes.data for a in plans])
+    up = P(*[a.ctypes.data for a in us])
+    vp = P(*[a.ctypes.data for a in vs])
+    rc = load().ot_assign_batch(k, cp, _p(ns), pp, _p(cost), up, vp, _p(status))
+    _check(rc, "ot_assign_batch")
+    out = []
+    for i in range(k):
+        out.append(OtError(int(status[i]), "instance %d" % i) if status[i] != 0
+                   else (plans[i], int(cost[i]), us[i], vs[i]))
+    return out
+
+
+def ot_schedule_get():
+    a, b = ctypes.c_int32(0), ctypes.c_int32(0)
+    _check(load().ot_schedule_get(ctypes.byref(a), ctypes.byref(b)), "ot_schedule_get")
+    return int(a.value), int(b.value)
+
+
+def ot_schedule_set(t64: int, t256: int):
+    _check(load().ot_schedule_set(int(t64), int(t256)), "ot_schedule_set")
+
+
+def ot_schedule_tune(reps: int = 8):
+    _check(load().ot_schedule_tune(int(reps)), "ot_schedule_tune")
+    return ot_schedule_get()
+
+
+# ----------------------------------------------------------------------------- device calls
+def _tp(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def stats_tensor(count=1, device="cuda"):
+    """int64 device tensor laid out as ot_stats[count] (fields as STATS_FIELDS)."""
+    import torch
+    return torch.zeros((count, len(STATS_FIELDS)), dtype=torch.int64, device=device)
+
+
+def ot_assign_dev(C, plan, cost, u=None, v=None, stats=None, max_paths=0, block=0, stream=None, ld=None,
+                  timers=False):
+    """Queue an assignment on device tensors (asynchronous on `stream`)."""
+    n = int(C.shape[0])
+    ld = int(ld if ld is not None else C.stride(0))
+    opt = _options(max_paths, block, timers)
+    rc = load().ot_assign_dev(_tp(C), n, ld, ctypes.byref(opt), _tp(plan), _tp(cost), _tp(u), _tp(v),
+                              _tp(stats), _stream(stream))
+    _check(rc, "ot_assign_dev")
+
+
+def ot_assign_batch_dev(count, max_n, C, coff, n, voff, plan, cost, u=None, v=None, stats=None, order=None,
+                        block=0, stream=None):
+    """Queue a persistent batch on device tensors (asynchronous on `stream`)."""
+    rc = load().ot_assign_batch_dev(int(count), int(max_n), _tp(C), _tp(coff), _tp(n), _tp(voff), _tp(order),
+                                    int(block), _tp(plan), _tp(cost), _tp(u), _tp(v), _tp(stats), _stream(stream))
+    _check(rc, "ot_assign_batch_dev")
+
+
+def ot_transport_dev(C, r, c, S, X, cost, u, v, stats=None, stream=None):
+    """Queue an integer transport solve on device tensors (asynchronous on `stream`)."""
+    n, m = int(C.shape[0]), int(C.shape[1])
+    rc = load().ot_transport_dev(_tp(C), _tp(r), _tp(c), n, m, int(S), _tp(X), _tp(cost), _tp(u), _tp(v),
+                                 _tp(stats), _stream(stream))
+    _check(rc, "ot_transport_dev")

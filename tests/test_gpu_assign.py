@@ -1,0 +1,168 @@
+"""GPU parity: the HIP solver against the CPU oracle on the same seeded inputs.
+
+Bar (integer work): the optimal cost is bit-exact against the oracle and the
+returned (plan, u, v) passes the LP-duality certificate.  Plans may differ from
+the oracle's when several optimal plans exist.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2005_01182_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def gpu_vs_oracle(ot, C, **kw):
+    say("case n=%d %s" % (C.shape[0], kw))
+    plan, cost, u, v, st = ot.ot_assign(C, with_stats=True, **kw)
+    assert st["status"] == 0
+    assert oracle.certify_assign(C, plan, u, v) == 0
+    _, ocost, _, _ = oracle.assign(C)
+    assert cost == ocost
+    assert st["paths"] == C.shape[0]
+    return plan, cost, u, v, st
+
+
+def test_small_uniform_config(otkm_gpu):
+    C = wl.uniform_assignment(64, seed=0)
+    gpu_vs_oracle(otkm_gpu, C)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 8, 17, 63, 64, 65, 100, 127, 128, 129, 200, 255, 256, 257, 300])
+def test_random_sizes_uniform(otkm_gpu, n):
+    C = wl.uniform_assignment(n, seed=1000 + n)
+    gpu_vs_oracle(otkm_gpu, C)
+
+
+@pytest.mark.parametrize("n", [7, 64, 150, 333])
+def test_heavy_ties(otkm_gpu, n):
+    rng = np.random.default_rng(n)
+    C = rng.integers(0, 3, (n, n), endpoint=True).astype(np.int32)
+    gpu_vs_oracle(otkm_gpu, C)
+
+
+def test_constant_matrix(otkm_gpu):
+    C = np.full((130, 130), 7, np.int32)
+    plan, cost, u, v, st = gpu_vs_oracle(otkm_gpu, C)
+    assert cost == 130 * 7
+
+
+@pytest.mark.parametrize("n", [5, 96, 400])
+def test_negative_and_wide_range(otkm_gpu, n):
+    rng = np.random.default_rng(7 + n)
+    C = rng.integers(-(2**30), 2**30 - 1, (n, n)).astype(np.int32)
+    gpu_vs_oracle(otkm_gpu, C)
+
+
+def test_extreme_range_edge(otkm_gpu):
+    rng = np.random.default_rng(3)
+    C = rng.integers(-(2**30), 2**30, (40, 40)).astype(np.int32)
+    C[0, 0] = -(2**30)
+    C[1, 1] = 2**30 - 1   # max - min = 2^31 - 1 exactly
+    gpu_vs_oracle(otkm_gpu, C)
+
+
+def test_planted_permutation_unique(otkm_gpu):
+    rng = np.random.default_rng(4)
+    n = 500
+    p = rng.permutation(n)
+    C = rng.integers(1, 100, (n, n)).astype(np.int32)
+    C[np.arange(n), p] = 0
+    plan, cost, _, _ = otkm_gpu.ot_assign(C)
+    assert cost == 0 and np.array_equal(plan, p)
+
+
+@pytest.mark.parametrize("n", [500, 1000, 1024, 1025, 1500])
+def test_geometric_mid(otkm_gpu, n):
+    C = wl.geometric_assignment(n, seed=n)
+    gpu_vs_oracle(otkm_gpu, C)
+
+
+def test_geometric_full_size_config(otkm_gpu):
+    # the headline workload at its full size: n = 2048, seed 0
+    C = wl.geometric_assignment(2048, seed=0)
+    plan, cost, u, v, st = gpu_vs_oracle(otkm_gpu, C)
+    say("n=2048 stats", st)
+
+
+def test_embedding_like(otkm_gpu):
+    for k, n in enumerate((16, 77, 256, 512)):
+        gpu_vs_oracle(otkm_gpu, wl.embedding_problem(n, seed=0, k=k))
+
+
+def test_max_size_4096_certificate(otkm_gpu):
+    # the oracle is slow at this size; optimality is proven by the certificate
+    C = wl.geometric_assignment(4096, seed=5)
+    say("case n=4096 certificate")
+    plan, cost, u, v, st = otkm_gpu.ot_assign(C, with_stats=True)
+    assert st["status"] == 0
+    assert oracle.certify_assign(C, plan, u, v) == 0
+    assert cost == int(C[np.arange(4096), plan].astype(np.int64).sum())
+
+
+@pytest.mark.parametrize("n", [60, 250, 1000])
+def test_every_width_gives_identical_results(otkm_gpu, n):
+    C = wl.uniform_assignment(n, seed=n, hi=50)
+    outs = []
+    for block in (64, 256, 512, 1024):
+        if (n + block - 1) // block > 8:
+            continue
+        say("case n=%d block=%d" % (n, block))
+        outs.append(otkm_gpu.ot_assign(C, block=block))
+    for o in outs[1:]:
+        assert np.array_equal(o[0], outs[0][0]) and o[1] == outs[0][1]
+        assert np.array_equal(o[2], outs[0][2]) and np.array_equal(o[3], outs[0][3])
+
+
+def test_repeat_runs_identical(otkm_gpu):
+    C = wl.geometric_assignment(700, seed=9)
+    first = otkm_gpu.ot_assign(C)
+    for _ in range(5):
+        again = otkm_gpu.ot_assign(C)
+        assert np.array_equal(again[0], first[0]) and again[1] == first[1]
+        assert np.array_equal(again[2], first[2]) and np.array_equal(again[3], first[3])
+
+
+@pytest.mark.parametrize("max_paths", [1, 3])
+def test_plain_km_mode_same_cost(otkm_gpu, max_paths):
+    C = wl.geometric_assignment(300, seed=2)
+    plan, cost, u, v, st = gpu_vs_oracle(otkm_gpu, C, max_paths=max_paths)
+    assert st["aug_events"] == 300 if max_paths == 1 else st["aug_events"] >= 100
+
+
+def test_device_api_matches_host_api(otkm_gpu):
+    import torch
+    C = wl.geometric_assignment(900, seed=4)
+    ref = otkm_gpu.ot_assign(C)
+    dC = torch.from_numpy(C).cuda()
+    plan = torch.empty(900, dtype=torch.int32, device="cuda")
+    cost = torch.empty(1, dtype=torch.int64, device="cuda")
+    u = torch.empty(900, dtype=torch.int64, device="cuda")
+    v = torch.empty(900, dtype=torch.int64, device="cuda")
+    st = otkm_gpu.stats_tensor()
+    otkm_gpu.ot_assign_dev(dC, plan, cost, u, v, st)
+    torch.cuda.synchronize()
+    assert int(st[0, 7]) == 0
+    assert np.array_equal(plan.cpu().numpy(), ref[0]) and int(cost.item()) == ref[1]
+    assert np.array_equal(u.cpu().numpy(), ref[2]) and np.array_equal(v.cpu().numpy(), ref[3])
+
+
+def test_device_api_with_row_stride(otkm_gpu):
+    import torch
+    C = wl.uniform_assignment(100, seed=5)
+    big = torch.zeros((100, 128), dtype=torch.int32, device="cuda")
+    big[:, :100] = torch.from_numpy(C).cuda()
+    big[:, 100:] = -12345   # padding the solver must not read
+    plan = torch.empty(100, dtype=torch.int32, device="cuda")
+    cost = torch.empty(1, dtype=torch.int64, device="cuda")
+    otkm_gpu.ot_assign_dev(big, plan, cost, ld=128)
+    torch.cuda.synchronize()
+    assert int(cost.item()) == oracle.assign(C)[1]

@@ -1,0 +1,186 @@
+"""GPU parity for the batch path, the transport path and the serving cost kernel."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2005_01182_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def test_batch_mixed_sizes_vs_oracle(otkm_gpu):
+    rng = np.random.default_rng(11)
+    sizes = [1, 2, 16, 63, 64, 65, 100, 128, 129, 200, 256, 257, 400, 512, 700, 1024, 1100]
+    Cs = []
+    for k, n in enumerate(sizes):
+        if k % 2:
+            Cs.append(wl.uniform_assignment(n, seed=k, hi=int(rng.integers(3, 5000))))
+        else:
+            Cs.append(wl.geometric_assignment(n, seed=k))
+    say("batch sizes", sizes)
+    res = otkm_gpu.ot_assign_batch(Cs)
+    for C, r in zip(Cs, res):
+        assert not isinstance(r, Exception), r
+        plan, cost, u, v = r
+        assert oracle.certify_assign(C, plan, u, v) == 0
+        assert cost == oracle.assign(C)[1]
+
+
+def test_batch_embedding_sample_matches_single(otkm_gpu):
+    sizes = wl.embedding_sizes(64, seed=3)
+    Cs = [wl.embedding_problem(int(n), 3, k) for k, n in enumerate(sizes)]
+    say("batch of 64 embedding problems")
+    res = otkm_gpu.ot_assign_batch(Cs)
+    for k, (C, r) in enumerate(zip(Cs, res)):
+        plan, cost, u, v = r
+        assert oracle.certify_assign(C, plan, u, v) == 0
+        if k % 8 == 0:
+            assert cost == oracle.assign(C)[1]
+            single = otkm_gpu.ot_assign(C)
+            assert single[1] == cost
+
+
+def test_batch_invalid_instance_reports_status(otkm_gpu):
+    good = wl.uniform_assignment(10, seed=1)
+    bad = np.zeros((3, 3), np.int32)
+    bad[0, 0] = -(2**31)
+    bad[1, 1] = 2**31 - 1
+    res = otkm_gpu.ot_assign_batch([good, bad, good])
+    assert not isinstance(res[0], Exception) and not isinstance(res[2], Exception)
+    assert isinstance(res[1], otkm_gpu.OtError) and res[1].code == otkm_gpu.OT_ERANGE
+
+
+def _pack_device(Cs):
+    import torch
+    ns = np.array([C.shape[0] for C in Cs], np.int32)
+    coff = np.zeros(len(Cs), np.int64)
+    voff = np.zeros(len(Cs), np.int64)
+    coff[1:] = np.cumsum(ns.astype(np.int64) ** 2)[:-1]
+    voff[1:] = np.cumsum(ns.astype(np.int64))[:-1]
+    flat = np.concatenate([C.reshape(-1) for C in Cs])
+    order = np.argsort(-ns, kind="stable").astype(np.int32)
+    d = lambda a: torch.from_numpy(a).cuda()
+    return ns, d(flat), d(coff), d(ns), d(voff), d(order), int(voff[-1] + ns[-1])
+
+
+def test_batch_dev_graph_replay_matches_eager(otkm_gpu):
+    import torch
+    sizes = wl.embedding_sizes(96, lo=16, hi=200, seed=5)
+    Cs = [wl.embedding_problem(int(n), 5, k) for k, n in enumerate(sizes)]
+    ns, dC, dcoff, dn, dvoff, dorder, vtot = _pack_device(Cs)
+    count, max_n = len(Cs), int(ns.max())
+    plan = torch.empty(vtot, dtype=torch.int32, device="cuda")
+    cost = torch.empty(count, dtype=torch.int64, device="cuda")
+    u = torch.empty(vtot, dtype=torch.int64, device="cuda")
+    v = torch.empty(vtot, dtype=torch.int64, device="cuda")
+    st = otkm_gpu.stats_tensor(count)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        otkm_gpu.ot_assign_batch_dev(count, max_n, dC, dcoff, dn, dvoff, plan, cost, u, v, st, order=dorder,
+                                     stream=s)
+    s.synchronize()
+    eager = (plan.clone(), cost.clone(), u.clone(), v.clone())
+    assert int(st[:, 7].abs().max()) == 0
+    for k in range(0, count, 12):
+        o = int(dvoff[k]); n = int(ns[k])
+        assert int(cost[k]) == oracle.assign(Cs[k])[1]
+        assert oracle.certify_assign(Cs[k], plan[o:o + n].cpu().numpy(), u[o:o + n].cpu().numpy(),
+                                     v[o:o + n].cpu().numpy()) == 0
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        otkm_gpu.ot_assign_batch_dev(count, max_n, dC, dcoff, dn, dvoff, plan, cost, u, v, st, order=dorder,
+                                     stream=s)
+    for rep in range(3):
+        plan.fill_(-1); cost.fill_(-1)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        say("replay", rep)
+        assert torch.equal(plan, eager[0]) and torch.equal(cost, eager[1])
+        assert torch.equal(u, eager[2]) and torch.equal(v, eager[3])
+
+
+def test_transport_pixel_config(otkm_gpu):
+    C, r, c = wl.pixel_histogram_pair()
+    say("transport 784x784, S=1024")
+    X, cost, u, v = otkm_gpu.ot_transport(C, r, c)
+    assert oracle.certify_transport(C, r, c, X, u, v) == 0
+    oX, ocost, ou, ov = oracle.transport(C, r, c)
+    assert cost == ocost
+    red = C.astype(np.int64) - u[:, None] - v[None, :]
+    for i in np.nonzero(r == 0)[0][:50]:
+        assert red[i, c > 0].min() == 0
+    for j in np.nonzero(c == 0)[0][:50]:
+        assert red[:, j].min() == 0
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_transport_small_with_zero_bins(otkm_gpu, seed):
+    rng = np.random.default_rng(seed)
+    n, m = 9, 13
+    C = rng.integers(0, 60, (n, m)).astype(np.int32)
+    r = rng.integers(0, 5, n).astype(np.int32)
+    c = rng.integers(0, 5, m).astype(np.int32)
+    d = int(r.sum() - c.sum())
+    if d > 0:
+        c[0] += d
+    else:
+        r[0] -= d
+    r[1] = 0 if r.sum() - r[1] > 0 else r[1]
+    c[2] = c[2]
+    d = int(r.sum() - c.sum())
+    c[0] += d if d > 0 else 0
+    r[0] += -d if d < 0 else 0
+    X, cost, u, v = otkm_gpu.ot_transport(C, r, c)
+    assert oracle.certify_transport(C, r, c, X, u, v) == 0
+    assert cost == oracle.transport(C, r, c)[1]
+    ou, ov = oracle.transport(C, r, c)[2:]
+    red = C.astype(np.int64) - u[:, None] - v[None, :]
+    for i in np.nonzero(r == 0)[0]:
+        assert red[i, c > 0].min() == 0
+
+
+def test_transport_unit_masses_equal_assign(otkm_gpu):
+    C = wl.uniform_assignment(120, seed=8)
+    one = np.ones(120, np.int32)
+    X, cost, u, v = otkm_gpu.ot_transport(C, one, one)
+    assert cost == otkm_gpu.ot_assign(C)[1]
+
+
+def test_transport_dev_matches_host(otkm_gpu):
+    import torch
+    C, r, c = wl.pixel_histogram_pair(side=20, seeds=(3, 4), total=500)
+    ref = otkm_gpu.ot_transport(C, r, c)
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    n, m = C.shape
+    X = torch.empty((n, m), dtype=torch.int32, device="cuda")
+    cost = torch.empty(1, dtype=torch.int64, device="cuda")
+    u = torch.empty(n, dtype=torch.int64, device="cuda")
+    v = torch.empty(m, dtype=torch.int64, device="cuda")
+    st = otkm_gpu.stats_tensor()
+    otkm_gpu.ot_transport_dev(d(C), d(r), d(c), int(r.sum()), X, cost, u, v, st)
+    torch.cuda.synchronize()
+    assert int(st[0, 7]) == 0
+    assert np.array_equal(X.cpu().numpy(), ref[0]) and int(cost.item()) == ref[1]
+
+
+def test_transport_dev_reports_unbalanced(otkm_gpu):
+    import torch
+    C = np.zeros((3, 3), np.int32)
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    X = torch.empty((3, 3), dtype=torch.int32, device="cuda")
+    cost = torch.zeros(1, dtype=torch.int64, device="cuda")
+    u = torch.empty(3, dtype=torch.int64, device="cuda")
+    v = torch.empty(3, dtype=torch.int64, device="cuda")
+    st = otkm_gpu.stats_tensor()
+    otkm_gpu.ot_transport_dev(d(C), d(np.array([1, 1, 1], np.int32)), d(np.array([1, 1, 2], np.int32)), 3,
+                              X, cost, u, v, st)
+    torch.cuda.synchronize()
+    assert int(st[0, 7]) == otkm_gpu.OT_EUNBALANCED
