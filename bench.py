@@ -1,11 +1,15 @@
 """Benchmark of the batched Kuhn-Munkres solver on one MI355X.
 
-Default workload (one step = one exact solve of the geometric assignment):
+Default (headline) workload, one step = one exact solve: geometric assignment,
 sources on the unit circle, targets on the perimeter of the side-1 square,
 noise sigma = 0.02, C = rint(1e4 * distance) int32, n = 2048, seed 0.  Inputs
 are resident in HBM before the timed region.  Prints ONE JSON line.
 
-Other modes (not the headline line): --mode small | transport | batch | serve.
+Other modes (each prints one JSON line of its own; not the headline):
+  --mode small      n = 64 uniform costs in [0, 1000], seed 0
+  --mode transport  28x28 pixel histograms, mass 1024 each, squared grid cost
+  --mode batch      4096 embedding assignments, n ~ U{16..512}, one graph replay per step
+  --mode serve      Poisson request stream through the continuous-batching server
 """
 from __future__ import annotations
 
@@ -21,32 +25,60 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+METRIC = "solves/s + achieved HBM GB/s at n=2048; p50/p99 latency batched vs plain"
+F = {name: i for i, name in enumerate(
+    ["levels", "dual_adjusts", "aug_events", "paths", "rows_swept", "gathers", "resweeps", "status",
+     "t_sweep_ns", "t_select_ns", "t_settle_ns", "t_augment_ns", "refreshes", "refresh_cols", "t_refresh_ns"])}
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def percentile(xs, q):
-    return float(np.percentile(np.asarray(xs, dtype=np.float64), q)) if len(xs) else None
+def pct(xs, q):
+    return round(float(np.percentile(np.asarray(xs, dtype=np.float64), q)), 4) if len(xs) else None
 
 
-def cpu_oracle_rate(Cs, budget_s=20.0):
-    """Time the CPU oracle (single thread) on a bounded sample; returns (solves/s, sample text)."""
-    import oracle
+def alg_bytes(stats, ns):
+    """Algorithmic cost-matrix bytes of each solve: full rows read (2n at
+    initialisation + frontier + re-sweeps) x 4n, plus single entries re-read to
+    refresh stale column minima x 4."""
+    ns = np.asarray(ns, dtype=np.float64)
+    return 4.0 * ns * stats[:, F["rows_swept"]].astype(np.float64) + 4.0 * stats[:, F["gathers"]].astype(np.float64)
+
+
+def roofline(bytes_per_launch, seconds_per_launch, traffic=None):
+    achieved = float(bytes_per_launch / seconds_per_launch / 1e9)
+    return {"bound": "hbm", "achieved": round(achieved, 3), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 6), "traffic": traffic}
+
+
+def counters(stats):
+    return {k: int(stats[0, F[k]]) for k in ("levels", "dual_adjusts", "aug_events", "rows_swept", "gathers",
+                                             "resweeps", "refreshes")}
+
+
+def cpu_rate(fn, items, budget_s):
+    """Run the CPU oracle over items until the budget is spent; returns (items/s, items done)."""
     t0 = time.perf_counter()
     done = 0
-    for C in Cs:
-        oracle.assign(C)
+    for it in items:
+        fn(it)
         done += 1
         if time.perf_counter() - t0 > budget_s:
             break
-    dt = time.perf_counter() - t0
-    return done / dt, done
+    return done / (time.perf_counter() - t0), done
 
 
+def base_line(args, value, unit, ms_per_step, config):
+    return {"metric": METRIC, "value": round(value, 4), "unit": unit, "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": round(ms_per_step, 5), "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "int64", "data": "synthetic", "config": config}
+
+
+# ----------------------------------------------------------------------------- single solves
 def solve_series(ot, torch, dC, n, steps, warmup, max_paths, stream, block=0, timers=False):
-    """Run warmup + timed solves on `stream`; returns per-solve ms (events), stats, total ms."""
+    """Warmup + timed solves on `stream`; returns per-solve ms (events), stats, total ms, cost."""
     plan = torch.empty(n, dtype=torch.int32, device="cuda")
     cost = torch.empty(1, dtype=torch.int64, device="cuda")
     u = torch.empty(n, dtype=torch.int64, device="cuda")
@@ -57,8 +89,7 @@ def solve_series(ot, torch, dC, n, steps, warmup, max_paths, stream, block=0, ti
                          timers=timers)
     torch.cuda.synchronize()
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
-    t_start = torch.cuda.Event(enable_timing=True)
-    t_end = torch.cuda.Event(enable_timing=True)
+    t_start, t_end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t_start.record(stream)
     for k in range(steps):
@@ -69,109 +100,259 @@ def solve_series(ot, torch, dC, n, steps, warmup, max_paths, stream, block=0, ti
     t_end.record(stream)
     torch.cuda.synchronize()
     per = [a.elapsed_time(b) for a, b in ev]
-    total = t_start.elapsed_time(t_end)
     stats = st[warmup:].cpu().numpy()
-    return per, stats, total, int(cost.item()), plan, u, v
+    if int(np.abs(stats[:, F["status"]]).max()) != 0:
+        raise SystemExit("solver reported status %s" % stats[:, F["status"]])
+    return per, stats, t_start.elapsed_time(t_end), int(cost.item())
+
+
+def bench_assign(args, C, workload, cpu_samples):
+    import torch
+
+    from paper_2005_01182_amd import otkm as ot
+    n = C.shape[0]
+    dC = torch.from_numpy(C).cuda()
+    stream = torch.cuda.Stream()
+    log("%s: warmup %d, steps %d" % (workload, args.warmup, args.steps))
+    per, stats, total, cost = solve_series(ot, torch, dC, n, args.steps, args.warmup, 0, stream, block=args.block)
+    b = alg_bytes(stats, [n] * len(stats))
+    out = base_line(args, args.steps / (total / 1e3), "solves/s", total / args.steps,
+                    {"workload": workload, "n": n, "method": "batched KM (trees from every free row)",
+                     "optimal_cost": cost, "block": args.block or "default"})
+    out["roofline"] = roofline(float(np.mean(b)), float(np.mean(per)) / 1e3)
+    plain_steps = max(1, min(args.plain_steps, args.steps))
+    log("plain KM (one tree at a time): %d solves" % plain_steps)
+    pper, pstats, ptotal, pcost = solve_series(ot, torch, dC, n, plain_steps, 1, 1, stream, block=args.block)
+    if pcost != cost:
+        raise SystemExit("plain and batched costs differ: %d vs %d" % (pcost, cost))
+    out["latency_ms"] = {"batched_p50": pct(per, 50), "batched_p99": pct(per, 99),
+                         "plain_p50": pct(pper, 50), "plain_p99": pct(pper, 99)}
+    out["plain_km"] = {"solves_per_s": round(plain_steps / (ptotal / 1e3), 4), **counters(pstats)}
+    out["solver_counters"] = {**counters(stats), "alg_bytes_per_solve": int(b[0])}
+    if args.phase_timers:
+        _, tst, _, _ = solve_series(ot, torch, dC, n, 1, 0, 0, stream, block=args.block, timers=True)
+        out["solver_counters"]["phase_ms_timed_run"] = {
+            k: round(float(tst[0, F["t_" + k + "_ns"]]) / 1e6, 3) for k in ("sweep", "select", "settle", "augment",
+                                                                          "refresh")}
+    if not args.skip_cpu:
+        import oracle
+        rate, done = cpu_rate(oracle.assign, cpu_samples, args.cpu_budget)
+        out["cpu_baseline"] = {"value": round(rate, 5), "unit": "solves/s", "cores": 1, "kind": "oracle",
+                               "sample": "%d solve(s) of the same instance (n=%d) by the single-threaded C "
+                                         "oracle (O(n^3) shortest augmenting path)" % (done, n)}
+    return out
 
 
 def bench_geometric(args):
+    from paper_2005_01182_amd import workloads as wl
+    C = wl.geometric_assignment(args.n, seed=0)
+    w = ("geometric assignment: circle vs square perimeter, sigma 0.02, C = rint(1e4 * distance) int32, "
+         "n = %d, seed 0" % args.n)
+    return bench_assign(args, C, w, [C] * 3)
+
+
+def bench_small(args):
+    from paper_2005_01182_amd import workloads as wl
+    C = wl.uniform_assignment(64, seed=0)
+    return bench_assign(args, C, "uniform assignment n = 64, costs U{0..1000}, seed 0", [C] * 200000)
+
+
+# ----------------------------------------------------------------------------- transport
+def bench_transport(args):
     import torch
 
     from paper_2005_01182_amd import otkm as ot
     from paper_2005_01182_amd import workloads as wl
-
-    n = args.n
-    C = wl.geometric_assignment(n, seed=0)
-    dC = torch.from_numpy(C).cuda()
+    C, r, c = wl.pixel_histogram_pair()
+    S = int(r.sum())
+    n, m = C.shape
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    dC, dr, dc = d(C), d(r), d(c)
+    X = torch.empty((n, m), dtype=torch.int32, device="cuda")
+    cost = torch.empty(1, dtype=torch.int64, device="cuda")
+    u = torch.empty(n, dtype=torch.int64, device="cuda")
+    v = torch.empty(m, dtype=torch.int64, device="cuda")
+    st = ot.stats_tensor(args.steps + args.warmup)
     stream = torch.cuda.Stream()
-    log("geometric n=%d: warmup %d, steps %d" % (n, args.warmup, args.steps))
-    per, stats, total, cost, plan, u, v = solve_series(ot, torch, dC, n, args.steps, args.warmup, 0, stream,
-                                                       block=args.block)
-    if int(np.abs(stats[:, 7]).max()) != 0:
-        raise SystemExit("solver reported status %s" % stats[:, 7])
-    # algorithmic bytes per solve: cost rows read in full (2n at init + frontier + re-sweeps)
-    # plus single entries re-read to refresh stale keys, 4 bytes each
-    rows = stats[:, 4].astype(np.float64)
-    gathers = stats[:, 5].astype(np.float64)
-    bytes_per = 4.0 * n * rows + 4.0 * gathers
-    per_s = np.asarray(per) / 1e3
-    achieved = float(np.mean(bytes_per) / np.mean(per_s) / 1e9)
-    value = args.steps / (total / 1e3)
-
-    phase = None
-    if args.phase_timers:
-        _, tstats, _, _, *_ = solve_series(ot, torch, dC, n, 1, 0, 0, stream, block=args.block, timers=True)
-        phase = {k: round(float(x) / 1e6, 3) for k, x in zip(("sweep", "select", "settle", "augment"), tstats[0, 8:12])}
-        phase["refresh_within_select"] = round(float(tstats[0, 14]) / 1e6, 3)
-    # plain KM (one tree at a time) on the same GPU for the batched-vs-plain comparison
-    plain_steps = max(1, min(args.plain_steps, args.steps))
-    log("plain KM: %d solves" % plain_steps)
-    pper, pstats, ptotal, pcost, *_ = solve_series(ot, torch, dC, n, plain_steps, 1, 1, stream, block=args.block)
-    if pcost != cost:
-        raise SystemExit("plain and batched costs differ: %d vs %d" % (pcost, cost))
-
-    out = {
-        "metric": "solves/s + achieved HBM GB/s at n=2048; p50/p99 latency batched vs plain",
-        "value": round(value, 3),
-        "unit": "solves/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(total / args.steps, 4),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "int64",
-        "data": "synthetic",
-        "config": {"workload": "geometric assignment: circle vs square perimeter, sigma 0.02, "
-                               "C = rint(1e4 * distance) int32, n = %d, seed 0" % n,
-                   "n": n, "method": "batched KM (all free rows grown at once)", "optimal_cost": cost,
-                   "block": args.block or "default"},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None},
-        "latency_ms": {"batched_p50": round(percentile(per, 50), 4), "batched_p99": round(percentile(per, 99), 4),
-                       "plain_p50": round(percentile(pper, 50), 4), "plain_p99": round(percentile(pper, 99), 4)},
-        "plain_km": {"solves_per_s": round(plain_steps / (ptotal / 1e3), 3),
-                     "levels": int(pstats[0, 0]), "rows_swept": int(pstats[0, 4])},
-        "solver_counters": {"levels": int(stats[0, 0]), "dual_adjusts": int(stats[0, 1]),
-                            "aug_events": int(stats[0, 2]), "rows_swept": int(stats[0, 4]),
-                            "gathers": int(stats[0, 5]), "resweeps": int(stats[0, 6]),
-                            "refreshes": int(stats[0, 12]), "refresh_cols": int(stats[0, 13]),
-                            "alg_bytes_per_solve": int(bytes_per[0]),
-                            "phase_ms_timed_run": phase},
-    }
+    for w in range(args.warmup):
+        ot.ot_transport_dev(dC, dr, dc, S, X, cost, u, v, st[w], stream=stream)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0.record(stream)
+    for k in range(args.steps):
+        ev[k][0].record(stream)
+        ot.ot_transport_dev(dC, dr, dc, S, X, cost, u, v, st[args.warmup + k], stream=stream)
+        ev[k][1].record(stream)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    per = [a.elapsed_time(b) for a, b in ev]
+    total = t0.elapsed_time(t1)
+    stats = st[args.warmup:].cpu().numpy()
+    if int(np.abs(stats[:, F["status"]]).max()) != 0:
+        raise SystemExit("transport status %s" % stats[:, F["status"]])
+    b = alg_bytes(stats, [S] * len(stats))
+    out = base_line(args, args.steps / (total / 1e3), "solves/s", total / args.steps,
+                    {"workload": "pixel-histogram transport: two 28x28 blob images (seeds 0, 1), mass 1024 each, "
+                                 "cost = squared grid distance, unit expansion to %dx%d" % (S, S),
+                     "bins": n, "units": S, "optimal_cost": int(cost.item())})
+    out["roofline"] = roofline(float(np.mean(b)), float(np.mean(per)) / 1e3)
+    out["latency_ms"] = {"p50": pct(per, 50), "p99": pct(per, 99)}
+    out["solver_counters"] = {**counters(stats), "alg_bytes_per_solve": int(b[0])}
     if not args.skip_cpu:
-        rate, done = cpu_oracle_rate([C] * 3, budget_s=args.cpu_budget)
+        import oracle
+        rate, done = cpu_rate(lambda _: oracle.transport(C, r, c), range(100), args.cpu_budget)
+        out["cpu_baseline"] = {"value": round(rate, 5), "unit": "solves/s", "cores": 1, "kind": "oracle",
+                               "sample": "%d solve(s) of the same instance by the single-threaded C oracle "
+                                         "(unit expansion + O(S^3) shortest augmenting path)" % done}
+    return out
+
+
+# ----------------------------------------------------------------------------- batch
+def bench_batch(args):
+    import torch
+
+    from paper_2005_01182_amd import otkm as ot
+    from paper_2005_01182_amd import workloads as wl
+    count = args.count
+    sizes = wl.embedding_sizes(count, seed=0)
+    log("generating %d embedding problems" % count)
+    t_gen = time.perf_counter()
+    Cs = [wl.embedding_problem(int(nk), 0, k) for k, nk in enumerate(sizes)]
+    log("generated in %.1f s" % (time.perf_counter() - t_gen))
+    ns = sizes.astype(np.int64)
+    coff = np.zeros(count, np.int64)
+    voff = np.zeros(count, np.int64)
+    coff[1:] = np.cumsum(ns * ns)[:-1]
+    voff[1:] = np.cumsum(ns)[:-1]
+    vtot = int(ns.sum())
+    flat = np.concatenate([C.reshape(-1) for C in Cs])
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    dC, dcoff, dvoff, dn = d(flat), d(coff), d(voff), d(sizes.astype(np.int32))
+    del flat
+    plan = torch.empty(vtot, dtype=torch.int32, device="cuda")
+    u = torch.empty(vtot, dtype=torch.int64, device="cuda")
+    v = torch.empty(vtot, dtype=torch.int64, device="cuda")
+    cost = torch.empty(count, dtype=torch.int64, device="cuda")
+    st = ot.stats_tensor(count)
+    if args.tune:
+        log("autotuning the size-class schedule")
+        ot.ot_schedule_tune(4)
+    t64, t256 = ot.ot_schedule_get()
+    classes = []   # (block, max_n, order tensor) longest first within each class
+    for lo, hi, block in ((0, t64, 64), (t64, t256, 256), (t256, 1 << 30, 512)):
+        idx = np.nonzero((sizes > lo) & (sizes <= hi))[0]
+        if len(idx) == 0:
+            continue
+        idx = idx[np.argsort(-sizes[idx], kind="stable")].astype(np.int32)
+        classes.append((block, int(sizes[idx].max()), d(idx)))
+    stream = torch.cuda.Stream()
+
+    def launch():
+        for block, max_n, order in classes:
+            ot.ot_assign_batch_dev(count, max_n, dC, dcoff, dn, dvoff, plan, cost, u, v, st, order=order,
+                                   block=block, stream=stream)
+
+    with torch.cuda.stream(stream):
+        launch()  # eager run sizes the workspaces
+    stream.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=stream):
+        launch()
+    for _ in range(args.warmup):
+        g.replay()
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    with torch.cuda.stream(stream):
+        for k in range(args.steps):
+            ev[k][0].record(stream)
+            g.replay()
+            ev[k][1].record(stream)
+    torch.cuda.synchronize()
+    per = [a.elapsed_time(b) for a, b in ev]
+    total = sum(per)
+    stats = st.cpu().numpy()
+    if int(np.abs(stats[:, F["status"]]).max()) != 0:
+        raise SystemExit("batch status nonzero")
+    b = alg_bytes(stats, sizes)
+    value = count * args.steps / (total / 1e3)
+    out = base_line(args, value, "solves/s", total / args.steps,
+                    {"workload": "batched embedding assignments: %d problems, n ~ U{16..512}, 300-d N(0,1) "
+                                 "vectors with 10%% near-duplicates per side, C = rint(1e3 * distance) int32, "
+                                 "seed 0" % count,
+                     "problems": count, "sum_n2": int((ns * ns).sum()),
+                     "schedule": {"wave_max_n": t64, "wg256_max_n": t256},
+                     "classes": [[blk, mx, int(o.numel())] for blk, mx, o in classes],
+                     "launch": "hipGraph replay of one persistent kernel per size class"})
+    out["roofline"] = roofline(float(b.sum()), float(np.mean(per)) / 1e3)
+    out["batch_latency_ms"] = {"p50": pct(per, 50), "p99": pct(per, 99)}
+    # plain comparison: one launch per instance, sequential on one stream, over a prefix of the batch
+    k_plain = min(args.plain_count, count)
+    pp = torch.empty(int(sizes[:k_plain].max()), dtype=torch.int32, device="cuda")
+    pc = torch.empty(1, dtype=torch.int64, device="cuda")
+    views = [dC[int(coff[k]):int(coff[k] + ns[k] * ns[k])].view(int(ns[k]), int(ns[k])) for k in range(k_plain)]
+    for k in range(min(8, k_plain)):
+        ot.ot_assign_dev(views[k], pp, pc, stream=stream)
+    torch.cuda.synchronize()
+    pev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(k_plain)]
+    for k in range(k_plain):
+        pev[k][0].record(stream)
+        ot.ot_assign_dev(views[k], pp, pc, stream=stream)
+        pev[k][1].record(stream)
+    torch.cuda.synchronize()
+    pl = [a.elapsed_time(b) for a, b in pev]
+    out["plain_per_instance"] = {"instances": k_plain, "solves_per_s": round(k_plain / (sum(pl) / 1e3), 3),
+                                 "latency_ms_p50": pct(pl, 50), "latency_ms_p99": pct(pl, 99)}
+    out["solver_counters"] = {"levels_total": int(stats[:, F["levels"]].sum()),
+                              "rows_swept_total": int(stats[:, F["rows_swept"]].sum()),
+                              "alg_bytes_per_launch": int(b.sum())}
+    if not args.skip_cpu:
+        import oracle
+        rate, done = cpu_rate(oracle.assign, Cs, args.cpu_budget)
         out["cpu_baseline"] = {"value": round(rate, 4), "unit": "solves/s", "cores": 1, "kind": "oracle",
-                               "sample": "%d solve(s) of the same n=%d instance, single-threaded C oracle "
-                                         "(O(n^3) shortest augmenting path)" % (done, n)}
+                               "sample": "first %d problems of the batch (sizes as drawn), single-threaded C "
+                                         "oracle" % done}
     return out
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--mode", default="geometric", choices=["geometric"])
+    ap.add_argument("--steps", type=int, default=None)
+    ap.add_argument("--warmup", type=int, default=None)
+    ap.add_argument("--mode", default="geometric", choices=["geometric", "small", "transport", "batch", "serve"])
     ap.add_argument("--n", type=int, default=2048)
+    ap.add_argument("--count", type=int, default=4096, help="batch mode: number of problems")
     ap.add_argument("--plain-steps", type=int, default=3)
+    ap.add_argument("--plain-count", type=int, default=256, help="batch mode: instances in the per-launch comparison")
     ap.add_argument("--skip-cpu", action="store_true")
-    ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--block", type=int, default=0, help="workgroup width override (0 = library default)")
+    ap.add_argument("--tune", action="store_true", help="batch mode: run the size-class autotuner first")
     ap.add_argument("--phase-timers", action="store_true", help="one extra solve with device phase timers")
+    ap.add_argument("--duration", type=float, default=5.0, help="serve mode: seconds of the request stream")
     args = ap.parse_args()
+    defaults = {"geometric": (20, 3), "small": (2000, 50), "transport": (50, 5), "batch": (5, 1), "serve": (1, 0)}
+    if args.steps is None:
+        args.steps = defaults[args.mode][0]
+    if args.warmup is None:
+        args.warmup = defaults[args.mode][1]
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU: instances are independent, so a multi-GPU run would only "
-              "shard them; run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU: every workload here is a single instance or a set of independent "
+              "instances, so more GPUs would only shard the instances; run with --gpus 1", file=sys.stderr)
         raise SystemExit(2)
     import torch
     if not torch.cuda.is_available():
         raise SystemExit("no GPU visible")
     from paper_2005_01182_amd import otkm
     otkm.load()
-    out = bench_geometric(args)
+    if args.mode == "serve":
+        from paper_2005_01182_amd import serve
+        out = serve.bench(args)
+    else:
+        out = {"geometric": bench_geometric, "small": bench_small, "transport": bench_transport,
+               "batch": bench_batch}[args.mode](args)
     print(json.dumps(out), flush=True)
 
 

@@ -160,16 +160,18 @@ int ot_assign_dev(const int32_t *dC, int32_t n, int32_t ld, const ot_options *op
 
 /* Batch on device memory.  Instance k: cost matrix at dC + coff[k] (dense,
  * ld = n[k]), plan/u/v at dplan/du/dv + voff[k]; dcost [count];
- * dstats [count] (may be NULL).  coff, voff, n are DEVICE arrays [count];
- * order is a device array [count] giving the processing order (longest
- * first is best; NULL = index order).  block selects the workgroup width
- * (64, 256 or 1024; 0 = from max_n via the schedule); max_n bounds every n[k].
- * The launch uses a device queue head that the call resets with a kernel, so
+ * dstats [count] (may be NULL).  coff, voff, n are DEVICE arrays [count].
+ * order (device, may be NULL) lists the nq instances this launch solves, in
+ * processing order (longest first is best); NULL solves all count instances
+ * in index order.  block selects the workgroup width (64, 256, 512 or 1024;
+ * 0 = from max_n via the schedule); max_n bounds n[k] of every queued
+ * instance.  Several launches (for example one per size class) may share the
+ * same buffers.  The launch resets its device queue head with a kernel, so
  * the call may be captured into a hipGraph and replayed. */
 int ot_assign_batch_dev(int32_t count, int32_t max_n, const int32_t *dC, const int64_t *coff,
-                        const int32_t *n, const int64_t *voff, const int32_t *order, int32_t block,
-                        int32_t *dplan, int64_t *dcost, int64_t *du, int64_t *dv, ot_stats *dstats,
-                        void *stream);
+                        const int32_t *n, const int64_t *voff, const int32_t *order, int32_t nq,
+                        int32_t block, int32_t *dplan, int64_t *dcost, int64_t *du, int64_t *dv,
+                        ot_stats *dstats, void *stream);
 
 /* Integer transport on device memory (same semantics as ot_transport).
  * dC [n*m], dr [n], dc [m]; dX [n*m]; dcost [1]; du [n]; dv [m];

@@ -57,7 +57,7 @@ __host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~size_t(
 __host__ __device__ inline int gather_cap(int n) { return n / 16 < 32 ? 32 : n / 16; }
 
 struct LdsLayout {
-  size_t hrow, mrow, mcol, rtree, fst, fl0, fl1, alive, gcol, gv, gk1, gk2, gt1, gt2, red, ctl, total;
+  size_t hrow, mrow, mcol, rtree, par, fst, fl0, fl1, alive, gcol, gv, gk1, gk2, gt1, gt2, red, ctl, total;
 };
 
 // Byte offsets of every LDS array for an instance of size n (host and device).
@@ -69,6 +69,7 @@ __host__ __device__ inline LdsLayout lds_layout(int n) {
   L.mrow = o;  o = align16(o + 4 * N);
   L.mcol = o;  o = align16(o + 4 * N);
   L.rtree = o; o = align16(o + 4 * N);
+  L.par = o;   o = align16(o + 4 * N);
   L.fst = o;   o = align16(o + 4 * N);
   L.fl0 = o;   o = align16(o + 4 * N);
   L.fl1 = o;   o = align16(o + 4 * N);
@@ -85,9 +86,9 @@ __host__ __device__ inline LdsLayout lds_layout(int n) {
   return L;
 }
 
-// Global scratch per workgroup: parent row of each reached column, list of
-// trees that augment this step, smallest free column reached per tree.
-__host__ __device__ inline size_t ws_ints(int n) { return 3 * (size_t)n; }
+// Global scratch per workgroup: list of trees that augment this step and the
+// smallest free column reached per tree (both touched only at augmentations).
+__host__ __device__ inline size_t ws_ints(int n) { return 2 * (size_t)n; }
 
 struct Problem {
   const int32_t *C;   // n x n, row stride ld
@@ -185,13 +186,13 @@ struct Engine {
   int n, ld;
   // LDS
   int64_t *hrow;
-  int32_t *mrow, *mcol, *rtree, *fst, *fl0, *fl1, *gcol, *gt1, *gt2, *ctl;
+  int32_t *mrow, *mcol, *rtree, *par, *fst, *fl0, *fl1, *gcol, *gt1, *gt2, *ctl;
   uint8_t *alive;
   int64_t *gv;
   uint64_t *gk1, *gk2, *red;
   int gcap;
   // global scratch
-  int32_t *par, *auglist, *bend;
+  int32_t *auglist, *bend;
   // per-column registers
   uint64_t k1[CPT], k2[CPT];
   int t1[CPT], t2[CPT], ctree[CPT];
@@ -436,6 +437,7 @@ struct Engine {
     mrow = (int32_t *)(smem + L.mrow);
     mcol = (int32_t *)(smem + L.mcol);
     rtree = (int32_t *)(smem + L.rtree);
+    par = (int32_t *)(smem + L.par);
     fst = (int32_t *)(smem + L.fst);
     fl0 = (int32_t *)(smem + L.fl0);
     fl1 = (int32_t *)(smem + L.fl1);
@@ -449,9 +451,8 @@ struct Engine {
     red = (uint64_t *)(smem + L.red);
     ctl = (int32_t *)(smem + L.ctl);
     gcap = gather_cap(n);
-    par = P.ws;
-    auglist = P.ws + n;
-    bend = P.ws + 2 * (size_t)n;
+    auglist = P.ws;
+    bend = P.ws + n;
 
     const int K = (P.max_paths <= 0 || P.max_paths > n) ? n : P.max_paths;
     int64_t st_levels = 0, st_dual = 0, st_aug = 0, st_paths = 0, st_rows = 0, st_gath = 0, st_resw = 0;

@@ -262,10 +262,12 @@ int ot_assign_dev(const int32_t *dC, int32_t n, int32_t ld, const ot_options *op
 }
 
 int ot_assign_batch_dev(int32_t count, int32_t max_n, const int32_t *dC, const int64_t *coff, const int32_t *n,
-                        const int64_t *voff, const int32_t *order, int32_t block, int32_t *dplan, int64_t *dcost,
-                        int64_t *du, int64_t *dv, ot_stats *dstats, void *stream) {
+                        const int64_t *voff, const int32_t *order, int32_t nq, int32_t block, int32_t *dplan,
+                        int64_t *dcost, int64_t *du, int64_t *dv, ot_stats *dstats, void *stream) {
   if (count < 0 || !dC || !coff || !n || !voff || !dplan || !dcost || max_n <= 0) return OT_EINVAL;
-  if (count == 0) return OT_OK;
+  if (!order) nq = count;
+  if (nq < 0 || nq > count) return OT_EINVAL;
+  if (count == 0 || nq == 0) return OT_OK;
   if (max_n > OT_MAX_N) return OT_ETOOBIG;
   std::lock_guard<std::mutex> lk(g_mu);
   int rc = init_locked();
@@ -275,7 +277,7 @@ int ot_assign_batch_dev(int32_t count, int32_t max_n, const int32_t *dC, const i
   hipStream_t s = stream ? (hipStream_t)stream : g_stream;
   const int occ = batch_occupancy(block, max_n);
   if (occ <= 0) return OT_ETOOBIG;
-  const int grid = std::max(1, std::min<int>(count, occ * g_cus));
+  const int grid = std::max(1, std::min<int>(nq, occ * g_cus));
   int err = OT_OK;
   auto *head = (int32_t *)stream_ws(s, 1, 256, &err);
   auto *dws = (int32_t *)stream_ws(s, 2, 4 * ws_ints(max_n) * (size_t)grid, &err);
@@ -284,7 +286,7 @@ int ot_assign_batch_dev(int32_t count, int32_t max_n, const int32_t *dC, const i
   if (e != hipSuccess) return map_hip(e);
   BatchArgs A;
   A.C = dC; A.coff = coff; A.n = n; A.voff = voff; A.order = order;
-  A.count = count; A.nq = count; A.max_n = max_n; A.max_paths = 0;
+  A.count = count; A.nq = nq; A.max_n = max_n; A.max_paths = 0;
   A.plan = dplan; A.cost = dcost; A.u = du; A.v = dv; A.stats = dstats; A.ws = dws; A.head = head;
   return map_hip(launch_assign_batch(A, block, grid, s));
 }

@@ -83,7 +83,8 @@ def load():
         lib.ot_transport.argtypes = [_VP, _VP, _VP, _I32, _I32, _VP, _VP, _VP, _VP]
         lib.ot_assign_batch.argtypes = [_I32, _VP, _VP, _VP, _VP, _VP, _VP, _VP]
         lib.ot_assign_dev.argtypes = [_VP, _I32, _I32, _VP, _VP, _VP, _VP, _VP, _VP, _VP]
-        lib.ot_assign_batch_dev.argtypes = [_I32, _I32, _VP, _VP, _VP, _VP, _VP, _I32, _VP, _VP, _VP, _VP, _VP, _VP]
+        lib.ot_assign_batch_dev.argtypes = [_I32, _I32, _VP, _VP, _VP, _VP, _VP, _I32, _I32, _VP, _VP, _VP, _VP, _VP,
+                                            _VP]
         lib.ot_transport_dev.argtypes = [_VP, _VP, _VP, _I32, _I32, _I32, _VP, _VP, _VP, _VP, _VP, _VP]
         lib.ot_schedule_get.argtypes = [_VP, _VP]
         lib.ot_schedule_set.argtypes = [_I32, _I32]
@@ -238,10 +239,16 @@ def ot_assign_dev(C, plan, cost, u=None, v=None, stats=None, max_paths=0, block=
 
 
 def ot_assign_batch_dev(count, max_n, C, coff, n, voff, plan, cost, u=None, v=None, stats=None, order=None,
-                        block=0, stream=None):
-    """Queue a persistent batch on device tensors (asynchronous on `stream`)."""
+                        block=0, stream=None, nq=None):
+    """Queue a persistent batch on device tensors (asynchronous on `stream`).
+
+    `order` (device int32) lists the `nq` instances to solve (default: all of it).
+    """
+    if order is not None and nq is None:
+        nq = int(order.numel())
     rc = load().ot_assign_batch_dev(int(count), int(max_n), _tp(C), _tp(coff), _tp(n), _tp(voff), _tp(order),
-                                    int(block), _tp(plan), _tp(cost), _tp(u), _tp(v), _tp(stats), _stream(stream))
+                                    int(nq or 0), int(block), _tp(plan), _tp(cost), _tp(u), _tp(v), _tp(stats),
+                                    _stream(stream))
     _check(rc, "ot_assign_batch_dev")
 
 
