@@ -183,6 +183,63 @@ int ot_transport_dev(const int32_t *dC, const int32_t *dr, const int32_t *dc, in
                      ot_stats *dstats, void *stream);
 
 /* ------------------------------------------------------------------------ */
+/* Serving: continuous batching of assignment requests                       */
+/* ------------------------------------------------------------------------ */
+/* Each request is an assignment between n source and n target points on the
+ * integer grid; its cost matrix C_ij = round(sqrt((x_i - x'_j)^2 + (y_i - y'_j)^2))
+ * (exact integer rounding, ties cannot occur) is built on the device, so only
+ * the points cross PCIe.  A server thread admits queued requests in arrival
+ * order while the device bytes of the admitted ones (4 n^2 + 64 n per
+ * request) stay within hbm_budget_bytes and a slot is free, and launches the
+ * newly admitted requests of each size class as one persistent batch on that
+ * class's stream.  Each request completes on its own (the device releases a
+ * completion flag per request), not when its whole batch does.
+ * Requests that arrive while others run are admitted as memory and slots
+ * free up, so their work overlaps on the device.  Results are identical to
+ * a solve of the same request alone (the solver is deterministic). */
+typedef struct ot_server ot_server;
+
+/* Device cost builder used by the server, exposed on its own:
+ * dC[i*n + j] = round(sqrt((src_i - dst_j)^2)) for int32 grid points
+ * dsrc, ddst [2n] (x, y pairs), exact integer rounding.  Asynchronous on stream. */
+int ot_grid_cost_dev(const int32_t *dsrc, const int32_t *ddst, int32_t n, int32_t *dC, void *stream);
+
+typedef struct ot_serve_cfg {
+    int64_t hbm_budget_bytes;  /* device bytes admitted requests may hold; 0 = 8 GiB */
+    int32_t max_inflight;      /* request slots (1..1024); 0 = 256; 1 = one request at a time */
+    int32_t streams;           /* 0 or 4: one stream per size class (n <= 128, 512, 2048, 4096) */
+    int32_t max_n;             /* largest n accepted (<= OT_MAX_N); 0 = OT_MAX_N */
+    int32_t reserved[5];       /* must be zero */
+} ot_serve_cfg;
+
+typedef struct ot_result {
+    int32_t *plan;             /* caller buffers [n] filled on completion (each may be NULL) */
+    int64_t *u, *v;
+    int64_t cost;              /* out */
+    int32_t status;            /* out: ot_status of the solve */
+    int32_t n;                 /* out */
+    double t_submit, t_admit, t_done;  /* out: seconds on the server's monotonic clock */
+} ot_result;
+
+typedef struct ot_serve_counters {
+    int64_t submitted, admitted, completed, groups, peak_inflight_bytes, peak_inflight;
+} ot_serve_counters;
+
+/* Start a server on the current device.  Returns OT_OK and *out, or an error. */
+int ot_serve_open(ot_server **out, const ot_serve_cfg *cfg);
+/* Queue a request; src, dst are host int32 [2n] (x, y pairs), copied before
+ * return.  *req_id receives an id unique within the server. */
+int ot_serve_submit(ot_server *s, const int32_t *src, const int32_t *dst, int32_t n, uint64_t *req_id);
+/* Wait up to timeout_us (< 0: forever) for request req_id.  OT_OK and *out
+ * filled when it completed (the result is then released); 1 when still
+ * pending; OT_EINVAL for an unknown id. */
+int ot_serve_poll(ot_server *s, uint64_t req_id, ot_result *out, int32_t timeout_us);
+/* Counters since open; now = the server clock. */
+int ot_serve_stats(ot_server *s, ot_serve_counters *out, double *now);
+/* Stop the server after in-flight groups drain; frees its resources. */
+int ot_serve_close(ot_server *s);
+
+/* ------------------------------------------------------------------------ */
 /* Size-class schedule (autotuner)                                           */
 /* ------------------------------------------------------------------------ */
 

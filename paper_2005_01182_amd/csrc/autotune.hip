@@ -27,7 +27,7 @@ float time_batch(int block, int n, int count, int32_t *dC, int64_t *dcoff, int32
   BatchArgs A;
   A.C = dC; A.coff = dcoff; A.n = dn; A.voff = dvoff; A.order = nullptr;
   A.count = count; A.nq = count; A.max_n = n; A.max_paths = 0;
-  A.plan = dplan; A.cost = dcost; A.u = nullptr; A.v = nullptr; A.stats = nullptr; A.ws = dws; A.head = head;
+  A.plan = dplan; A.cost = dcost; A.u = nullptr; A.v = nullptr; A.stats = nullptr; A.ws = dws; A.head = head; A.done = nullptr; A.tag = 0;
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess) return -1.f;
   if (hipEventCreate(&e1) != hipSuccess) { hipEventDestroy(e0); return -1.f; }

@@ -61,6 +61,13 @@ __global__ __launch_bounds__(BLOCK) void k_assign_batch(BatchArgs A) {
     P.ws = ws;
     Engine<BLOCK, CPT> E;
     E.run(P, smem);
+    if (A.done) {
+      // outputs may live in host memory: make every thread's writes visible
+      // system-wide before the completion flag is released
+      __threadfence_system();
+      __syncthreads();
+      if (threadIdx.x == 0) __hip_atomic_store(&A.done[k], A.tag, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
     __syncthreads();
   }
 }

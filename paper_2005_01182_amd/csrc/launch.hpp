@@ -22,6 +22,8 @@ struct BatchArgs {
   ot_stats *stats;
   int32_t *ws;            // grid * ws_ints(max_n)
   int32_t *head;          // queue head (reset to 0 before the launch)
+  int32_t *done;          // [count] or null: done[k] = tag once instance k's outputs are visible to the host
+  int32_t tag;
 };
 
 struct TransportArgs {

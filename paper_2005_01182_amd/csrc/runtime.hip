@@ -287,7 +287,7 @@ int ot_assign_batch_dev(int32_t count, int32_t max_n, const int32_t *dC, const i
   BatchArgs A;
   A.C = dC; A.coff = coff; A.n = n; A.voff = voff; A.order = order;
   A.count = count; A.nq = nq; A.max_n = max_n; A.max_paths = 0;
-  A.plan = dplan; A.cost = dcost; A.u = du; A.v = dv; A.stats = dstats; A.ws = dws; A.head = head;
+  A.plan = dplan; A.cost = dcost; A.u = du; A.v = dv; A.stats = dstats; A.ws = dws; A.head = head; A.done = nullptr; A.tag = 0;
   return map_hip(launch_assign_batch(A, block, grid, s));
 }
 
@@ -361,7 +361,7 @@ int ot_assign_batch(int32_t count, const int32_t *const *C, const int32_t *n, in
     BatchArgs A;
     A.C = dC; A.coff = dcoff; A.n = dn; A.voff = dvoff; A.order = dorder + spans[ci].first;
     A.count = count; A.nq = spans[ci].second; A.max_n = max_n; A.max_paths = 0;
-    A.plan = dplan; A.cost = dcost; A.u = du; A.v = dv; A.stats = dstats; A.ws = dws; A.head = head + ci;
+    A.plan = dplan; A.cost = dcost; A.u = du; A.v = dv; A.stats = dstats; A.ws = dws; A.head = head + ci; A.done = nullptr; A.tag = 0;
     if ((e = launch_assign_batch(A, block, grid, s)) != hipSuccess) return map_hip(e);
     ++ci;
   }

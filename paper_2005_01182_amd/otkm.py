@@ -25,6 +25,7 @@ EXPORTS = [
     "ot_strerror", "ot_init", "ot_assign", "ot_assign_ex", "ot_transport", "ot_assign_batch",
     "ot_assign_dev", "ot_assign_batch_dev", "ot_transport_dev",
     "ot_schedule_get", "ot_schedule_set", "ot_schedule_tune",
+    "ot_grid_cost_dev", "ot_serve_open", "ot_serve_submit", "ot_serve_poll", "ot_serve_stats", "ot_serve_close",
 ]
 
 
@@ -47,6 +48,25 @@ class ot_options(ctypes.Structure):
 
 
 OT_FLAG_PHASE_TIMERS = 1
+
+
+class ot_serve_cfg(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_int64), ("max_inflight", ctypes.c_int32),
+                ("streams", ctypes.c_int32), ("max_n", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
+
+
+class ot_result(ctypes.Structure):
+    _fields_ = [("plan", ctypes.c_void_p), ("u", ctypes.c_void_p), ("v", ctypes.c_void_p),
+                ("cost", ctypes.c_int64), ("status", ctypes.c_int32), ("n", ctypes.c_int32),
+                ("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double), ("t_done", ctypes.c_double)]
+
+
+class ot_serve_counters(ctypes.Structure):
+    _fields_ = [(name, ctypes.c_int64) for name in
+                ("submitted", "admitted", "completed", "groups", "peak_inflight_bytes", "peak_inflight")]
+
+    def as_dict(self):
+        return {name: int(getattr(self, name)) for name, _ in self._fields_}
 
 
 class OtError(RuntimeError):
@@ -89,6 +109,12 @@ def load():
         lib.ot_schedule_get.argtypes = [_VP, _VP]
         lib.ot_schedule_set.argtypes = [_I32, _I32]
         lib.ot_schedule_tune.argtypes = [_I32]
+        lib.ot_grid_cost_dev.argtypes = [_VP, _VP, _I32, _VP, _VP]
+        lib.ot_serve_open.argtypes = [ctypes.POINTER(ctypes.c_void_p), _VP]
+        lib.ot_serve_submit.argtypes = [_VP, _VP, _VP, _I32, ctypes.POINTER(ctypes.c_uint64)]
+        lib.ot_serve_poll.argtypes = [_VP, ctypes.c_uint64, _VP, _I32]
+        lib.ot_serve_stats.argtypes = [_VP, _VP, ctypes.POINTER(ctypes.c_double)]
+        lib.ot_serve_close.argtypes = [_VP]
         for name in EXPORTS:
             if name != "ot_strerror":
                 getattr(lib, name).restype = ctypes.c_int
@@ -258,3 +284,67 @@ def ot_transport_dev(C, r, c, S, X, cost, u, v, stats=None, stream=None):
     rc = load().ot_transport_dev(_tp(C), _tp(r), _tp(c), n, m, int(S), _tp(X), _tp(cost), _tp(u), _tp(v),
                                  _tp(stats), _stream(stream))
     _check(rc, "ot_transport_dev")
+
+
+def ot_grid_cost_dev(src, dst, C, stream=None):
+    """Build C[i, j] = round(|src_i - dst_j|) on the device (int32 point tensors [n, 2])."""
+    n = int(src.shape[0])
+    _check(load().ot_grid_cost_dev(_tp(src), _tp(dst), n, _tp(C), _stream(stream)), "ot_grid_cost_dev")
+
+
+# ----------------------------------------------------------------------------- serving
+class Server:
+    """Continuous-batching server (ot_serve_* calls)."""
+
+    def __init__(self, hbm_budget_bytes=0, max_inflight=0, max_n=0):
+        cfg = ot_serve_cfg()
+        cfg.hbm_budget_bytes = int(hbm_budget_bytes)
+        cfg.max_inflight = int(max_inflight)
+        cfg.max_n = int(max_n)
+        h = ctypes.c_void_p()
+        _check(load().ot_serve_open(ctypes.byref(h), ctypes.byref(cfg)), "ot_serve_open")
+        self._h = h
+
+    def submit(self, src, dst) -> int:
+        src = np.ascontiguousarray(src, dtype=np.int32)
+        dst = np.ascontiguousarray(dst, dtype=np.int32)
+        if src.shape != dst.shape or src.ndim != 2 or src.shape[1] != 2:
+            raise ValueError("points must be two (n, 2) int32 arrays")
+        rid = ctypes.c_uint64(0)
+        _check(load().ot_serve_submit(self._h, _p(src), _p(dst), int(src.shape[0]), ctypes.byref(rid)),
+               "ot_serve_submit")
+        return int(rid.value)
+
+    def poll(self, rid, n, timeout_us=-1, want_arrays=True):
+        """Result dict when done, None while pending."""
+        res = ot_result()
+        plan = np.empty(n, np.int32) if want_arrays else None
+        u = np.empty(n, np.int64) if want_arrays else None
+        v = np.empty(n, np.int64) if want_arrays else None
+        res.plan = plan.ctypes.data if want_arrays else None
+        res.u = u.ctypes.data if want_arrays else None
+        res.v = v.ctypes.data if want_arrays else None
+        rc = load().ot_serve_poll(self._h, ctypes.c_uint64(rid), ctypes.byref(res), int(timeout_us))
+        if rc == 1:
+            return None
+        _check(rc, "ot_serve_poll")
+        return {"plan": plan, "u": u, "v": v, "cost": int(res.cost), "status": int(res.status), "n": int(res.n),
+                "t_submit": res.t_submit, "t_admit": res.t_admit, "t_done": res.t_done}
+
+    def stats(self):
+        c = ot_serve_counters()
+        now = ctypes.c_double(0)
+        _check(load().ot_serve_stats(self._h, ctypes.byref(c), ctypes.byref(now)), "ot_serve_stats")
+        return c.as_dict(), float(now.value)
+
+    def close(self):
+        if self._h:
+            rc = load().ot_serve_close(self._h)
+            self._h = None
+            _check(rc, "ot_serve_close")
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

@@ -75,6 +75,15 @@ VALIDATION = textwrap.dedent(r"""
     out["schedule"] = ot.ot_schedule_get()
     ot.ot_schedule_set(100, 900); out["schedule_set"] = ot.ot_schedule_get()
     out["schedule_bad"] = code(ot.ot_schedule_set, -1, 5)
+    def serve_code(**kw):
+        try:
+            ot.Server(**kw).close(); return 0
+        except ot.OtError as e:
+            return e.code
+    out["serve_bad_slots"] = serve_code(max_inflight=5000)
+    out["serve_bad_maxn"] = serve_code(max_n=5000)
+    out["serve_budget_too_small"] = serve_code(hbm_budget_bytes=1000)
+    out["serve_nodev"] = serve_code()
     print(repr(out))
 """)
 
@@ -113,3 +122,7 @@ def test_validation_codes(codes):
     assert codes["schedule"] == (128, 1024)
     assert codes["schedule_set"] == (100, 900)
     assert codes["schedule_bad"] == -1
+    assert codes["serve_bad_slots"] == -1
+    assert codes["serve_bad_maxn"] == -1
+    assert codes["serve_budget_too_small"] == -5
+    assert codes["serve_nodev"] == -8
