@@ -76,6 +76,47 @@ def base_line(args, value, unit, ms_per_step, config):
             "scaling": "weak", "vs_baseline": None, "dtype": "int64", "data": "synthetic", "config": config}
 
 
+def traffic_for(tag):
+    """Measured HBM bytes per solve of the single-instance kernel, from the committed
+    rocprofv3 counter summary for this size, or None when there is none or when the
+    kernel sources changed after the counters were taken."""
+    from paper_2005_01182_amd import profsum
+    path = os.path.join(ROOT, "profiles", "traffic_k_assign_one_%s.md" % tag)
+    rec = profsum.read_traffic(path)
+    if rec is None or rec.get("source_sha256") != profsum.kernel_source_sha():
+        return None
+    return int(rec["traffic_bytes_per_launch"])
+
+
+# ----------------------------------------------------------------------------- copy calibration
+def bench_copy(args):
+    """A plain streaming kernel of known size (dst = src + 1 over int32), for scaling
+    the FETCH_SIZE / WRITE_SIZE counters to bytes.  Not a solver workload."""
+    import torch
+    count = args.copy_mib << 18   # int32 elements
+    src = torch.zeros(count, dtype=torch.int32, device="cuda")
+    dst = torch.empty_like(src)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        for _ in range(args.warmup):
+            torch.add(src, 1, out=dst)
+        stream.synchronize()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+        for k in range(args.steps):
+            ev[k][0].record(stream)
+            torch.add(src, 1, out=dst)
+            ev[k][1].record(stream)
+    torch.cuda.synchronize()
+    per = [a.elapsed_time(b) for a, b in ev]
+    nbytes = 2 * 4 * count
+    out = base_line(args, nbytes / (float(np.mean(per)) / 1e3) / 1e9, "GB/s", float(np.mean(per)),
+                    {"workload": "calibration copy: dst = src + 1, %d MiB int32 read + %d MiB written" %
+                                 (args.copy_mib, args.copy_mib),
+                     "bytes_read_per_launch": 4 * count, "bytes_written_per_launch": 4 * count})
+    out["metric"] = "copy bandwidth (counter calibration)"
+    return out
+
+
 # ----------------------------------------------------------------------------- single solves
 def solve_series(ot, torch, dC, n, steps, warmup, max_paths, stream, block=0, timers=False):
     """Warmup + timed solves on `stream`; returns per-solve ms (events), stats, total ms, cost."""
@@ -106,7 +147,7 @@ def solve_series(ot, torch, dC, n, steps, warmup, max_paths, stream, block=0, ti
     return per, stats, t_start.elapsed_time(t_end), int(cost.item())
 
 
-def bench_assign(args, C, workload, cpu_samples):
+def bench_assign(args, C, workload, cpu_samples, tag):
     import torch
 
     from paper_2005_01182_amd import otkm as ot
@@ -120,14 +161,16 @@ def bench_assign(args, C, workload, cpu_samples):
                     {"workload": workload, "n": n, "method": "batched KM (trees from every free row)",
                      "optimal_cost": cost, "block": args.block or "default"})
     out["roofline"] = roofline(float(np.mean(b)), float(np.mean(per)) / 1e3)
-    plain_steps = max(1, min(args.plain_steps, args.steps))
-    log("plain KM (one tree at a time): %d solves" % plain_steps)
-    pper, pstats, ptotal, pcost = solve_series(ot, torch, dC, n, plain_steps, 1, 1, stream, block=args.block)
-    if pcost != cost:
-        raise SystemExit("plain and batched costs differ: %d vs %d" % (pcost, cost))
-    out["latency_ms"] = {"batched_p50": pct(per, 50), "batched_p99": pct(per, 99),
-                         "plain_p50": pct(pper, 50), "plain_p99": pct(pper, 99)}
-    out["plain_km"] = {"solves_per_s": round(plain_steps / (ptotal / 1e3), 4), **counters(pstats)}
+    out["roofline"]["traffic"] = traffic_for(tag)
+    out["latency_ms"] = {"batched_p50": pct(per, 50), "batched_p99": pct(per, 99)}
+    plain_steps = min(args.plain_steps, args.steps)
+    if plain_steps > 0:
+        log("plain KM (one tree at a time): %d solves" % plain_steps)
+        pper, pstats, ptotal, pcost = solve_series(ot, torch, dC, n, plain_steps, 1, 1, stream, block=args.block)
+        if pcost != cost:
+            raise SystemExit("plain and batched costs differ: %d vs %d" % (pcost, cost))
+        out["latency_ms"].update(plain_p50=pct(pper, 50), plain_p99=pct(pper, 99))
+        out["plain_km"] = {"solves_per_s": round(plain_steps / (ptotal / 1e3), 4), **counters(pstats)}
     out["solver_counters"] = {**counters(stats), "alg_bytes_per_solve": int(b[0])}
     if args.phase_timers:
         _, tst, _, _ = solve_series(ot, torch, dC, n, 1, 0, 0, stream, block=args.block, timers=True)
@@ -148,13 +191,13 @@ def bench_geometric(args):
     C = wl.geometric_assignment(args.n, seed=0)
     w = ("geometric assignment: circle vs square perimeter, sigma 0.02, C = rint(1e4 * distance) int32, "
          "n = %d, seed 0" % args.n)
-    return bench_assign(args, C, w, [C] * 3)
+    return bench_assign(args, C, w, [C] * 3, "geometric_n%d" % args.n)
 
 
 def bench_small(args):
     from paper_2005_01182_amd import workloads as wl
     C = wl.uniform_assignment(64, seed=0)
-    return bench_assign(args, C, "uniform assignment n = 64, costs U{0..1000}, seed 0", [C] * 200000)
+    return bench_assign(args, C, "uniform assignment n = 64, costs U{0..1000}, seed 0", [C] * 200000, "uniform_n64")
 
 
 # ----------------------------------------------------------------------------- transport
@@ -320,7 +363,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
-    ap.add_argument("--mode", default="geometric", choices=["geometric", "small", "transport", "batch", "serve"])
+    ap.add_argument("--mode", default="geometric", choices=["geometric", "small", "transport", "batch", "serve",
+                                                             "copy"])
     ap.add_argument("--n", type=int, default=2048)
     ap.add_argument("--count", type=int, default=4096, help="batch mode: number of problems")
     ap.add_argument("--plain-steps", type=int, default=3)
@@ -331,8 +375,10 @@ def main():
     ap.add_argument("--tune", action="store_true", help="batch mode: run the size-class autotuner first")
     ap.add_argument("--phase-timers", action="store_true", help="one extra solve with device phase timers")
     ap.add_argument("--duration", type=float, default=5.0, help="serve mode: seconds of the request stream")
+    ap.add_argument("--copy-mib", type=int, default=1024, help="copy mode: MiB per buffer")
     args = ap.parse_args()
-    defaults = {"geometric": (20, 3), "small": (2000, 50), "transport": (50, 5), "batch": (5, 1), "serve": (1, 0)}
+    defaults = {"geometric": (20, 3), "small": (2000, 50), "transport": (50, 5), "batch": (5, 1), "serve": (1, 0),
+                "copy": (5, 2)}
     if args.steps is None:
         args.steps = defaults[args.mode][0]
     if args.warmup is None:
@@ -352,7 +398,7 @@ def main():
         out = serve.bench(args)
     else:
         out = {"geometric": bench_geometric, "small": bench_small, "transport": bench_transport,
-               "batch": bench_batch}[args.mode](args)
+               "batch": bench_batch, "copy": bench_copy}[args.mode](args)
     print(json.dumps(out), flush=True)
 
 

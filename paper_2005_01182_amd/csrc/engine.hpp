@@ -248,6 +248,7 @@ struct Engine {
   // below 2^30) every key value is below 2^32, so the test runs in 32-bit
   // modular arithmetic, which is exact there.  Returns rows used.
   static constexpr int U = CPT >= 8 ? 2 : 16 / CPT > 8 ? 8 : 16 / CPT;
+  static constexpr int GU = 8;  // forest rows in flight per lane when recomputing a stale column
   template <bool NARROW>
   __device__ __forceinline__ int sweep_t(const int32_t *list, int cnt) {
     int used = 0;
@@ -373,12 +374,12 @@ struct Engine {
         uint64_t a1 = kInf, a2 = kInf;
         int ta1 = -1, ta2 = -1;
         const int stride = 64 * wpc;
-        for (int f0 = slice * 64 + lane; f0 < nf; f0 += 4 * stride) {
-          int i[4], t[4];
-          int64_t h[4];
-          int32_t c[4];
+        for (int f0 = slice * 64 + lane; f0 < nf; f0 += GU * stride) {
+          int i[GU], t[GU];
+          int64_t h[GU];
+          int32_t c[GU];
 #pragma unroll
-          for (int q = 0; q < 4; ++q) {
+          for (int q = 0; q < GU; ++q) {
             const int f = f0 + q * stride;
             i[q] = f < nf ? fst[f] : 0;
             if ((unsigned)i[q] >= (unsigned)n) { fail(OT_EINTERNAL); i[q] = 0; }
@@ -386,9 +387,9 @@ struct Engine {
             h[q] = hrow[i[q]];
           }
 #pragma unroll
-          for (int q = 0; q < 4; ++q) c[q] = C[(size_t)i[q] * (size_t)ld + j];
+          for (int q = 0; q < GU; ++q) c[q] = C[(size_t)i[q] * (size_t)ld + j];
 #pragma unroll
-          for (int q = 0; q < 4; ++q) {
+          for (int q = 0; q < GU; ++q) {
             if (t[q] < 0) continue;
             int64_t val = (int64_t)c[q] - h[q] - v;
             if (val < 0) { fail(OT_EINTERNAL); val = 0; }
