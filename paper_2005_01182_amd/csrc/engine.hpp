@@ -93,6 +93,8 @@ __host__ __device__ inline size_t ws_ints(int n) { return 2 * (size_t)n; }
 struct Problem {
   const int32_t *C;   // n x n, row stride ld
   int n, ld;
+  const int32_t *CT;  // transpose of C (n x n, row stride n), or null; only read to refresh single columns
+
   int max_paths;      // 0 = all free rows
   int flags;          // OT_FLAG_* bits
   int32_t *plan;      // [n]
@@ -152,14 +154,17 @@ __device__ __forceinline__ int64_t wave_sum_i64(int64_t x) {
 // a1 = best key overall (tree ta1), a2 = best key among trees != ta1.
 __device__ __forceinline__ void top2_push(uint64_t &a1, int &ta1, uint64_t &a2, int &ta2, uint64_t c, int t) {
   // same tree as the best: only the best can improve; another tree: c may
-  // become the best (the old best moves to second) or the second.
+  // become the best (the old best moves to second) or the second.  a1 <= a2,
+  // so c < a1 implies c < a2 and the second changes exactly when c is from
+  // another tree and below a2.  Flat selects only (no divergent branches).
   const bool same = t == ta1, lt1 = c < a1, lt2 = c < a2;
-  const uint64_t n2 = same ? a2 : (lt1 ? a1 : (lt2 ? c : a2));
-  const int m2 = same ? ta2 : (lt1 ? ta1 : (lt2 ? t : ta2));
-  ta1 = (!same && lt1) ? t : ta1;
+  const bool ch2 = !same && lt2;
+  const uint64_t x = lt1 ? a1 : c;
+  const int tx = lt1 ? ta1 : t;
+  a2 = ch2 ? x : a2;
+  ta2 = ch2 ? tx : ta2;
   a1 = lt1 ? c : a1;
-  a2 = n2;
-  ta2 = m2;
+  ta1 = lt1 ? t : ta1;
 }
 
 // Merge two exact top-2 summaries (symmetric, so both butterfly partners agree).
@@ -183,6 +188,7 @@ struct Engine {
 
   // problem
   const int32_t *__restrict__ C;
+  const int32_t *__restrict__ CT;
   int n, ld;
   // LDS
   int64_t *hrow;
@@ -199,7 +205,9 @@ struct Engine {
   // v_j lies in [-R, R] and the level at which a column is reached in [0, R]
   // (R = max C - min C < 2^31), so both fit 32 bits.
   int32_t vj[CPT], dcol[CPT];
-  uint32_t lim32[CPT];  // value of k2 saturated to 32 bits: a candidate above it cannot enter the top-2
+  // k1 / k2 values saturated to 32 bits: a candidate above lim2, or above lim1
+  // from the best key's own tree, cannot change the column's top-2
+  uint32_t lim1[CPT], lim2[CPT];
   bool narrow;          // cost range below 2^30
   uint32_t vis;   // bit k: column k has been reached (is in a tree)
   uint32_t stl;   // bit k: k1 is only a lower bound (its tree is gone)
@@ -221,32 +229,21 @@ struct Engine {
   }
 
   __device__ __forceinline__ void sync_lim(int k) {
-    const int64_t v2 = kval(k2[k]);
-    lim32[k] = v2 > 0xffffffffll ? 0xffffffffu : (uint32_t)v2;
-  }
-
-  __device__ __forceinline__ void push(int k, uint64_t c, int t) {
-    top2_push(k1[k], t1[k], k2[k], t2[k], c, t);
-    if (t1[k] == t) stl &= ~(1u << k);  // best key now from a live tree
-    sync_lim(k);
-  }
-
-  // Offer reduced-cost value `val` from row r of tree t to owned column k.
-  // Nearly every candidate is rejected by the single compare against lim2.
-  __device__ __forceinline__ void offer(int k, int64_t val, int r, int t) {
-    if (val > kval(k2[k])) return;
-    if (val < 0) { fail(OT_EINTERNAL); val = 0; }
-    push(k, pack(val, r), t);
+    const int64_t v1 = kval(k1[k]), v2 = kval(k2[k]);
+    lim1[k] = v1 > 0xffffffffll ? 0xffffffffu : (uint32_t)v1;
+    lim2[k] = v2 > 0xffffffffll ? 0xffffffffu : (uint32_t)v2;
   }
 
   // Fold cost rows list[0..cnt) (forest rows; rows no longer in the forest
   // are skipped) into every owned column's top-2 keys.  Rows go in chunks of U
   // whose loads are all issued before any is used, so a short frontier costs
   // one memory latency.  Each chunk first tests every (row, column) candidate
-  // against the column's second key without branching; only candidates that
-  // can enter a top-2 take the exact 64-bit path.  With NARROW (cost range
-  // below 2^30) every key value is below 2^32, so the test runs in 32-bit
-  // modular arithmetic, which is exact there.  Returns rows used.
+  // against the column's second key without branching; only (row, column)
+  // slots where some lane of the wavefront passes take the exact update.
+  // With NARROW (cost range below 2^30) every key value is below 2^32: the
+  // test runs in 32-bit modular arithmetic, which is exact there, and the
+  // update is select-only (no divergent branches, which cost more than they
+  // save when a few lanes pass).  Returns rows used.
   static constexpr int U = CPT >= 8 ? 2 : 16 / CPT > 8 ? 8 : 16 / CPT;
   static constexpr int GU = 8;  // forest rows in flight per lane when recomputing a stale column
   template <bool NARROW>
@@ -270,6 +267,7 @@ struct Engine {
         for (int k = 0; k < CPT; ++k) c[q][k] = row[lcol(k)];
       }
       uint32_t pass = 0;
+      uint32_t v32[U][CPT];  // NARROW: exact key values of the candidates
 #pragma unroll
       for (int q = 0; q < U; ++q) {
         used += t[q] >= 0;
@@ -278,24 +276,68 @@ struct Engine {
           bool p;
           if (NARROW) {
             const uint32_t v = (uint32_t)c[q][k] - ((uint32_t)h[q] + (uint32_t)vj[k]);
-            p = v <= lim32[k];
+            v32[q][k] = v;
+            p = v <= lim2[k];
           } else {
-            p = (int64_t)c[q][k] - h[q] - vj[k] <= kval(k2[k]);
+            const int64_t v = (int64_t)c[q][k] - h[q] - vj[k];
+            p = v <= kval(k2[k]);
           }
-          pass |= (p && t[q] >= 0) ? (1u << (q * CPT + k)) : 0u;
+          pass |= (p & (t[q] >= 0) & (col(k) < n)) ? (1u << (q * CPT + k)) : 0u;
         }
       }
       // Slots nobody in the wavefront needs are skipped with one scalar branch.
       if (__builtin_amdgcn_ballot_w64(pass != 0) != 0) {
+        uint32_t clr = 0, hit = 0;
 #pragma unroll
         for (int q = 0; q < U; ++q) {
 #pragma unroll
           for (int k = 0; k < CPT; ++k) {
-            const bool p = ((pass >> (q * CPT + k)) & 1u) && col(k) < n;
+            const bool p = (pass >> (q * CPT + k)) & 1u;
             if (__builtin_amdgcn_ballot_w64(p) == 0) continue;
-            if (p) offer(k, (int64_t)c[q][k] - h[q] - vj[k], r[q], t[q]);
+            if (NARROW) {
+              // select-only update (a failed slot offers kInf, which changes nothing)
+              const uint64_t key = p ? (((uint64_t)v32[q][k] << kRowBits) | (uint32_t)r[q]) : kInf;
+              const int tq = t[q];
+              const bool lt1 = key < k1[k];
+              const bool ch2 = (tq != t1[k]) & (key < k2[k]);
+              const uint64_t x = lt1 ? k1[k] : key;
+              const int tx = lt1 ? t1[k] : tq;
+              k2[k] = ch2 ? x : k2[k];
+              t2[k] = ch2 ? tx : t2[k];
+              k1[k] = lt1 ? key : k1[k];
+              t1[k] = lt1 ? tq : t1[k];
+              clr |= lt1 ? (1u << k) : 0u;  // best key now from a live tree
+              hit |= p ? (1u << k) : 0u;
+              continue;
+            }
+            // Divergent from here on: typically a few lanes of the wavefront
+            // take each branch, and a branch no lane takes is skipped whole.
+            if (p) {
+              uint64_t key;
+              if (NARROW) {
+                key = ((uint64_t)v32[q][k] << kRowBits) | (uint32_t)r[q];
+              } else {
+                int64_t val = (int64_t)c[q][k] - h[q] - vj[k];
+                if (val < 0) { fail(OT_EINTERNAL); val = 0; }
+                key = pack(val, r[q]);
+              }
+              const int tq = t[q];
+              if (key < k1[k]) {
+                // new best; the old best stays second unless it is from the same tree
+                if (tq != t1[k]) { k2[k] = k1[k]; t2[k] = t1[k]; }
+                k1[k] = key; t1[k] = tq;
+                clr |= 1u << k;  // best key now from a live tree
+              } else if (tq != t1[k] && key < k2[k]) {
+                k2[k] = key; t2[k] = tq;
+              }
+              hit |= 1u << k;
+            }
           }
         }
+        stl &= ~clr;
+#pragma unroll
+        for (int k = 0; k < CPT; ++k)
+          if ((hit >> k) & 1u) sync_lim(k);
       }
     }
     return used;
@@ -371,6 +413,10 @@ struct Engine {
       if (s < g) {
         const int j = gcol[s];
         const int64_t v = gv[s];
+        // column j of C: a contiguous row of the transpose when there is one,
+        // else one entry per cost row
+        const int32_t *colp = CT ? CT + (size_t)j * (size_t)n : C + j;
+        const size_t cstride = CT ? 1 : (size_t)ld;
         uint64_t a1 = kInf, a2 = kInf;
         int ta1 = -1, ta2 = -1;
         const int stride = 64 * wpc;
@@ -387,7 +433,7 @@ struct Engine {
             h[q] = hrow[i[q]];
           }
 #pragma unroll
-          for (int q = 0; q < GU; ++q) c[q] = C[(size_t)i[q] * (size_t)ld + j];
+          for (int q = 0; q < GU; ++q) c[q] = colp[(size_t)i[q] * cstride];
 #pragma unroll
           for (int q = 0; q < GU; ++q) {
             if (t[q] < 0) continue;
@@ -430,7 +476,7 @@ struct Engine {
   }
 
   __device__ __forceinline__ void run(const Problem &P, char *smem) {
-    C = P.C; n = P.n; ld = P.ld;
+    C = P.C; CT = P.CT; n = P.n; ld = P.ld;
     tid = threadIdx.x; lane = tid & 63; wid = tid >> 6;
     err_local = 0;
     const LdsLayout L = lds_layout(n);
@@ -510,7 +556,8 @@ struct Engine {
 #pragma unroll
     for (int k = 0; k < CPT; ++k) {
       k1[k] = kInf; k2[k] = kInf; t1[k] = -1; t2[k] = -1; vj[k] = 0; dcol[k] = 0; ctree[k] = -1;
-      lim32[k] = 0xffffffffu;
+      lim1[k] = 0xffffffffu;
+      lim2[k] = 0xffffffffu;
     }
     {
       uint64_t b1[CPT], b2[CPT];

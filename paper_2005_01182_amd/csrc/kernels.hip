@@ -51,6 +51,7 @@ __global__ __launch_bounds__(BLOCK) void k_assign_batch(BatchArgs A) {
     P.C = A.C + A.coff[k];
     P.n = n;
     P.ld = n;
+    P.CT = nullptr;
     P.max_paths = A.max_paths;
     P.flags = 0;
     P.plan = A.plan + A.voff[k];
@@ -69,6 +70,23 @@ __global__ __launch_bounds__(BLOCK) void k_assign_batch(BatchArgs A) {
       if (threadIdx.x == 0) __hip_atomic_store(&A.done[k], A.tag, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
     }
     __syncthreads();
+  }
+}
+
+// CT = C^T (n x n, row stride n) from C (row stride ld): 64 x 64 tiles through
+// LDS so that both the read and the write are coalesced.
+__global__ __launch_bounds__(256) void k_transpose(const int32_t *C, int n, int ld, int32_t *CT) {
+  __shared__ int32_t tile[64][65];
+  const int bj = blockIdx.x * 64, bi = blockIdx.y * 64;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  for (int r = ty; r < 64; r += 4) {
+    const int i = bi + r, j = bj + tx;
+    if (i < n && j < n) tile[r][tx] = C[(size_t)i * (size_t)ld + j];
+  }
+  __syncthreads();
+  for (int r = ty; r < 64; r += 4) {
+    const int j = bj + r, i = bi + tx;
+    if (i < n && j < n) CT[(size_t)j * (size_t)n + i] = tile[tx][r];
   }
 }
 
@@ -308,8 +326,9 @@ hipError_t launch_transport(const TransportArgs &T, int block, hipStream_t s) {
   hipLaunchKernelGGL(k_tr_expand, dim3((T.S + 255) / 256, T.S), dim3(256), 0, s, T.C, T.m, T.S, T.rowbin, T.colbin,
                      T.Cx, T.gate);
   if ((e = hipGetLastError()) != hipSuccess) return e;
+  if (T.CxT && (e = launch_transpose(T.Cx, T.S, T.S, T.CxT, s)) != hipSuccess) return e;
   Problem P;
-  P.C = T.Cx; P.n = T.S; P.ld = T.S; P.max_paths = T.max_paths; P.flags = 0;
+  P.C = T.Cx; P.n = T.S; P.ld = T.S; P.max_paths = T.max_paths; P.flags = 0; P.CT = T.CxT;
   P.plan = T.plan; P.cost = T.cost; P.u = T.U; P.v = T.V; P.stats = T.stats; P.ws = T.ws;
   if ((e = launch_assign_one(P, block, T.gate, s)) != hipSuccess) return e;
   if ((e = launch_fill_i32(T.X, 0, (int64_t)T.n * T.m, s)) != hipSuccess) return e;
@@ -325,6 +344,12 @@ hipError_t launch_transport(const TransportArgs &T, int block, hipStream_t s) {
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(k_tr_duals_zero_cols, dim3((T.m + 255) / 256), dim3(256), 0, s, T.C, T.c, T.n, T.m, T.u, T.v,
                      T.gate, T.stats);
+  return hipGetLastError();
+}
+
+hipError_t launch_transpose(const int32_t *C, int n, int ld, int32_t *CT, hipStream_t s) {
+  const int t = (n + 63) / 64;
+  hipLaunchKernelGGL(k_transpose, dim3(t, t), dim3(256), 0, s, C, n, ld, CT);
   return hipGetLastError();
 }
 

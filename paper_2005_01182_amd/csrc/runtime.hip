@@ -212,12 +212,14 @@ int ot_assign_ex(const int32_t *C, int32_t n, const ot_options *opt, int32_t *pl
   auto *dcost = (int64_t *)pool_get(4, 8, &err);
   auto *dstats = (ot_stats *)pool_get(5, sizeof(ot_stats), &err);
   auto *dws = (int32_t *)pool_get(6, 4 * ws_ints(n), &err);
+  auto *dCT = (int32_t *)pool_get(7, 4 * N * N, &err);
   if (err) return err;
   hipStream_t s = g_stream;
   hipError_t e = hipMemcpyAsync(dC, C, 4 * N * N, hipMemcpyHostToDevice, s);
   if (e != hipSuccess) return map_hip(e);
+  if ((e = launch_transpose(dC, n, n, dCT, s)) != hipSuccess) return map_hip(e);
   Problem P;
-  P.C = dC; P.n = n; P.ld = n; P.max_paths = max_paths; P.flags = flags;
+  P.C = dC; P.n = n; P.ld = n; P.CT = dCT; P.max_paths = max_paths; P.flags = flags;
   P.plan = dplan; P.cost = dcost; P.u = du; P.v = dv; P.stats = dstats; P.ws = dws;
   if ((e = launch_assign_one(P, block, nullptr, s)) != hipSuccess) return map_hip(e);
   ot_stats hs;
@@ -255,9 +257,12 @@ int ot_assign_dev(const int32_t *dC, int32_t n, int32_t ld, const ot_options *op
   hipStream_t s = stream ? (hipStream_t)stream : g_stream;
   int err = OT_OK;
   auto *dws = (int32_t *)stream_ws(s, 0, 4 * ws_ints(n), &err);
+  auto *dCT = (int32_t *)stream_ws(s, 3, 4 * (size_t)n * (size_t)n, &err);
   if (err) return err;
+  hipError_t e = launch_transpose(dC, n, ld, dCT, s);
+  if (e != hipSuccess) return map_hip(e);
   Problem P;
-  P.C = dC; P.n = n; P.ld = ld; P.max_paths = max_paths; P.flags = flags;
+  P.C = dC; P.n = n; P.ld = ld; P.CT = dCT; P.max_paths = max_paths; P.flags = flags;
   P.plan = dplan; P.cost = dcost; P.u = du; P.v = dv; P.stats = dstats; P.ws = dws;
   return map_hip(launch_assign_one(P, block, nullptr, s));
 }
@@ -428,6 +433,7 @@ static int transport_buffers(TransportArgs &T, int n, int m, int S, bool async, 
   T.U = (int64_t *)get(7, 8 * SS);
   T.V = (int64_t *)get(8, 8 * SS);
   T.ws = (int32_t *)get(9, 4 * ws_ints(S));
+  T.CxT = (int32_t *)(async ? stream_ws(s, 25, 4 * SS * SS, &err) : pool_get(70, 4 * SS * SS, &err));
   return err;
 }
 
