@@ -99,7 +99,16 @@ typedef struct ot_options {
                               1 = one tree at a time (classical KM), k = at most k */
     int32_t block;         /* workgroup width: 0 = automatic, else 64, 256, 512 or 1024 */
     int32_t flags;         /* OT_FLAG_* bits */
-    int32_t reserved[5];   /* must be zero */
+    int32_t scale;         /* cost scaling factor s (Section 2.3.1: one scaling factor turns the
+                              costs into small integers): 0 or 1 = exact.  With s > 1 the solver
+                              runs on C'_ij = floor(C_ij / s) and returns
+                                plan  an optimal plan for C',
+                                cost  sum_i C[i, plan[i]] on the ORIGINAL costs,
+                                u, v  s * (optimal duals of C'), which are feasible for C
+                                      (u_i + v_j <= C_ij), so
+                              sum u + sum v <= OPT(C) <= cost <= sum u + sum v + n (s - 1).
+                              Assignment calls only (ot_assign_ex, ot_assign_dev). */
+    int32_t reserved[4];   /* must be zero */
 } ot_options;
 
 /* Status text for a code; never NULL. */

@@ -10,6 +10,8 @@ Functions (all exact, int64 results):
 * ``assign(C)``             -> (plan, cost, u, v)   shortest-augmenting-path KM, O(n^3)
 * ``brute_force(C)``        -> (best, num_optimal)  all n! permutations, n <= 10
 * ``certify_assign(C, plan, u, v)``   -> 0 if the LP-duality certificate holds
+* ``assign_scaled(C, s)``   -> (plan, cost, u, v)   single scaling factor (Section 2.3.1):
+                             ``assign`` on floor(C / s), cost over C, duals times s
 * ``transport(C, r, c)``    -> (X, cost, u, v)      unit expansion + ``assign``
 * ``certify_transport(C, r, c, X, u, v)`` -> 0 if the certificate holds
 """
@@ -80,6 +82,26 @@ def assign(C):
     if rc:
         raise RuntimeError("oracle_assign failed: %d" % rc)
     return plan, int(cost.value), u, v
+
+
+def assign_scaled(C, s: int):
+    """Assignment under one scaling factor s >= 1 (Section 2.3.1, Batched KM: the
+    costs are replaced by small integers before solving).
+
+    Solves floor(C / s) exactly (floor toward minus infinity) and returns
+    (plan, cost of the plan over C, s * u', s * v') where (u', v') are optimal
+    duals of the scaled problem.  Because s * floor(C / s) <= C, the returned
+    duals are feasible for C, and for every permutation the scaled cost times s
+    is within n (s - 1) below its cost over C, so
+    sum(u) + sum(v) <= OPT(C) <= cost <= sum(u) + sum(v) + n (s - 1).
+    """
+    C = _square(C)
+    if int(s) < 1:
+        raise ValueError("scaling factor must be >= 1")
+    Cs = np.floor_divide(C.astype(np.int64), int(s)).astype(np.int32)
+    plan, _, u, v = assign(Cs)
+    cost = int(C.astype(np.int64)[np.arange(C.shape[0]), plan].sum())
+    return plan, cost, u * int(s), v * int(s)
 
 
 def brute_force(C):

@@ -94,6 +94,9 @@ struct Problem {
   const int32_t *C;   // n x n, row stride ld
   int n, ld;
   const int32_t *CT;  // transpose of C (n x n, row stride n), or null; only read to refresh single columns
+  const int32_t *Cout;  // costs the reported total is taken over (row stride ldo), or null for C
+  int ldo;
+  int dscale;         // reported duals are dscale * (duals of C); 1 unless C holds scaled-down costs
 
   int max_paths;      // 0 = all free rows
   int flags;          // OT_FLAG_* bits
@@ -781,16 +784,18 @@ struct Engine {
     const int err = ctl[ERR];
     if (err == 0) {
       int64_t part = 0;
+      const int32_t *Cr = P.Cout ? P.Cout : C;
+      const size_t ldr = P.Cout ? (size_t)P.ldo : (size_t)ld;
       for (int i = tid; i < n; i += BLOCK) {
         const int j = mrow[i];
         P.plan[i] = j;
-        if (P.u) P.u[i] = hrow[i];
-        part += (j >= 0 && j < n) ? (int64_t)C[(size_t)i * (size_t)ld + j] : 0;
+        if (P.u) P.u[i] = hrow[i] * P.dscale;
+        part += (j >= 0 && j < n) ? (int64_t)Cr[(size_t)i * ldr + j] : 0;
       }
       if (P.v) {
 #pragma unroll
         for (int k = 0; k < CPT; ++k)
-          if (col(k) < n) P.v[col(k)] = vj[k];
+          if (col(k) < n) P.v[col(k)] = (int64_t)vj[k] * P.dscale;
       }
       part = wave_sum_i64(part);
       int64_t *sred = (int64_t *)(red + 16);

@@ -52,6 +52,9 @@ __global__ __launch_bounds__(BLOCK) void k_assign_batch(BatchArgs A) {
     P.n = n;
     P.ld = n;
     P.CT = nullptr;
+    P.Cout = nullptr;
+    P.ldo = n;
+    P.dscale = 1;
     P.max_paths = A.max_paths;
     P.flags = 0;
     P.plan = A.plan + A.voff[k];
@@ -87,6 +90,18 @@ __global__ __launch_bounds__(256) void k_transpose(const int32_t *C, int n, int 
   for (int r = ty; r < 64; r += 4) {
     const int j = bj + r, i = bi + tx;
     if (i < n && j < n) CT[(size_t)j * (size_t)n + i] = tile[tx][r];
+  }
+}
+
+// Cs = floor(C / s) element-wise (row stride ld in, n out): the scaled costs of
+// the single-scaling-factor mode.  floor(C/s) * s <= C, so duals feasible for
+// Cs become feasible for C when multiplied by s.
+__global__ void k_floor_div(const int32_t *C, int n, int ld, int32_t s, int32_t *Cs) {
+  const int i = blockIdx.y;
+  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x) {
+    const int32_t c = C[(size_t)i * (size_t)ld + j];
+    const int32_t q = c / s;  // truncates toward zero; step down for negative non-multiples
+    Cs[(size_t)i * (size_t)n + j] = (c % s != 0 && c < 0) ? q - 1 : q;
   }
 }
 
@@ -329,6 +344,7 @@ hipError_t launch_transport(const TransportArgs &T, int block, hipStream_t s) {
   if (T.CxT && (e = launch_transpose(T.Cx, T.S, T.S, T.CxT, s)) != hipSuccess) return e;
   Problem P;
   P.C = T.Cx; P.n = T.S; P.ld = T.S; P.max_paths = T.max_paths; P.flags = 0; P.CT = T.CxT;
+  P.Cout = nullptr; P.ldo = T.S; P.dscale = 1;
   P.plan = T.plan; P.cost = T.cost; P.u = T.U; P.v = T.V; P.stats = T.stats; P.ws = T.ws;
   if ((e = launch_assign_one(P, block, T.gate, s)) != hipSuccess) return e;
   if ((e = launch_fill_i32(T.X, 0, (int64_t)T.n * T.m, s)) != hipSuccess) return e;
@@ -344,6 +360,12 @@ hipError_t launch_transport(const TransportArgs &T, int block, hipStream_t s) {
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(k_tr_duals_zero_cols, dim3((T.m + 255) / 256), dim3(256), 0, s, T.C, T.c, T.n, T.m, T.u, T.v,
                      T.gate, T.stats);
+  return hipGetLastError();
+}
+
+hipError_t launch_floor_div(const int32_t *C, int n, int ld, int32_t s, int32_t *Cs, hipStream_t st) {
+  const int bx = (n + 255) / 256;
+  hipLaunchKernelGGL(k_floor_div, dim3(bx < 8 ? bx : 8, n), dim3(256), 0, st, C, n, ld, s, Cs);
   return hipGetLastError();
 }
 

@@ -145,16 +145,18 @@ static bool range_ok(const int32_t *C, int64_t count) {
   return (int64_t)mx - (int64_t)mn <= 0x7fffffffll;
 }
 
-static int check_options(const ot_options *opt, int n, int *block, int *max_paths, int *flags) {
+static int check_options(const ot_options *opt, int n, int *block, int *max_paths, int *flags, int *scale) {
   *block = default_block(n);
   *max_paths = 0;
   *flags = 0;
+  *scale = 1;
   if (!opt) return OT_OK;
-  for (int k = 0; k < 5; ++k)
+  for (int k = 0; k < 4; ++k)
     if (opt->reserved[k] != 0) return OT_EINVAL;
-  if (opt->max_paths < 0 || (opt->flags & ~OT_FLAG_PHASE_TIMERS) != 0) return OT_EINVAL;
+  if (opt->max_paths < 0 || (opt->flags & ~OT_FLAG_PHASE_TIMERS) != 0 || opt->scale < 0) return OT_EINVAL;
   *max_paths = opt->max_paths;
   *flags = opt->flags;
+  *scale = opt->scale > 1 ? opt->scale : 1;
   if (opt->block != 0) {
     if (!block_ok(opt->block, n)) return OT_EINVAL;
     *block = opt->block;
@@ -196,8 +198,8 @@ int ot_assign_ex(const int32_t *C, int32_t n, const ot_options *opt, int32_t *pl
                  int64_t *v, ot_stats *stats) {
   if (!C || !plan || !cost || n <= 0) return OT_EINVAL;
   if (n > OT_MAX_N) return OT_ETOOBIG;
-  int block, max_paths, flags;
-  int rc = check_options(opt, n, &block, &max_paths, &flags);
+  int block, max_paths, flags, scale;
+  int rc = check_options(opt, n, &block, &max_paths, &flags, &scale);
   if (rc) return rc;
   if (!range_ok(C, (int64_t)n * n)) return OT_ERANGE;
 
@@ -213,13 +215,20 @@ int ot_assign_ex(const int32_t *C, int32_t n, const ot_options *opt, int32_t *pl
   auto *dstats = (ot_stats *)pool_get(5, sizeof(ot_stats), &err);
   auto *dws = (int32_t *)pool_get(6, 4 * ws_ints(n), &err);
   auto *dCT = (int32_t *)pool_get(7, 4 * N * N, &err);
+  auto *dCs = scale > 1 ? (int32_t *)pool_get(8, 4 * N * N, &err) : nullptr;
   if (err) return err;
   hipStream_t s = g_stream;
   hipError_t e = hipMemcpyAsync(dC, C, 4 * N * N, hipMemcpyHostToDevice, s);
   if (e != hipSuccess) return map_hip(e);
-  if ((e = launch_transpose(dC, n, n, dCT, s)) != hipSuccess) return map_hip(e);
+  const int32_t *dsolve = dC;
+  if (scale > 1) {
+    if ((e = launch_floor_div(dC, n, n, scale, dCs, s)) != hipSuccess) return map_hip(e);
+    dsolve = dCs;
+  }
+  if ((e = launch_transpose(dsolve, n, n, dCT, s)) != hipSuccess) return map_hip(e);
   Problem P;
-  P.C = dC; P.n = n; P.ld = n; P.CT = dCT; P.max_paths = max_paths; P.flags = flags;
+  P.C = dsolve; P.n = n; P.ld = n; P.CT = dCT; P.max_paths = max_paths; P.flags = flags;
+  P.Cout = dC; P.ldo = n; P.dscale = scale;
   P.plan = dplan; P.cost = dcost; P.u = du; P.v = dv; P.stats = dstats; P.ws = dws;
   if ((e = launch_assign_one(P, block, nullptr, s)) != hipSuccess) return map_hip(e);
   ot_stats hs;
@@ -249,8 +258,8 @@ int ot_assign_dev(const int32_t *dC, int32_t n, int32_t ld, const ot_options *op
                   int64_t *du, int64_t *dv, ot_stats *dstats, void *stream) {
   if (!dC || !dplan || !dcost || n <= 0 || ld < n) return OT_EINVAL;
   if (n > OT_MAX_N) return OT_ETOOBIG;
-  int block, max_paths, flags;
-  int rc = check_options(opt, n, &block, &max_paths, &flags);
+  int block, max_paths, flags, scale;
+  int rc = check_options(opt, n, &block, &max_paths, &flags, &scale);
   if (rc) return rc;
   std::lock_guard<std::mutex> lk(g_mu);
   if ((rc = init_locked())) return rc;
@@ -258,11 +267,20 @@ int ot_assign_dev(const int32_t *dC, int32_t n, int32_t ld, const ot_options *op
   int err = OT_OK;
   auto *dws = (int32_t *)stream_ws(s, 0, 4 * ws_ints(n), &err);
   auto *dCT = (int32_t *)stream_ws(s, 3, 4 * (size_t)n * (size_t)n, &err);
+  auto *dCs = scale > 1 ? (int32_t *)stream_ws(s, 4, 4 * (size_t)n * (size_t)n, &err) : nullptr;
   if (err) return err;
-  hipError_t e = launch_transpose(dC, n, ld, dCT, s);
-  if (e != hipSuccess) return map_hip(e);
+  hipError_t e;
+  const int32_t *dsolve = dC;
+  int lds = ld;
+  if (scale > 1) {
+    if ((e = launch_floor_div(dC, n, ld, scale, dCs, s)) != hipSuccess) return map_hip(e);
+    dsolve = dCs;
+    lds = n;
+  }
+  if ((e = launch_transpose(dsolve, n, lds, dCT, s)) != hipSuccess) return map_hip(e);
   Problem P;
-  P.C = dC; P.n = n; P.ld = ld; P.CT = dCT; P.max_paths = max_paths; P.flags = flags;
+  P.C = dsolve; P.n = n; P.ld = lds; P.CT = dCT; P.max_paths = max_paths; P.flags = flags;
+  P.Cout = dC; P.ldo = ld; P.dscale = scale;
   P.plan = dplan; P.cost = dcost; P.u = du; P.v = dv; P.stats = dstats; P.ws = dws;
   return map_hip(launch_assign_one(P, block, nullptr, s));
 }

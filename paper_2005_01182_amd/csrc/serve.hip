@@ -62,7 +62,8 @@ struct Lane {  // one stream per size class
   hipEvent_t ev = nullptr;
   bool busy = false;
   uint32_t tag = 0;
-  std::vector<Req *> group;
+  std::vector<Req *> group;  // requests admitted for the next launch (cleared once launched)
+  int outstanding = 0;       // requests of the launched group not yet retired
   // descriptors of the group in flight (device and pinned staging)
   int64_t *d_coff = nullptr, *d_voff = nullptr, *h_coff = nullptr, *h_voff = nullptr;
   int32_t *d_n = nullptr, *d_order = nullptr, *h_n = nullptr, *h_order = nullptr;
@@ -179,6 +180,10 @@ int launch_group(ot_server *s, int c) {
   if ((e = launch_assign_batch(A, block, grid, L.s)) != hipSuccess) return map_hip(e);
   if ((e = hipEventRecord(L.ev, L.s)) != hipSuccess) return map_hip(e);
   L.busy = true;
+  // A retired request may be handed back and freed by ot_serve_poll before this
+  // lane's event completes, so the lane keeps a count, never the pointers.
+  L.outstanding = G;
+  L.group.clear();
   ++s->ctr.groups;
   return OT_OK;
 }
@@ -202,6 +207,7 @@ bool retire(ot_server *s) {
     }
     r->t_done = s->now();
     r->done = true;
+    --L.outstanding;
     s->arena->release(r->off, r->abytes);
     s->free_slots.push_back(r->slot);
     s->inflight_bytes -= r->bytes;
@@ -215,11 +221,8 @@ bool retire(ot_server *s) {
     Lane &L = s->lanes[c];
     if (!L.busy) continue;
     if (hipEventQuery(L.ev) != hipSuccess) continue;
-    bool all = true;
-    for (Req *r : L.group) all = all && r->done;
-    if (!all) continue;  // the flags of a finished kernel are visible on the next pass
+    if (L.outstanding > 0) continue;  // the flags of a finished kernel are visible on the next pass
     L.busy = false;
-    L.group.clear();
     changed = true;
   }
   return changed;

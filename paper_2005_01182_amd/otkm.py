@@ -44,7 +44,7 @@ STATS_FIELDS = [name for name, _ in ot_stats._fields_]
 
 class ot_options(ctypes.Structure):
     _fields_ = [("max_paths", ctypes.c_int32), ("block", ctypes.c_int32), ("flags", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 5)]
+                ("scale", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
 
 
 OT_FLAG_PHASE_TIMERS = 1
@@ -146,19 +146,23 @@ def device_info() -> dict:
             "mem_gb": props.total_memory / 2**30}
 
 
-def _options(max_paths=0, block=0, timers=False):
+def _options(max_paths=0, block=0, timers=False, scale=1):
     o = ot_options()
     o.max_paths = int(max_paths)
     o.block = int(block)
     o.flags = OT_FLAG_PHASE_TIMERS if timers else 0
+    o.scale = int(scale)
     return o
 
 
 # ----------------------------------------------------------------------------- host calls
-def ot_assign(C, max_paths: int = 0, block: int = 0, with_stats: bool = False, timers: bool = False):
-    """Exact assignment of a square int32 cost matrix.
+def ot_assign(C, max_paths: int = 0, block: int = 0, with_stats: bool = False, timers: bool = False,
+              scale: int = 1):
+    """Assignment of a square int32 cost matrix (exact; with scale > 1, optimal for floor(C / scale)).
 
-    Returns (plan, cost, u, v) or (plan, cost, u, v, stats_dict).
+    Returns (plan, cost, u, v) or (plan, cost, u, v, stats_dict).  With scale > 1
+    cost is taken over C and (u, v) are scale times the duals of floor(C / scale):
+    feasible for C, with sum(u) + sum(v) <= OPT(C) <= cost <= sum(u) + sum(v) + n (scale - 1).
     """
     C = np.ascontiguousarray(C, dtype=np.int32)
     if C.ndim != 2 or C.shape[0] != C.shape[1]:
@@ -169,7 +173,7 @@ def ot_assign(C, max_paths: int = 0, block: int = 0, with_stats: bool = False, t
     v = np.empty(n, np.int64)
     cost = ctypes.c_int64(0)
     st = ot_stats()
-    opt = _options(max_paths, block, timers)
+    opt = _options(max_paths, block, timers, scale)
     rc = load().ot_assign_ex(_p(C), n, ctypes.byref(opt), _p(plan), ctypes.byref(cost), _p(u), _p(v),
                              ctypes.byref(st))
     _check(rc, "ot_assign")
@@ -254,11 +258,11 @@ def stats_tensor(count=1, device="cuda"):
 
 
 def ot_assign_dev(C, plan, cost, u=None, v=None, stats=None, max_paths=0, block=0, stream=None, ld=None,
-                  timers=False):
+                  timers=False, scale=1):
     """Queue an assignment on device tensors (asynchronous on `stream`)."""
     n = int(C.shape[0])
     ld = int(ld if ld is not None else C.stride(0))
-    opt = _options(max_paths, block, timers)
+    opt = _options(max_paths, block, timers, scale)
     rc = load().ot_assign_dev(_tp(C), n, ld, ctypes.byref(opt), _tp(plan), _tp(cost), _tp(u), _tp(v),
                               _tp(stats), _stream(stream))
     _check(rc, "ot_assign_dev")

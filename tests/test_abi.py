@@ -59,6 +59,8 @@ VALIDATION = textwrap.dedent(r"""
     out["assign_bad_block"] = code(ot.ot_assign, C, block=100)
     out["assign_block_too_narrow"] = code(ot.ot_assign, np.zeros((600, 600), np.int32), block=64)
     out["assign_neg_paths"] = code(ot.ot_assign, C, max_paths=-1)
+    out["assign_neg_scale"] = code(ot.ot_assign, C, scale=-2)
+    out["assign_scale_ok_but_nodev"] = code(ot.ot_assign, C, scale=10)
     r = np.array([1, 1, 2], np.int32); c = np.array([2, 2], np.int32)
     Ct = np.zeros((3, 2), np.int32)
     out["transport_ok_but_nodev"] = code(ot.ot_transport, Ct, r, c)
@@ -108,6 +110,8 @@ def test_validation_codes(codes):
     assert codes["assign_range"] == -2
     assert codes["assign_range_edge"] == -8       # range exactly 2^31 - 1: passes validation
     assert codes["assign_bad_block"] == -1
+    assert codes["assign_neg_scale"] == -1
+    assert codes["assign_scale_ok_but_nodev"] == -8
     assert codes["assign_block_too_narrow"] == -1
     assert codes["assign_neg_paths"] == -1
     assert codes["transport_ok_but_nodev"] == -8

@@ -166,3 +166,68 @@ def test_device_api_with_row_stride(otkm_gpu):
     otkm_gpu.ot_assign_dev(big, plan, cost, ld=128)
     torch.cuda.synchronize()
     assert int(cost.item()) == oracle.assign(C)[1]
+
+
+# ----------------------------------------------------------------------------- one scaling factor
+def check_scaled(C, s, plan, cost, u, v):
+    """The scaled-mode contract, checked against the oracle's scaled solve."""
+    n = C.shape[0]
+    C64 = C.astype(np.int64)
+    assert sorted(plan.tolist()) == list(range(n))
+    assert cost == int(C64[np.arange(n), plan].sum())
+    assert (u % s == 0).all() and (v % s == 0).all()
+    Cs = np.floor_divide(C64, s).astype(np.int32)
+    assert oracle.certify_assign(Cs, plan, u // s, v // s) == 0   # optimal for floor(C / s)
+    assert (u[:, None] + v[None, :] <= C64).all()                 # feasible for C
+    lower = int(u.sum() + v.sum())
+    assert cost - lower <= n * (s - 1)
+    _, ocost, ou, ov = oracle.assign_scaled(C, s)
+    # same scaled optimum as the oracle (plans may differ on ties)
+    assert int(Cs.astype(np.int64)[np.arange(n), plan].sum()) == int(ou.sum() + ov.sum()) // s
+    _, opt, _, _ = oracle.assign(C)
+    assert lower <= opt <= cost
+
+
+@pytest.mark.parametrize("s", [2, 7, 100])
+@pytest.mark.parametrize("n", [17, 64, 300, 1000])
+def test_scaled_host_api(otkm_gpu, n, s):
+    C = wl.geometric_assignment(n, seed=70 + n)
+    say("case scaled n=%d s=%d" % (n, s))
+    plan, cost, u, v, st = otkm_gpu.ot_assign(C, with_stats=True, scale=s)
+    assert st["status"] == 0
+    check_scaled(C, s, plan, cost, u, v)
+
+
+def test_scaled_negative_costs(otkm_gpu):
+    rng = np.random.default_rng(91)
+    C = rng.integers(-50_000, 50_000, (257, 257)).astype(np.int32)
+    for s in (3, 1000):
+        say("case scaled negative s=%d" % s)
+        plan, cost, u, v = otkm_gpu.ot_assign(C, scale=s)
+        check_scaled(C, s, plan, cost, u, v)
+
+
+def test_scaled_factor_one_is_exact(otkm_gpu):
+    C = wl.geometric_assignment(200, seed=3)
+    a = otkm_gpu.ot_assign(C)
+    b = otkm_gpu.ot_assign(C, scale=1)
+    assert all(np.array_equal(x, y) for x, y in zip((a[0], a[2], a[3]), (b[0], b[2], b[3]))) and a[1] == b[1]
+
+
+def test_scaled_device_api_with_row_stride(otkm_gpu):
+    import torch
+    n, s = 300, 50
+    C = wl.geometric_assignment(n, seed=8)
+    big = torch.full((n, n + 20), 2_000_000_000, dtype=torch.int32, device="cuda")  # padding never read
+    big[:, :n] = torch.from_numpy(C).cuda()
+    plan = torch.empty(n, dtype=torch.int32, device="cuda")
+    cost = torch.empty(1, dtype=torch.int64, device="cuda")
+    u = torch.empty(n, dtype=torch.int64, device="cuda")
+    v = torch.empty(n, dtype=torch.int64, device="cuda")
+    st = otkm_gpu.stats_tensor()
+    otkm_gpu.ot_assign_dev(big, plan, cost, u, v, st, ld=n + 20, scale=s)
+    torch.cuda.synchronize()
+    assert int(st[0, 7]) == 0
+    check_scaled(C, s, plan.cpu().numpy(), int(cost.item()), u.cpu().numpy(), v.cpu().numpy())
+    ref = otkm_gpu.ot_assign(C, scale=s)
+    assert int(cost.item()) == ref[1]

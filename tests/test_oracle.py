@@ -60,6 +60,60 @@ def test_brute_force_small(n, kind):
         assert (cb, cc) == (best, cnt)
 
 
+# ----------------------------------------------------------------------------- one scaling factor
+def py_floor_scaled(C, s):
+    """floor(C / s) entry by entry with Python integers (floor toward minus infinity)."""
+    return np.array([[int(x) // s for x in row] for row in C], dtype=np.int32)
+
+
+def test_scaled_with_factor_one_is_exact():
+    rng = np.random.default_rng(41)
+    for n in (1, 5, 40):
+        C = rng.integers(-300, 3000, (n, n)).astype(np.int32)
+        plan, cost, u, v = oracle.assign_scaled(C, 1)
+        _, opt, _, _ = check_assign(C)
+        assert cost == opt
+        assert oracle.certify_assign(C, plan, u, v) == 0
+
+
+@pytest.mark.parametrize("s", [2, 3, 10, 1000])
+@pytest.mark.parametrize("kind", ["wide", "negative", "ties"])
+def test_scaled_bounds_against_brute_force(s, kind):
+    """sum(u)+sum(v) <= OPT <= cost <= sum(u)+sum(v) + n(s-1), duals feasible for C."""
+    rng = np.random.default_rng(7 * s + len(kind))
+    for n in (1, 2, 4, 6, 7):
+        if kind == "wide":
+            C = rng.integers(0, 100_000, (n, n))
+        elif kind == "negative":
+            C = rng.integers(-5_000, 5_000, (n, n))  # floor and truncation differ here
+        else:
+            C = rng.integers(0, 3 * s, (n, n))
+        C = C.astype(np.int32)
+        opt, _ = py_brute(C)
+        plan, cost, u, v = oracle.assign_scaled(C, s)
+        assert sorted(plan.tolist()) == list(range(n))
+        assert cost == sum(int(C[i, plan[i]]) for i in range(n))
+        assert (u[:, None] + v[None, :] <= C.astype(np.int64)).all()
+        lower = int(u.sum() + v.sum())
+        assert lower <= opt <= cost <= lower + n * (s - 1)
+        # the plan is exactly optimal for the scaled costs, certified by u/s, v/s
+        assert (u % s == 0).all() and (v % s == 0).all()
+        Cs = py_floor_scaled(C, s)
+        assert oracle.certify_assign(Cs, plan, u // s, v // s) == 0
+        assert sum(int(Cs[i, plan[i]]) for i in range(n)) == py_brute(Cs)[0]
+
+
+def test_scaled_exact_on_multiples():
+    """C = s * A: scaling loses nothing, the gap is zero and the cost is optimal."""
+    rng = np.random.default_rng(5)
+    s = 25
+    A = rng.integers(-40, 400, (30, 30))
+    C = (s * A).astype(np.int32)
+    plan, cost, u, v = oracle.assign_scaled(C, s)
+    _, opt, _, _ = check_assign(C)
+    assert cost == opt == int(u.sum() + v.sum())
+
+
 def test_brute_force_n8_extreme_values():
     rng = np.random.default_rng(8)
     C = rng.integers(-(2**30), 2**30, (8, 8)).astype(np.int32)
