@@ -97,6 +97,11 @@ struct Problem {
   const int32_t *Cout;  // costs the reported total is taken over (row stride ldo), or null for C
   int ldo;
   int dscale;         // reported duals are dscale * (duals of C); 1 unless C holds scaled-down costs
+  // Optional results of the grid-wide initial sweeps (k_init_rows / k_init_cols /
+  // k_init_merge), or null to run them inside the workgroup:
+  const int64_t *init_u;     // [n] row minima u_i = min_j C_ij
+  const uint64_t *init_b;    // [n][2] per column the two smallest keys pack(C_ij - u_i, i)
+  const int32_t *init_rmax;  // [n] row maxima (with the row minima: the cost range)
 
   int max_paths;      // 0 = all free rows
   int flags;          // OT_FLAG_* bits
@@ -513,8 +518,17 @@ struct Engine {
     if (tid < 8) red[tid] = kInf;
 
     // ---- initialisation: u_i = min_j C_ij (one wavefront per row) and the cost range
+    const bool pre = P.init_u && P.init_b && P.init_rmax;
     int gmin = 0x7fffffff, gmax = (int)0x80000000;
-    for (int i = wid; i < n; i += NW) {
+    if (pre) {
+      for (int i = tid; i < n; i += BLOCK) {
+        const int64_t mn = P.init_u[i];
+        hrow[i] = mn;
+        gmin = min(gmin, (int)mn);
+        gmax = max(gmax, P.init_rmax[i]);
+      }
+    }
+    for (int i = pre ? n : wid; i < n; i += NW) {
       const int32_t *row = C + (size_t)i * (size_t)ld;
       int mn = 0x7fffffff, mx = (int)0x80000000;
       for (int j0 = 0; j0 < n; j0 += 64 * 16) {
@@ -565,8 +579,11 @@ struct Engine {
     {
       uint64_t b1[CPT], b2[CPT];
 #pragma unroll
-      for (int k = 0; k < CPT; ++k) { b1[k] = kInf; b2[k] = kInf; }
-      int i = 0;
+      for (int k = 0; k < CPT; ++k) {
+        b1[k] = pre ? P.init_b[2 * (size_t)lcol(k)] : kInf;
+        b2[k] = pre ? P.init_b[2 * (size_t)lcol(k) + 1] : kInf;
+      }
+      int i = pre ? n : 0;
       for (; i + 4 <= n; i += 4) {
         int32_t c[4][CPT];
 #pragma unroll

@@ -55,6 +55,7 @@ __global__ __launch_bounds__(BLOCK) void k_assign_batch(BatchArgs A) {
     P.Cout = nullptr;
     P.ldo = n;
     P.dscale = 1;
+    P.init_u = nullptr; P.init_b = nullptr; P.init_rmax = nullptr;
     P.max_paths = A.max_paths;
     P.flags = 0;
     P.plan = A.plan + A.voff[k];
@@ -74,6 +75,100 @@ __global__ __launch_bounds__(BLOCK) void k_assign_batch(BatchArgs A) {
     }
     __syncthreads();
   }
+}
+
+// ---------------------------------------------------------------------------
+// grid-wide initial sweeps of one instance (the two full passes over C that the
+// KM reduction needs: row minima, then per column the two smallest C_ij - u_i)
+// ---------------------------------------------------------------------------
+// u_i = min_j C_ij and rmax_i = max_j C_ij, one wavefront per row (the cost
+// range min_i u_i .. max_i rmax_i is reduced by the solver; no global atomics).
+__global__ __launch_bounds__(256) void k_init_rows(const int32_t *C, int n, int ld, int64_t *u, int32_t *rmax) {
+  const int lane = threadIdx.x & 63;
+  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (i >= n) return;
+  const int32_t *row = C + (size_t)i * (size_t)ld;
+  int mn = 0x7fffffff, mx = (int)0x80000000;
+  if ((ld & 3) == 0 && ((uintptr_t)C & 15) == 0) {
+    // 16-byte loads: four columns per lane per step, two steps in flight
+    int j = lane * 4;
+    for (; j + 256 + 3 < n; j += 512) {
+      const int4 a = *(const int4 *)(row + j);
+      const int4 b = *(const int4 *)(row + j + 256);
+      mn = min(mn, min(min(min(a.x, a.y), min(a.z, a.w)), min(min(b.x, b.y), min(b.z, b.w))));
+      mx = max(mx, max(max(max(a.x, a.y), max(a.z, a.w)), max(max(b.x, b.y), max(b.z, b.w))));
+    }
+    for (; j + 3 < n; j += 256) {
+      const int4 a = *(const int4 *)(row + j);
+      mn = min(mn, min(min(a.x, a.y), min(a.z, a.w)));
+      mx = max(mx, max(max(a.x, a.y), max(a.z, a.w)));
+    }
+    for (int t = j; t < n && t < j + 4; ++t) { mn = min(mn, row[t]); mx = max(mx, row[t]); }
+  } else {
+    for (int t = lane; t < n; t += 64) { mn = min(mn, row[t]); mx = max(mx, row[t]); }
+  }
+  mn = wave_min_i32(mn);
+  mx = wave_max_i32(mx);
+  if (lane == 0) {
+    u[i] = mn;
+    rmax[i] = mx;
+  }
+}
+
+__device__ __forceinline__ void two_smallest(uint64_t &b1, uint64_t &b2, uint64_t key) {
+  const bool l1 = key < b1, l2 = key < b2;
+  b2 = l1 ? b1 : (l2 ? key : b2);
+  b1 = l1 ? key : b1;
+}
+
+// Partial top-2 per column over one slice of kInitSliceRows rows:
+// part[(y * n + j) * 2 + {0,1}] = the two smallest pack(C_ij - u_i, i), i in
+// slice y.  A workgroup covers 64 columns; its four wavefronts split the slice
+// (each row a coalesced 256-byte read) and merge through LDS.
+constexpr int kInitSliceRows = 128;
+__global__ __launch_bounds__(256) void k_init_cols(const int32_t *C, int n, int ld, const int64_t *u,
+                                                   uint64_t *part) {
+  __shared__ uint64_t sb[4][64][2];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int j = blockIdx.x * 64 + lane;
+  const int jc = j < n ? j : n - 1;
+  const int i0 = blockIdx.y * kInitSliceRows + w * (kInitSliceRows / 4);
+  const int i1 = min(n, i0 + kInitSliceRows / 4);
+  uint64_t b1 = kInf, b2 = kInf;
+  int i = i0;
+  for (; i + 8 <= i1; i += 8) {
+    int32_t c[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) c[q] = C[(size_t)(i + q) * (size_t)ld + jc];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) two_smallest(b1, b2, pack((int64_t)c[q] - u[i + q], i + q));
+  }
+  for (; i < i1; ++i) two_smallest(b1, b2, pack((int64_t)C[(size_t)i * (size_t)ld + jc] - u[i], i));
+  sb[w][lane][0] = b1;
+  sb[w][lane][1] = b2;
+  __syncthreads();
+  if (w == 0 && j < n) {
+#pragma unroll
+    for (int v = 1; v < 4; ++v) {
+      two_smallest(b1, b2, sb[v][lane][0]);
+      two_smallest(b1, b2, sb[v][lane][1]);
+    }
+    part[((size_t)blockIdx.y * n + j) * 2] = b1;
+    part[((size_t)blockIdx.y * n + j) * 2 + 1] = b2;
+  }
+}
+
+// b[j][0..1] = the two smallest keys of column j over all slices.
+__global__ __launch_bounds__(256) void k_init_merge(const uint64_t *part, int slices, int n, uint64_t *b) {
+  const int j = blockIdx.x * 256 + threadIdx.x;
+  if (j >= n) return;
+  uint64_t b1 = kInf, b2 = kInf;
+  for (int y = 0; y < slices; ++y) {
+    two_smallest(b1, b2, part[((size_t)y * n + j) * 2]);
+    two_smallest(b1, b2, part[((size_t)y * n + j) * 2 + 1]);
+  }
+  b[2 * (size_t)j] = b1;
+  b[2 * (size_t)j + 1] = b2;
 }
 
 // CT = C^T (n x n, row stride n) from C (row stride ld): 64 x 64 tiles through
@@ -345,6 +440,7 @@ hipError_t launch_transport(const TransportArgs &T, int block, hipStream_t s) {
   Problem P;
   P.C = T.Cx; P.n = T.S; P.ld = T.S; P.max_paths = T.max_paths; P.flags = 0; P.CT = T.CxT;
   P.Cout = nullptr; P.ldo = T.S; P.dscale = 1;
+  P.init_u = nullptr; P.init_b = nullptr; P.init_rmax = nullptr;
   P.plan = T.plan; P.cost = T.cost; P.u = T.U; P.v = T.V; P.stats = T.stats; P.ws = T.ws;
   if ((e = launch_assign_one(P, block, T.gate, s)) != hipSuccess) return e;
   if ((e = launch_fill_i32(T.X, 0, (int64_t)T.n * T.m, s)) != hipSuccess) return e;
@@ -360,6 +456,22 @@ hipError_t launch_transport(const TransportArgs &T, int block, hipStream_t s) {
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(k_tr_duals_zero_cols, dim3((T.m + 255) / 256), dim3(256), 0, s, T.C, T.c, T.n, T.m, T.u, T.v,
                      T.gate, T.stats);
+  return hipGetLastError();
+}
+
+size_t init_part_bytes(int n) {
+  return (size_t)((n + kInitSliceRows - 1) / kInitSliceRows) * (size_t)n * 16;
+}
+
+hipError_t launch_init_sweeps(const int32_t *C, int n, int ld, int64_t *u, int32_t *rmax, uint64_t *part,
+                              uint64_t *b, hipStream_t st) {
+  hipError_t e;
+  hipLaunchKernelGGL(k_init_rows, dim3((n + 3) / 4), dim3(256), 0, st, C, n, ld, u, rmax);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  const int slices = (n + kInitSliceRows - 1) / kInitSliceRows;
+  hipLaunchKernelGGL(k_init_cols, dim3((n + 63) / 64, slices), dim3(256), 0, st, C, n, ld, u, part);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_init_merge, dim3((n + 255) / 256), dim3(256), 0, st, part, slices, n, b);
   return hipGetLastError();
 }
 

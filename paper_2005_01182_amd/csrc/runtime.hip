@@ -226,9 +226,16 @@ int ot_assign_ex(const int32_t *C, int32_t n, const ot_options *opt, int32_t *pl
     dsolve = dCs;
   }
   if ((e = launch_transpose(dsolve, n, n, dCT, s)) != hipSuccess) return map_hip(e);
+  auto *du0 = (int64_t *)pool_get(80, 8 * N, &err);
+  auto *drmax = (int32_t *)pool_get(81, 4 * N, &err);
+  auto *dpart = (uint64_t *)pool_get(82, init_part_bytes(n), &err);
+  auto *db = (uint64_t *)pool_get(83, 16 * N, &err);
+  if (err) return err;
+  if ((e = launch_init_sweeps(dsolve, n, n, du0, drmax, dpart, db, s)) != hipSuccess) return map_hip(e);
   Problem P;
   P.C = dsolve; P.n = n; P.ld = n; P.CT = dCT; P.max_paths = max_paths; P.flags = flags;
   P.Cout = dC; P.ldo = n; P.dscale = scale;
+  P.init_u = du0; P.init_b = db; P.init_rmax = drmax;
   P.plan = dplan; P.cost = dcost; P.u = du; P.v = dv; P.stats = dstats; P.ws = dws;
   if ((e = launch_assign_one(P, block, nullptr, s)) != hipSuccess) return map_hip(e);
   ot_stats hs;
@@ -278,9 +285,16 @@ int ot_assign_dev(const int32_t *dC, int32_t n, int32_t ld, const ot_options *op
     lds = n;
   }
   if ((e = launch_transpose(dsolve, n, lds, dCT, s)) != hipSuccess) return map_hip(e);
+  auto *du0 = (int64_t *)stream_ws(s, 40, 8 * (size_t)n, &err);
+  auto *drmax = (int32_t *)stream_ws(s, 41, 4 * (size_t)n, &err);
+  auto *dpart = (uint64_t *)stream_ws(s, 42, init_part_bytes(n), &err);
+  auto *db = (uint64_t *)stream_ws(s, 43, 16 * (size_t)n, &err);
+  if (err) return err;
+  if ((e = launch_init_sweeps(dsolve, n, lds, du0, drmax, dpart, db, s)) != hipSuccess) return map_hip(e);
   Problem P;
   P.C = dsolve; P.n = n; P.ld = lds; P.CT = dCT; P.max_paths = max_paths; P.flags = flags;
   P.Cout = dC; P.ldo = ld; P.dscale = scale;
+  P.init_u = du0; P.init_b = db; P.init_rmax = drmax;
   P.plan = dplan; P.cost = dcost; P.u = du; P.v = dv; P.stats = dstats; P.ws = dws;
   return map_hip(launch_assign_one(P, block, nullptr, s));
 }

@@ -102,14 +102,21 @@ def kernel_source_sha():
 
 
 def counter_avg(path, kernel, counter, skip=0):
-    """Average of one counter per dispatch of the kernels whose name contains `kernel`."""
+    """Per-launch value of one counter: for every kernel whose name contains
+    `kernel`, the average per dispatch; summed over those kernels (each kernel
+    of a solve runs once per solve).  Returns (value, dispatches of the most
+    frequent kernel)."""
     db = sqlite3.connect(path)
     rows = db.execute("select dispatch_id, kernel_name, sum(value) from counters_collection "
                       "where counter_name = ? group by dispatch_id order by dispatch_id", (counter,)).fetchall()
-    vals = [v for _, name, v in rows if kernel in name][skip:]
-    if not vals:
+    per = defaultdict(list)
+    for _, name, v in rows:
+        if kernel in name:
+            per[name].append(v)
+    per = {k: v[skip:] for k, v in per.items() if v[skip:]}
+    if not per:
         raise SystemExit("%s: no %s samples for kernels matching %r" % (path, counter, kernel))
-    return sum(vals) / len(vals), len(vals)
+    return sum(sum(v) / len(v) for v in per.values()), max(len(v) for v in per.values())
 
 
 def traffic(a):
@@ -152,6 +159,23 @@ def read_traffic(path):
     return rec if len(rec) == 2 else None
 
 
+def bandwidth(path, specs, skip=0, peak_gbs=8000.0):
+    """GB/s of kernels whose bytes per dispatch are given as NAME=BYTES."""
+    db = sqlite3.connect(path)
+    kv = _view_with(db, {"name", "duration", "start", "dispatch_id", "grid_x"})
+    rows = db.execute("select name, duration from %s order by start" % kv).fetchall()
+    out = ["| kernel | bytes per dispatch | avg us | GB/s | of %.0f GB/s |" % peak_gbs, "|---|---|---|---|---|"]
+    for spec in specs:
+        name, nbytes = spec.split("=")
+        d = [t for k, t in rows if name in k][skip:]
+        if not d:
+            continue
+        us = sum(d) / len(d) / 1e3
+        gbs = float(nbytes) / (us * 1e-6) / 1e9
+        out.append("| %s | %d | %.2f | %.0f | %.1f%% |" % (name, int(float(nbytes)), us, gbs, 100 * gbs / peak_gbs))
+    return "\n".join(out)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("db", nargs="*")
@@ -164,6 +188,8 @@ def main():
     ap.add_argument("--copy-write")
     ap.add_argument("--copy-kernel", default="elementwise")
     ap.add_argument("--copy-bytes", type=float, default=0)
+    ap.add_argument("--bw", action="append", default=[],
+                    help="NAME=BYTES: bytes one dispatch of kernels matching NAME moves (adds a GB/s table)")
     a = ap.parse_args()
     if a.traffic:
         print(traffic(a))
@@ -172,6 +198,9 @@ def main():
         print("### %s\n" % p)
         print(summarise(p, a.kernel, a.skip))
         print()
+        if a.bw:
+            print(bandwidth(p, a.bw, a.skip))
+            print()
 
 
 if __name__ == "__main__":

@@ -231,3 +231,47 @@ def test_scaled_device_api_with_row_stride(otkm_gpu):
     check_scaled(C, s, plan.cpu().numpy(), int(cost.item()), u.cpu().numpy(), v.cpu().numpy())
     ref = otkm_gpu.ot_assign(C, scale=s)
     assert int(cost.item()) == ref[1]
+
+
+# ----------------------------------------------------------------------------- grid-wide initial sweeps
+def test_device_range_error_reported(otkm_gpu):
+    """Device calls check the cost range on the device (from the initial row sweep)."""
+    import torch
+    C = np.zeros((70, 70), np.int32)
+    C[3, 4] = -2**31
+    C[5, 6] = 2**31 - 1
+    dC = torch.from_numpy(C).cuda()
+    plan = torch.empty(70, dtype=torch.int32, device="cuda")
+    cost = torch.empty(1, dtype=torch.int64, device="cuda")
+    st = otkm_gpu.stats_tensor()
+    otkm_gpu.ot_assign_dev(dC, plan, cost, stats=st[0])
+    torch.cuda.synchronize()
+    assert int(st[0, 7]) == otkm_gpu.OT_ERANGE
+
+
+@pytest.mark.parametrize("n", [1, 3, 63, 257, 1000, 2049])
+def test_grid_init_matches_in_workgroup_init(otkm_gpu, n):
+    """Single-instance calls take u and the initial column keys from the grid-wide
+    sweeps; the batched kernel computes them inside the workgroup.  Results must be
+    bit-identical (same plan, same duals)."""
+    C = wl.geometric_assignment(n, seed=400 + n) if n > 3 else wl.uniform_assignment(n, seed=n)
+    say("case grid init n=%d" % n)
+    a = otkm_gpu.ot_assign(C)
+    b = otkm_gpu.ot_assign_batch([C])[0]
+    assert a[1] == b[1]
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[2], b[2]) and np.array_equal(a[3], b[3])
+
+
+def test_grid_init_unaligned_rows(otkm_gpu):
+    """A matrix view whose rows are not 16-byte aligned (odd stride, odd offset)."""
+    import torch
+    n, ld = 301, 303
+    C = wl.uniform_assignment(n, seed=77)
+    buf = torch.zeros(n * ld + 1, dtype=torch.int32, device="cuda")
+    view = buf[1:].view(n, ld)
+    view[:, :n] = torch.from_numpy(C).cuda()
+    plan = torch.empty(n, dtype=torch.int32, device="cuda")
+    cost = torch.empty(1, dtype=torch.int64, device="cuda")
+    otkm_gpu.ot_assign_dev(view, plan, cost, ld=ld)
+    torch.cuda.synchronize()
+    assert int(cost.item()) == oracle.assign(C)[1]
