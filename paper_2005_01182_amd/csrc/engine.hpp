@@ -190,7 +190,9 @@ __device__ __forceinline__ void top2_merge(uint64_t &a1, int &ta1, uint64_t &a2,
 
 __device__ __forceinline__ int64_t now_ticks() { return (int64_t)wall_clock64(); }
 
-template <int BLOCK, int CPT>
+// LONG: also sweep long frontiers in chunks of 2U rows (more registers; used by
+// the one-instance kernel, where occupancy does not matter).
+template <int BLOCK, int CPT, bool LONG = false>
 struct Engine {
   static constexpr int NW = BLOCK / 64;
 
@@ -213,9 +215,6 @@ struct Engine {
   // v_j lies in [-R, R] and the level at which a column is reached in [0, R]
   // (R = max C - min C < 2^31), so both fit 32 bits.
   int32_t vj[CPT], dcol[CPT];
-  // k1 / k2 values saturated to 32 bits: a candidate above lim2, or above lim1
-  // from the best key's own tree, cannot change the column's top-2
-  uint32_t lim1[CPT], lim2[CPT];
   bool narrow;          // cost range below 2^30
   uint32_t vis;   // bit k: column k has been reached (is in a tree)
   uint32_t stl;   // bit k: k1 is only a lower bound (its tree is gone)
@@ -236,28 +235,22 @@ struct Engine {
     if (ok) stl &= ~(1u << k); else stl |= 1u << k;
   }
 
-  __device__ __forceinline__ void sync_lim(int k) {
-    const int64_t v1 = kval(k1[k]), v2 = kval(k2[k]);
-    lim1[k] = v1 > 0xffffffffll ? 0xffffffffu : (uint32_t)v1;
-    lim2[k] = v2 > 0xffffffffll ? 0xffffffffu : (uint32_t)v2;
-  }
-
   // Fold cost rows list[0..cnt) (forest rows; rows no longer in the forest
   // are skipped) into every owned column's top-2 keys.  Rows go in chunks of U
   // whose loads are all issued before any is used, so a short frontier costs
-  // one memory latency.  Each chunk first tests every (row, column) candidate
-  // against the column's second key without branching; only (row, column)
-  // slots where some lane of the wavefront passes take the exact update.
-  // With NARROW (cost range below 2^30) every key value is below 2^32: the
-  // test runs in 32-bit modular arithmetic, which is exact there, and the
-  // update is select-only (no divergent branches, which cost more than they
-  // save when a few lanes pass).  Returns rows used.
+  // one memory latency.  With NARROW (cost range below 2^30) every key value
+  // is below 2^32, so reduced costs are formed in 32-bit modular arithmetic
+  // (exact there) and each chunk is reduced to its own top-2 per column before
+  // one merge.  Returns rows used.
   static constexpr int U = CPT >= 8 ? 2 : 16 / CPT > 8 ? 8 : 16 / CPT;
+  static constexpr int UB = 2 * U > 16 ? 16 : 2 * U;  // long-frontier chunk (UB * CPT <= 32 pass bits)
   static constexpr int GU = 8;  // forest rows in flight per lane when recomputing a stale column
-  template <bool NARROW>
-  __device__ __forceinline__ int sweep_t(const int32_t *list, int cnt) {
+  // One chunk of UU rows list[f .. f+UU) (slots past cnt are skipped).
+  template <bool NARROW, int UU>
+  __device__ __forceinline__ int sweep_chunk(const int32_t *list, int f, int cnt) {
     int used = 0;
-    for (int f = 0; f < cnt; f += U) {
+    {
+      constexpr int U = UU;
       int r[U], t[U];
       int64_t h[U];
       int32_t c[U][CPT];
@@ -274,61 +267,81 @@ struct Engine {
 #pragma unroll
         for (int k = 0; k < CPT; ++k) c[q][k] = row[lcol(k)];
       }
-      uint32_t pass = 0;
-      uint32_t v32[U][CPT];  // NARROW: exact key values of the candidates
 #pragma unroll
-      for (int q = 0; q < U; ++q) {
-        used += t[q] >= 0;
+      for (int q = 0; q < U; ++q) used += t[q] >= 0;
+      if (NARROW) {
+        // Per column: the exact top-2 of this chunk's candidates (the best, then
+        // the best from another tree), merged once into the column's top-2.
+        // Select-only: a few lanes of a wavefront improve a key in a typical
+        // chunk, and divergent branches cost more than they skip.
+        uint32_t clr = 0;
 #pragma unroll
         for (int k = 0; k < CPT; ++k) {
-          bool p;
-          if (NARROW) {
+          uint64_t key[U];
+          uint64_t b1 = kInf, b2 = kInf;
+          int tb1 = -1, tb2 = -1;
+#pragma unroll
+          for (int q = 0; q < U; ++q) {
+            // exact: every key value is below 2^32 here, so 32-bit wrap-around cannot occur
             const uint32_t v = (uint32_t)c[q][k] - ((uint32_t)h[q] + (uint32_t)vj[k]);
-            v32[q][k] = v;
-            p = v <= lim2[k];
-          } else {
-            const int64_t v = (int64_t)c[q][k] - h[q] - vj[k];
-            p = v <= kval(k2[k]);
+            const bool ok = (t[q] >= 0) & (col(k) < n);
+            key[q] = ok ? (((uint64_t)v << kRowBits) | (uint32_t)r[q]) : kInf;
+            const bool lt = key[q] < b1;
+            b1 = lt ? key[q] : b1;
+            tb1 = lt ? t[q] : tb1;
           }
+#pragma unroll
+          for (int q = 0; q < U; ++q) {
+            const bool ok = (t[q] != tb1) & (key[q] < b2);
+            b2 = ok ? key[q] : b2;
+            tb2 = ok ? t[q] : tb2;
+          }
+          // merge (b1, tb1, b2, tb2) into (k1, t1, k2, t2): the smaller best
+          // wins, and the second is the better of the loser's best (when it
+          // is from another tree) or its second, and the winner's second
+          const bool sw = b1 < k1[k];
+          const uint64_t x1 = sw ? b1 : k1[k], x2 = sw ? b2 : k2[k];
+          const int tx1 = sw ? tb1 : t1[k], tx2 = sw ? tb2 : t2[k];
+          const uint64_t y1 = sw ? k1[k] : b1, y2 = sw ? k2[k] : b2;
+          const int ty1 = sw ? t1[k] : tb1, ty2 = sw ? t2[k] : tb2;
+          const bool d = ty1 != tx1;
+          const uint64_t cc = d ? y1 : y2;
+          const int tc = d ? ty1 : ty2;
+          const bool lt = cc < x2;
+          k1[k] = x1; t1[k] = tx1;
+          k2[k] = lt ? cc : x2; t2[k] = lt ? tc : tx2;
+          clr |= sw ? (1u << k) : 0u;  // best key now from a live tree
+        }
+        stl &= ~clr;
+        return used;
+      }
+      // Wide cost range: filter against the second key without branching,
+      // then exact 64-bit updates on the (rare) slots where some lane passes.
+      uint32_t pass = 0;
+#pragma unroll
+      for (int q = 0; q < U; ++q) {
+#pragma unroll
+        for (int k = 0; k < CPT; ++k) {
+          const int64_t v = (int64_t)c[q][k] - h[q] - vj[k];
+          const bool p = v <= kval(k2[k]);
           pass |= (p & (t[q] >= 0) & (col(k) < n)) ? (1u << (q * CPT + k)) : 0u;
         }
       }
       // Slots nobody in the wavefront needs are skipped with one scalar branch.
       if (__builtin_amdgcn_ballot_w64(pass != 0) != 0) {
-        uint32_t clr = 0, hit = 0;
+        uint32_t clr = 0;
 #pragma unroll
         for (int q = 0; q < U; ++q) {
 #pragma unroll
           for (int k = 0; k < CPT; ++k) {
             const bool p = (pass >> (q * CPT + k)) & 1u;
             if (__builtin_amdgcn_ballot_w64(p) == 0) continue;
-            if (NARROW) {
-              // select-only update (a failed slot offers kInf, which changes nothing)
-              const uint64_t key = p ? (((uint64_t)v32[q][k] << kRowBits) | (uint32_t)r[q]) : kInf;
-              const int tq = t[q];
-              const bool lt1 = key < k1[k];
-              const bool ch2 = (tq != t1[k]) & (key < k2[k]);
-              const uint64_t x = lt1 ? k1[k] : key;
-              const int tx = lt1 ? t1[k] : tq;
-              k2[k] = ch2 ? x : k2[k];
-              t2[k] = ch2 ? tx : t2[k];
-              k1[k] = lt1 ? key : k1[k];
-              t1[k] = lt1 ? tq : t1[k];
-              clr |= lt1 ? (1u << k) : 0u;  // best key now from a live tree
-              hit |= p ? (1u << k) : 0u;
-              continue;
-            }
             // Divergent from here on: typically a few lanes of the wavefront
             // take each branch, and a branch no lane takes is skipped whole.
             if (p) {
-              uint64_t key;
-              if (NARROW) {
-                key = ((uint64_t)v32[q][k] << kRowBits) | (uint32_t)r[q];
-              } else {
-                int64_t val = (int64_t)c[q][k] - h[q] - vj[k];
-                if (val < 0) { fail(OT_EINTERNAL); val = 0; }
-                key = pack(val, r[q]);
-              }
+              int64_t val = (int64_t)c[q][k] - h[q] - vj[k];
+              if (val < 0) { fail(OT_EINTERNAL); val = 0; }
+              const uint64_t key = pack(val, r[q]);
               const int tq = t[q];
               if (key < k1[k]) {
                 // new best; the old best stays second unless it is from the same tree
@@ -338,18 +351,27 @@ struct Engine {
               } else if (tq != t1[k] && key < k2[k]) {
                 k2[k] = key; t2[k] = tq;
               }
-              hit |= 1u << k;
             }
           }
         }
         stl &= ~clr;
-#pragma unroll
-        for (int k = 0; k < CPT; ++k)
-          if ((hit >> k) & 1u) sync_lim(k);
       }
     }
     return used;
   }
+
+  // Rows go in chunks of U, or of 2U while at least 2U rows remain: a short
+  // frontier pays one small chunk, a long one fewer, fuller chunks.
+  template <bool NARROW>
+  __device__ __forceinline__ int sweep_t(const int32_t *list, int cnt) {
+    int used = 0;
+    int f = 0;
+    if (LONG)
+      for (; f + UB <= cnt; f += UB) used += sweep_chunk<NARROW, UB>(list, f, cnt);
+    for (; f < cnt; f += U) used += sweep_chunk<NARROW, U>(list, f, cnt);
+    return used;
+  }
+
   __device__ __forceinline__ int sweep(const int32_t *list, int cnt) {
     return narrow ? sweep_t<true>(list, cnt) : sweep_t<false>(list, cnt);
   }
@@ -403,7 +425,7 @@ struct Engine {
     if (g > gcap) {
       // too many: one coalesced re-sweep of every forest row fixes all keys
 #pragma unroll
-      for (int k = 0; k < CPT; ++k) { k1[k] = kInf; k2[k] = kInf; t1[k] = -1; t2[k] = -1; sync_lim(k); }
+      for (int k = 0; k < CPT; ++k) { k1[k] = kInf; k2[k] = kInf; t1[k] = -1; t2[k] = -1; }
       stl = 0;
       swept = sweep(fst, nf);
       resweep = true;
@@ -478,7 +500,6 @@ struct Engine {
       const int s = slot[k];
       k1[k] = gk1[s]; t1[k] = gt1[s]; k2[k] = gk2[s]; t2[k] = gt2[s];
       stl &= ~(1u << k);
-      sync_lim(k);
     }
     return (int64_t)g * (int64_t)nf;
   }
@@ -573,8 +594,6 @@ struct Engine {
 #pragma unroll
     for (int k = 0; k < CPT; ++k) {
       k1[k] = kInf; k2[k] = kInf; t1[k] = -1; t2[k] = -1; vj[k] = 0; dcol[k] = 0; ctree[k] = -1;
-      lim1[k] = 0xffffffffu;
-      lim2[k] = 0xffffffffu;
     }
     {
       uint64_t b1[CPT], b2[CPT];
@@ -625,7 +644,6 @@ struct Engine {
           k1[k] = pack(0, krow(b1[k]));
           t1[k] = krow(b1[k]);
           if (b2[k] != kInf) { k2[k] = pack(kval(b2[k]) - vj[k], krow(b2[k])); t2[k] = krow(b2[k]); }
-          sync_lim(k);
         }
       }
     }
@@ -765,7 +783,6 @@ struct Engine {
           }
           if (nalive == 0) { k1[k] = kInf; k2[k] = kInf; t1[k] = -1; t2[k] = -1; }
           recompute_stale(k);
-          sync_lim(k);
         }
         if (tid == 0) ctl[FCNT] = 0;
         __syncthreads();
