@@ -142,6 +142,15 @@ __device__ __forceinline__ uint64_t wave_min_u64(uint64_t x) {
   x = umin64(x, dpp64<0x128>(x));  // row_ror:8
   return umin64(umin64(readlane64(x, 0), readlane64(x, 16)), umin64(readlane64(x, 32), readlane64(x, 48)));
 }
+__device__ __forceinline__ uint32_t wave_min_u32(uint32_t x) {
+  x = min(x, (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x121, 0xf, 0xf, false));  // row_ror:1
+  x = min(x, (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x122, 0xf, 0xf, false));  // row_ror:2
+  x = min(x, (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x124, 0xf, 0xf, false));  // row_ror:4
+  x = min(x, (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x128, 0xf, 0xf, false));  // row_ror:8
+  const uint32_t r0 = (uint32_t)__builtin_amdgcn_readlane((int)x, 0), r1 = (uint32_t)__builtin_amdgcn_readlane((int)x, 16);
+  const uint32_t r2 = (uint32_t)__builtin_amdgcn_readlane((int)x, 32), r3 = (uint32_t)__builtin_amdgcn_readlane((int)x, 48);
+  return min(min(r0, r1), min(r2, r3));
+}
 __device__ __forceinline__ int wave_min_i32(int x) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) x = min(x, __shfl_xor(x, off, 64));
@@ -379,19 +388,40 @@ struct Engine {
   // Workgroup minimum of valid / stale keys over unreached owned columns plus
   // the error code, into slot set `s` (u64 pair at red[2s], int at ctl[es]).
   // The slots must hold (kInf, kInf, 0) beforehand; the caller issues the barrier.
+  // Only key values are used downstream (the level, the refresh limit), so the
+  // slots receive value << kRowBits.  With NARROW every value is below 2^32 - 1
+  // and the wavefront reduction runs on 32-bit words.
   __device__ __forceinline__ void reduce_min(int s, int es) {
-    uint64_t a = kInf, b = kInf;
+    if (narrow) {
+      uint32_t a = 0xffffffffu, b = 0xffffffffu;
 #pragma unroll
-    for (int k = 0; k < CPT; ++k) {
-      if (col(k) >= n || ((vis >> k) & 1u)) continue;
-      if (stale(k)) b = umin64(b, k1[k]);
-      else a = umin64(a, k1[k]);
-    }
-    a = wave_min_u64(a);
-    b = wave_min_u64(b);
-    if (lane == 0) {
-      if (a != kInf) atomicMin((unsigned long long *)&red[2 * s], (unsigned long long)a);
-      if (b != kInf) atomicMin((unsigned long long *)&red[2 * s + 1], (unsigned long long)b);
+      for (int k = 0; k < CPT; ++k) {
+        const bool open = (col(k) < n) & !((vis >> k) & 1u);
+        const uint32_t v = open ? (uint32_t)kval(k1[k]) : 0xffffffffu;  // kInf maps to 0xffffffff
+        const bool st = stale(k);
+        a = st ? a : min(a, v);
+        b = st ? min(b, v) : b;
+      }
+      a = wave_min_u32(a);
+      b = wave_min_u32(b);
+      if (lane == 0) {
+        if (a != 0xffffffffu) atomicMin((unsigned long long *)&red[2 * s], (unsigned long long)a << kRowBits);
+        if (b != 0xffffffffu) atomicMin((unsigned long long *)&red[2 * s + 1], (unsigned long long)b << kRowBits);
+      }
+    } else {
+      uint64_t a = kInf, b = kInf;
+#pragma unroll
+      for (int k = 0; k < CPT; ++k) {
+        if (col(k) >= n || ((vis >> k) & 1u)) continue;
+        if (stale(k)) b = umin64(b, k1[k]);
+        else a = umin64(a, k1[k]);
+      }
+      a = wave_min_u64(a);
+      b = wave_min_u64(b);
+      if (lane == 0) {
+        if (a != kInf) atomicMin((unsigned long long *)&red[2 * s], (unsigned long long)a);
+        if (b != kInf) atomicMin((unsigned long long *)&red[2 * s + 1], (unsigned long long)b);
+      }
     }
     if (err_local != 0) atomicMin(&ctl[es], err_local);  // rare: only lanes that saw an error
   }
