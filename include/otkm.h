@@ -253,10 +253,13 @@ int ot_serve_close(ot_server *s);
 /* ------------------------------------------------------------------------ */
 
 /* The batch path picks a workgroup width per size class: n <= t64 uses one
- * wavefront (64 lanes), n <= t256 uses 256 lanes, larger n uses 1024 lanes.
+ * wavefront (64 lanes), n <= t256 uses 256 lanes, larger n uses 512 lanes.
  * ot_schedule_get returns the thresholds in force; ot_schedule_set overrides
  * them (0 restores the default); ot_schedule_tune times synthetic instances
- * on the device and sets them (returns OT_OK or an error). */
+ * on the device and sets them (returns OT_OK or an error).  Each of its probes
+ * holds reps times as many instances as the chip has workgroup slots at the
+ * narrowest width (capped at 1 GiB of costs), so it ranks widths by
+ * throughput; reps < 1 counts as 1. */
 int ot_schedule_get(int32_t *t64, int32_t *t256);
 int ot_schedule_set(int32_t t64, int32_t t256);
 int ot_schedule_tune(int32_t reps);

@@ -2,8 +2,11 @@
 //
 // For a ladder of instance sizes, time the persistent batch kernel at each
 // eligible workgroup width (64, 256, 512 lanes) on synthetic instances and
-// keep, per size, the width with the highest instance throughput.  The
-// thresholds are the largest sizes up to which the narrower widths win.
+// keep, per size, the width with the highest instance throughput.  Each probe
+// holds enough instances to fill every workgroup slot of the chip several
+// times over at the narrowest width, so it measures throughput rather than the
+// latency of one wave of instances.  The thresholds are the largest sizes up to
+// which the narrower widths win.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -56,13 +59,16 @@ extern "C" int ot_schedule_tune(int32_t reps) {
   if (rc) return rc;
   const int sizes[] = {32, 48, 64, 96, 128, 192, 256, 384, 512, 768, 1024};
   const int widths[] = {64, 256, 512};
-  const int64_t budget = 16ll << 20;  // cost entries per probe (64 MiB)
+  const int64_t budget = 256ll << 20;  // cost entries per probe (1 GiB)
   hipStream_t s = lib_stream();
   int best_w[sizeof(sizes) / sizeof(sizes[0])];
   uint64_t lcg = 0x9e3779b97f4a7c15ull;
   for (size_t si = 0; si < sizeof(sizes) / sizeof(sizes[0]); ++si) {
     const int n = sizes[si];
-    int count = (int)std::min<int64_t>(std::max(reps, 64) * 8, budget / ((int64_t)n * n));
+    int slots = 1;  // workgroup slots of the whole chip at the narrowest eligible width
+    for (int w : widths)
+      if (cpt_for(n, w) != 0) { slots = std::max(1, batch_occupancy(w, n)) * device_cus(); break; }
+    int count = (int)std::min<int64_t>((int64_t)std::max(reps, 1) * slots, budget / ((int64_t)n * n));
     count = std::max(count, 4);
     std::vector<int32_t> hC((size_t)count * n * n);
     for (auto &x : hC) {
