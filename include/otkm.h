@@ -216,7 +216,9 @@ int ot_grid_cost_dev(const int32_t *dsrc, const int32_t *ddst, int32_t n, int32_
 typedef struct ot_serve_cfg {
     int64_t hbm_budget_bytes;  /* device bytes admitted requests may hold; 0 = 8 GiB */
     int32_t max_inflight;      /* request slots (1..1024); 0 = 256; 1 = one request at a time */
-    int32_t streams;           /* 0 or 4: one stream per size class (n <= 128, 512, 2048, 4096) */
+    int32_t streams;           /* streams per size class (n <= 128, 512, 2048, 4096), 1..8; 0 = 1.
+                                  Each stream runs one group of admitted requests at a time, so up
+                                  to this many groups of one class overlap on the device */
     int32_t max_n;             /* largest n accepted (<= OT_MAX_N); 0 = OT_MAX_N */
     int32_t reserved[5];       /* must be zero */
 } ot_serve_cfg;

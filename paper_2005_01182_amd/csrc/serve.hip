@@ -32,6 +32,12 @@ using namespace otkm;
 namespace {
 
 constexpr int kClasses = 4;
+constexpr int kMaxLanesPerClass = 8;
+// One stream per class by default: on the serving workload (Poisson 2000/s,
+// n log-uniform in [32, 4096]) four streams per class halved the throughput
+// (1493 -> 752 solves/s): concurrent persistent kernels of one class split the
+// chip instead of draining one queue longest-first.
+constexpr int kDefaultLanesPerClass = 1;
 // size classes: (largest n, workgroup width)
 constexpr int kClassMaxN[kClasses] = {128, 512, 2048, OT_MAX_N};
 constexpr int kClassBlock[kClasses] = {64, 64, 256, 512};
@@ -57,7 +63,7 @@ struct Req {
   std::vector<int64_t> u, v;
 };
 
-struct Lane {  // one stream per size class
+struct Lane {  // one stream; each size class has cfg.streams of them
   hipStream_t s = nullptr;
   hipEvent_t ev = nullptr;
   bool busy = false;
@@ -86,7 +92,9 @@ struct ot_server {
   int32_t *h_plan = nullptr;                  // pinned [slots][maxn]
   int64_t *h_u = nullptr, *h_v = nullptr;     // pinned [slots][maxn]
   std::vector<int> free_slots;
-  Lane lanes[kClasses];
+  Lane lanes[kClasses * kMaxLanesPerClass];  // lane c * lpc + l: class c, stream l
+  int lpc = kDefaultLanesPerClass;
+  int nlanes() const { return kClasses * lpc; }
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
   std::deque<Req *> pending;
@@ -133,9 +141,10 @@ T *dptr(T *host) {  // device address of pinned host memory
   return (T *)d;
 }
 
-// Launch the group collected in lane c.  Requires s->mu.
-int launch_group(ot_server *s, int c) {
-  Lane &L = s->lanes[c];
+// Launch the group collected in lane li.  Requires s->mu.
+int launch_group(ot_server *s, int li) {
+  Lane &L = s->lanes[li];
+  const int c = li / s->lpc;
   const int G = (int)L.group.size();
   const size_t M = (size_t)s->maxn;
   hipError_t e;
@@ -143,7 +152,7 @@ int launch_group(ot_server *s, int c) {
   for (int k = 0; k < G; ++k) {
     Req *r = L.group[k];
     r->pos = k;
-    r->stream = c;
+    r->stream = li;
     r->tag = L.tag;
     max_n = std::max(max_n, r->n);
     int32_t *hp = s->h_pts + (size_t)r->slot * 4 * M;
@@ -217,8 +226,8 @@ bool retire(ot_server *s) {
     s->running.pop_back();
     changed = true;
   }
-  for (int c = 0; c < kClasses; ++c) {
-    Lane &L = s->lanes[c];
+  for (int li = 0; li < s->nlanes(); ++li) {
+    Lane &L = s->lanes[li];
     if (!L.busy) continue;
     if (hipEventQuery(L.ev) != hipSuccess) continue;
     if (L.outstanding > 0) continue;  // the flags of a finished kernel are visible on the next pass
@@ -231,12 +240,17 @@ bool retire(ot_server *s) {
 // Admit queued requests into free lanes and launch them.  Requires s->mu.
 bool admit(ot_server *s) {
   bool any = false;
-  bool lane_open[kClasses];
-  for (int c = 0; c < kClasses; ++c) lane_open[c] = !s->lanes[c].busy;
+  // this round's target lane of each class: its first idle stream, if any
+  int target[kClasses];
+  for (int c = 0; c < kClasses; ++c) {
+    target[c] = -1;
+    for (int l = 0; l < s->lpc && target[c] < 0; ++l)
+      if (!s->lanes[c * s->lpc + l].busy) target[c] = c * s->lpc + l;
+  }
   int scanned = 0;
   for (auto it = s->pending.begin(); it != s->pending.end() && scanned < 4096; ++scanned) {
     Req *r = *it;
-    if (!lane_open[r->cls]) { ++it; continue; }
+    if (target[r->cls] < 0) { ++it; continue; }
     if (s->free_slots.empty() || s->inflight >= s->cfg.max_inflight) break;
     if (s->inflight_bytes + r->bytes > s->cfg.hbm_budget_bytes) { ++it; continue; }
     const int64_t abytes = 4ll * r->n * r->n;
@@ -252,16 +266,17 @@ bool admit(ot_server *s) {
     s->ctr.peak_inflight_bytes = std::max(s->ctr.peak_inflight_bytes, s->inflight_bytes);
     s->ctr.peak_inflight = std::max<int64_t>(s->ctr.peak_inflight, s->inflight);
     ++s->ctr.admitted;
-    s->lanes[r->cls].group.push_back(r);
+    s->lanes[target[r->cls]].group.push_back(r);
     s->running.push_back(r);
     it = s->pending.erase(it);
     any = true;
   }
   for (int c = 0; c < kClasses; ++c) {
-    Lane &L = s->lanes[c];
-    if (!lane_open[c] || L.group.empty()) continue;
+    if (target[c] < 0) continue;
+    Lane &L = s->lanes[target[c]];
+    if (L.group.empty()) continue;
     ++L.tag;
-    const int rc = launch_group(s, c);
+    const int rc = launch_group(s, target[c]);
     if (rc != OT_OK) { s->fatal = rc; return any; }
   }
   return any;
@@ -308,11 +323,11 @@ int ot_serve_open(ot_server **out, const ot_serve_cfg *cfg_in) {
   for (int k = 0; k < 5; ++k)
     if (cfg.reserved[k] != 0) return OT_EINVAL;
   if (cfg.hbm_budget_bytes < 0 || cfg.max_inflight < 0 || cfg.max_inflight > 1024 || cfg.streams < 0 ||
-      (cfg.streams != 0 && cfg.streams != kClasses) || cfg.max_n < 0 || cfg.max_n > OT_MAX_N)
+      cfg.streams > kMaxLanesPerClass || cfg.max_n < 0 || cfg.max_n > OT_MAX_N)
     return OT_EINVAL;
   if (cfg.hbm_budget_bytes == 0) cfg.hbm_budget_bytes = 8ll << 30;
   if (cfg.max_inflight == 0) cfg.max_inflight = 256;
-  if (cfg.streams == 0) cfg.streams = kClasses;
+  if (cfg.streams == 0) cfg.streams = kDefaultLanesPerClass;
   if (cfg.max_n == 0) cfg.max_n = OT_MAX_N;
   if (request_bytes(cfg.max_n) > cfg.hbm_budget_bytes) return OT_ETOOBIG;
   {
@@ -336,8 +351,10 @@ int ot_serve_open(ot_server **out, const ot_serve_cfg *cfg_in) {
   chk(hipHostMalloc(&s->h_u, 8 * M * SL, hipHostMallocMapped | hipHostMallocCoherent));
   chk(hipHostMalloc(&s->h_v, 8 * M * SL, hipHostMallocMapped | hipHostMallocCoherent));
   const int ws_grid = std::min<int>(s->slots, 8 * s->cus);
-  for (int c = 0; c < kClasses && e == hipSuccess; ++c) {
-    Lane &L = s->lanes[c];
+  s->lpc = cfg.streams;
+  for (int li = 0; li < s->nlanes() && e == hipSuccess; ++li) {
+    const int c = li / s->lpc;
+    Lane &L = s->lanes[li];
     chk(hipStreamCreateWithFlags(&L.s, hipStreamNonBlocking));
     chk(hipEventCreateWithFlags(&L.ev, hipEventDisableTiming));
     chk(hipMalloc(&L.d_coff, 8 * SL)); chk(hipMalloc(&L.d_voff, 8 * SL));
@@ -357,7 +374,7 @@ int ot_serve_open(ot_server **out, const ot_serve_cfg *cfg_in) {
     free_server(s);
     return rc;
   }
-  for (auto &L : s->lanes) std::memset(L.h_done, 0, 4 * SL);
+  for (int li = 0; li < s->nlanes(); ++li) std::memset(s->lanes[li].h_done, 0, 4 * SL);
   s->arena.reset(new otkm::Arena(cfg.hbm_budget_bytes));
   for (int k = s->slots - 1; k >= 0; --k) s->free_slots.push_back(k);
   s->worker = std::thread(worker_main, s);

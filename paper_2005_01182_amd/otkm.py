@@ -300,11 +300,12 @@ def ot_grid_cost_dev(src, dst, C, stream=None):
 class Server:
     """Continuous-batching server (ot_serve_* calls)."""
 
-    def __init__(self, hbm_budget_bytes=0, max_inflight=0, max_n=0):
+    def __init__(self, hbm_budget_bytes=0, max_inflight=0, max_n=0, streams=0):
         cfg = ot_serve_cfg()
         cfg.hbm_budget_bytes = int(hbm_budget_bytes)
         cfg.max_inflight = int(max_inflight)
         cfg.max_n = int(max_n)
+        cfg.streams = int(streams)
         h = ctypes.c_void_p()
         _check(load().ot_serve_open(ctypes.byref(h), ctypes.byref(cfg)), "ot_serve_open")
         self._h = h

@@ -84,6 +84,7 @@ VALIDATION = textwrap.dedent(r"""
             return e.code
     out["serve_bad_slots"] = serve_code(max_inflight=5000)
     out["serve_bad_maxn"] = serve_code(max_n=5000)
+    out["serve_bad_streams"] = serve_code(streams=9)
     out["serve_budget_too_small"] = serve_code(hbm_budget_bytes=1000)
     out["serve_nodev"] = serve_code()
     print(repr(out))
@@ -128,5 +129,6 @@ def test_validation_codes(codes):
     assert codes["schedule_bad"] == -1
     assert codes["serve_bad_slots"] == -1
     assert codes["serve_bad_maxn"] == -1
+    assert codes["serve_bad_streams"] == -1
     assert codes["serve_budget_too_small"] == -5
     assert codes["serve_nodev"] == -8

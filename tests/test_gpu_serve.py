@@ -92,3 +92,19 @@ def test_serve_rejects_oversized(otkm_gpu):
         with pytest.raises(otkm_gpu.OtError) as e:
             srv.submit(s, d)
         assert e.value.code == otkm_gpu.OT_ETOOBIG
+
+
+def test_streams_per_class_do_not_change_results(otkm_gpu):
+    """One stream per size class and eight give the same results."""
+    rng = np.random.default_rng(5)
+    sizes = [40, 40, 300, 300, 700, 700, 1500, 40, 300]
+    reqs = [points(rng, n) for n in sizes]
+    out = []
+    for streams in (1, 8):
+        say("serving streams=%d" % streams)
+        with otkm_gpu.Server(streams=streams) as srv:
+            ids = [srv.submit(s, d) for s, d in reqs]
+            out.append([srv.poll(i, n) for i, n in zip(ids, sizes)])
+    for a, b in zip(*out):
+        assert a["status"] == 0 and b["status"] == 0 and a["cost"] == b["cost"]
+        assert np.array_equal(a["plan"], b["plan"]) and np.array_equal(a["u"], b["u"])
