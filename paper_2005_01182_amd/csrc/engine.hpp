@@ -251,8 +251,11 @@ struct Engine {
   // is below 2^32, so reduced costs are formed in 32-bit modular arithmetic
   // (exact there) and each chunk is reduced to its own top-2 per column before
   // one merge.  Returns rows used.
-  static constexpr int U = CPT >= 8 ? 2 : 16 / CPT > 8 ? 8 : 16 / CPT;
-  static constexpr int UB = 2 * U > 16 ? 16 : 2 * U;  // long-frontier chunk (UB * CPT <= 32 pass bits)
+  // Rows per chunk, measured on MI355X (geometric n = 512..4096): U * CPT = 8
+  // loads per lane (two rows at 4 columns per lane) beat 16 and 4 on the short
+  // frontiers that dominate; long frontiers take chunks of UB = 2U rows.
+  static constexpr int U = CPT >= 8 ? 2 : 8 / CPT;
+  static constexpr int UB = 2 * U * CPT > 32 ? 32 / CPT : 2 * U;  // UB * CPT <= 32 pass bits
   static constexpr int GU = 8;  // forest rows in flight per lane when recomputing a stale column
   // One chunk of UU rows list[f .. f+UU) (slots past cnt are skipped).
   template <bool NARROW, int UU>
@@ -369,8 +372,9 @@ struct Engine {
     return used;
   }
 
-  // Rows go in chunks of U, or of 2U while at least 2U rows remain: a short
-  // frontier pays one small chunk, a long one fewer, fuller chunks.
+  // Rows go in chunks of U, or (one-instance kernel) of UB while at least UB
+  // rows remain: a short frontier pays one small chunk, a long one fewer,
+  // fuller chunks.
   template <bool NARROW>
   __device__ __forceinline__ int sweep_t(const int32_t *list, int cnt) {
     int used = 0;

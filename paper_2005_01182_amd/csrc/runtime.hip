@@ -122,8 +122,8 @@ void schedule_set_locked(int t64, int t256) {
 
 // Single-instance width (measured on the geometric workload): one wavefront
 // needs no workgroup barrier and wins while its 8 columns per lane cover n;
-// then 8 wavefronts (n <= 2048) and 16 wavefronts (n <= 4096).
-int default_block(int n) { return n <= 512 ? 64 : n <= 2048 ? 512 : 1024; }
+// then 8 wavefronts (at n = 4096, 16 wavefronts have too few registers each).
+int default_block(int n) { return n <= 512 ? 64 : 512; }
 
 int schedule_block(int n) {
   const int t64 = g_t64 > 0 ? g_t64 : kDefaultT64;
