@@ -57,7 +57,7 @@ __host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~size_t(
 __host__ __device__ inline int gather_cap(int n) { return n / 16 < 32 ? 32 : n / 16; }
 
 struct LdsLayout {
-  size_t hrow, mrow, mcol, rtree, par, fst, fl0, fl1, alive, gcol, gv, gk1, gk2, gt1, gt2, red, ctl, total;
+  size_t hrow, mrow, mcol, rtree, par, fst, fr, alive, gcol, gv, gk1, gk2, gt1, gt2, red, ctl, total;
 };
 
 // Byte offsets of every LDS array for an instance of size n (host and device).
@@ -71,8 +71,7 @@ __host__ __device__ inline LdsLayout lds_layout(int n) {
   L.rtree = o; o = align16(o + 4 * N);
   L.par = o;   o = align16(o + 4 * N);
   L.fst = o;   o = align16(o + 4 * N);
-  L.fl0 = o;   o = align16(o + 4 * N);
-  L.fl1 = o;   o = align16(o + 4 * N);
+  L.fr = o;    o = align16(o + 8 * N);
   L.alive = o; o = align16(o + N);
   L.gcol = o;  o = align16(o + 4 * G);
   L.gv = o;    o = align16(o + 8 * G);
@@ -211,7 +210,8 @@ struct Engine {
   int n, ld;
   // LDS
   int64_t *hrow;
-  int32_t *mrow, *mcol, *rtree, *par, *fst, *fl0, *fl1, *gcol, *gt1, *gt2, *ctl;
+  int32_t *mrow, *mcol, *rtree, *par, *fst, *gcol, *gt1, *gt2, *ctl;
+  int2 *fr;  // frontier records of the next sweep: (row | tree << 16, low 32 bits of h)
   uint8_t *alive;
   int64_t *gv;
   uint64_t *gk1, *gk2, *red;
@@ -257,21 +257,35 @@ struct Engine {
   static constexpr int U = CPT >= 8 ? 2 : 8 / CPT;
   static constexpr int UB = 2 * U * CPT > 32 ? 32 / CPT : 2 * U;  // UB * CPT <= 32 pass bits
   static constexpr int GU = 8;  // forest rows in flight per lane when recomputing a stale column
-  // One chunk of UU rows list[f .. f+UU) (slots past cnt are skipped).
-  template <bool NARROW, int UU>
+  // One chunk of UU rows list[f .. f+UU) (slots past cnt are skipped).  REC:
+  // list holds frontier records (row, tree and the low word of h, written when
+  // the row joined, so no dependent LDS read of rtree / hrow is needed in the
+  // narrow case); otherwise plain row ids.
+  template <bool NARROW, int UU, bool REC>
   __device__ __forceinline__ int sweep_chunk(const int32_t *list, int f, int cnt) {
     int used = 0;
     {
       constexpr int U = UU;
       int r[U], t[U];
       int64_t h[U];
+      uint32_t h32[U];
       int32_t c[U][CPT];
 #pragma unroll
       for (int q = 0; q < U; ++q) {
-        r[q] = f + q < cnt ? list[f + q] : 0;
-        if ((unsigned)r[q] >= (unsigned)n) { fail(OT_EINTERNAL); r[q] = 0; }
-        t[q] = f + q < cnt ? rtree[r[q]] : -1;
-        h[q] = hrow[r[q]];
+        if (REC) {
+          const int2 e = ((const int2 *)list)[f + q < cnt ? f + q : cnt - 1];
+          r[q] = e.x & 0xffff;
+          if ((unsigned)r[q] >= (unsigned)n) { fail(OT_EINTERNAL); r[q] = 0; }
+          t[q] = (f + q < cnt && e.x >= 0) ? (e.x >> 16) : -1;  // sign bit: the row's tree has gone
+          h32[q] = (uint32_t)e.y;
+          h[q] = NARROW ? 0 : hrow[r[q]];
+        } else {
+          r[q] = f + q < cnt ? list[f + q] : 0;
+          if ((unsigned)r[q] >= (unsigned)n) { fail(OT_EINTERNAL); r[q] = 0; }
+          t[q] = f + q < cnt ? rtree[r[q]] : -1;
+          h[q] = hrow[r[q]];
+          h32[q] = (uint32_t)h[q];
+        }
       }
 #pragma unroll
       for (int q = 0; q < U; ++q) {
@@ -295,7 +309,7 @@ struct Engine {
 #pragma unroll
           for (int q = 0; q < U; ++q) {
             // exact: every key value is below 2^32 here, so 32-bit wrap-around cannot occur
-            const uint32_t v = (uint32_t)c[q][k] - ((uint32_t)h[q] + (uint32_t)vj[k]);
+            const uint32_t v = (uint32_t)c[q][k] - (h32[q] + (uint32_t)vj[k]);
             const bool ok = (t[q] >= 0) & (col(k) < n);
             key[q] = ok ? (((uint64_t)v << kRowBits) | (uint32_t)r[q]) : kInf;
             const bool lt = key[q] < b1;
@@ -375,18 +389,25 @@ struct Engine {
   // Rows go in chunks of U, or (one-instance kernel) of UB while at least UB
   // rows remain: a short frontier pays one small chunk, a long one fewer,
   // fuller chunks.
-  template <bool NARROW>
+  template <bool NARROW, bool REC>
   __device__ __forceinline__ int sweep_t(const int32_t *list, int cnt) {
     int used = 0;
     int f = 0;
     if (LONG)
-      for (; f + UB <= cnt; f += UB) used += sweep_chunk<NARROW, UB>(list, f, cnt);
-    for (; f < cnt; f += U) used += sweep_chunk<NARROW, U>(list, f, cnt);
+      for (; f + UB <= cnt; f += UB) used += sweep_chunk<NARROW, UB, REC>(list, f, cnt);
+    for (; f < cnt; f += U) used += sweep_chunk<NARROW, U, REC>(list, f, cnt);
     return used;
   }
 
   __device__ __forceinline__ int sweep(const int32_t *list, int cnt) {
-    return narrow ? sweep_t<true>(list, cnt) : sweep_t<false>(list, cnt);
+    return narrow ? sweep_t<true, false>(list, cnt) : sweep_t<false, false>(list, cnt);
+  }
+  __device__ __forceinline__ int sweep_frontier(int cnt) {
+    const int32_t *list = (const int32_t *)fr;
+    return narrow ? sweep_t<true, true>(list, cnt) : sweep_t<false, true>(list, cnt);
+  }
+  __device__ __forceinline__ static int2 frontier_rec(int row, int tree, int64_t h) {
+    return make_int2(row | (tree << 16), (int)(uint32_t)h);
   }
 
   // Workgroup minimum of valid / stale keys over unreached owned columns plus
@@ -549,8 +570,7 @@ struct Engine {
     rtree = (int32_t *)(smem + L.rtree);
     par = (int32_t *)(smem + L.par);
     fst = (int32_t *)(smem + L.fst);
-    fl0 = (int32_t *)(smem + L.fl0);
-    fl1 = (int32_t *)(smem + L.fl1);
+    fr = (int2 *)(smem + L.fr);
     alive = (uint8_t *)(smem + L.alive);
     gcol = (int32_t *)(smem + L.gcol);
     gv = (int64_t *)(smem + L.gv);
@@ -687,7 +707,7 @@ struct Engine {
       ctl[CNT0] = 0; ctl[CNT1] = 0; ctl[FCNT] = K;
     }
     if (K < n) {
-      for (int i = tid; i < K; i += BLOCK) fl0[i] = i;
+      for (int i = tid; i < K; i += BLOCK) fr[i] = frontier_rec(i, i, hrow[i]);
       if (tid == 0) ctl[CNT0] = K;
     }
     __syncthreads();
@@ -702,7 +722,7 @@ struct Engine {
       const int ps = cur;  // slot parity of this level
       // (1) fold the rows that joined last step into the keys
       const int nf = ctl[cur == 0 ? CNT0 : CNT1];
-      st_rows += sweep(cur == 0 ? fl0 : fl1, nf);
+      st_rows += sweep_frontier(nf);
       const int64_t t0 = timers ? now_ticks() : 0;
       tm_sweep += t0 - tprev;
       // (2) smallest key over unreached columns
@@ -738,7 +758,8 @@ struct Engine {
       tm_select += t1_ - t0;
 
       // (3) settle every unreached column at the current level
-      int32_t *nxt = cur == 0 ? fl1 : fl0;
+      // the next frontier overwrites this one: every wavefront finished
+      // reading it before the barrier above
       int *nxtcnt = &ctl[cur == 0 ? CNT1 : CNT0];
 #pragma unroll
       for (int k = 0; k < CPT; ++k) {
@@ -759,8 +780,9 @@ struct Engine {
         } else {
           // the matched row joins the tree (undone below if the tree augments now)
           rtree[mc] = tr;
-          hrow[mc] -= D;
-          nxt[atomicAdd(nxtcnt, 1)] = mc;
+          const int64_t hm = hrow[mc] - D;
+          hrow[mc] = hm;
+          fr[atomicAdd(nxtcnt, 1)] = frontier_rec(mc, tr, hm);
           fst[atomicAdd(&ctl[FCNT], 1)] = mc;
         }
       }
@@ -796,6 +818,11 @@ struct Engine {
           const int t = rtree[i];
           if (t >= 0 && !alive[t]) { hrow[i] += D; rtree[i] = -1; }
         }
+        // rows that joined this step in a tree that just finished leave the next sweep
+        for (int q = tid; q < *nxtcnt; q += BLOCK) {
+          const int2 e = fr[q];
+          if (e.x >= 0 && !alive[e.x >> 16]) fr[q].x = e.x | (int)0x80000000;
+        }
 #pragma unroll
         for (int k = 0; k < CPT; ++k) {
           if (col(k) >= n) continue;
@@ -830,8 +857,9 @@ struct Engine {
             const int r = cursor + q;
             rtree[r] = r;
             alive[r] = 1;
-            hrow[r] -= D;
-            nxt[atomicAdd(nxtcnt, 1)] = r;
+            const int64_t hr = hrow[r] - D;
+            hrow[r] = hr;
+            fr[atomicAdd(nxtcnt, 1)] = frontier_rec(r, r, hr);
             fst[atomicAdd(&ctl[FCNT], 1)] = r;
           }
           cursor += need;
