@@ -847,9 +847,19 @@ struct Engine {
         }
         if (tid == 0) ctl[FCNT] = 0;
         __syncthreads();
-        // (6) rebuild the forest list; with a tree cap, start new trees from the next free rows
-        for (int i = tid; i < n; i += BLOCK)
-          if (rtree[i] >= 0) fst[atomicAdd(&ctl[FCNT], 1)] = i;
+        // (6) rebuild the forest list (one LDS atomic per wavefront and 64 rows,
+        // each lane's slot from its rank among the lanes that keep a row); with
+        // a tree cap, start new trees from the next free rows
+        for (int i0 = wid * 64; i0 < n; i0 += BLOCK) {
+          const int i = i0 + lane;
+          const bool keep = i < n && rtree[i] >= 0;
+          const uint64_t m = __builtin_amdgcn_ballot_w64(keep);
+          int base = 0;
+          if (lane == 0 && m != 0) base = atomicAdd(&ctl[FCNT], (int)__builtin_popcountll(m));
+          base = __builtin_amdgcn_readfirstlane(base);
+          const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0));
+          if (keep) fst[base + rank] = i;
+        }
         const int need = min(K - nalive, n - cursor);
         if (need > 0) {
           __syncthreads();  // the scan above must not see the new roots
