@@ -260,8 +260,8 @@ int ot_serve_close(ot_server *s);
  * them (0 restores the default); ot_schedule_tune times synthetic instances
  * on the device and sets them (returns OT_OK or an error).  Each of its probes
  * holds reps times as many instances as the chip has workgroup slots at the
- * narrowest width (capped at 1 GiB of costs), so it ranks widths by
- * throughput; reps < 1 counts as 1. */
+ * narrowest width (their matrices cycle through at most 64 distinct ones), so
+ * it ranks widths by throughput; reps < 1 counts as 1. */
 int ot_schedule_get(int32_t *t64, int32_t *t256);
 int ot_schedule_set(int32_t t64, int32_t t256);
 int ot_schedule_tune(int32_t reps);

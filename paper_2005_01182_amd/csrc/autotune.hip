@@ -68,16 +68,19 @@ extern "C" int ot_schedule_tune(int32_t reps) {
     int slots = 1;  // workgroup slots of the whole chip at the narrowest eligible width
     for (int w : widths)
       if (cpt_for(n, w) != 0) { slots = std::max(1, batch_occupancy(w, n)) * device_cus(); break; }
-    int count = (int)std::min<int64_t>((int64_t)std::max(reps, 1) * slots, budget / ((int64_t)n * n));
-    count = std::max(count, 4);
-    std::vector<int32_t> hC((size_t)count * n * n);
+    // enough instances to fill every slot reps times over; they cycle through
+    // `distinct` matrices (instances only read their matrix), so the probe's
+    // memory stays bounded however many instances it holds
+    const int count = std::max(4, std::min(65536, std::max(reps, 1) * slots));
+    const int distinct = (int)std::max<int64_t>(1, std::min<int64_t>(std::min(count, 64), budget / ((int64_t)n * n)));
+    std::vector<int32_t> hC((size_t)distinct * n * n);
     for (auto &x : hC) {
       lcg = lcg * 6364136223846793005ull + 1442695040888963407ull;
       x = (int32_t)((lcg >> 33) % 10000);
     }
     std::vector<int64_t> coff(count), voff(count);
     std::vector<int32_t> nn(count, n);
-    for (int k = 0; k < count; ++k) { coff[k] = (int64_t)k * n * n; voff[k] = (int64_t)k * n; }
+    for (int k = 0; k < count; ++k) { coff[k] = (int64_t)(k % distinct) * n * n; voff[k] = (int64_t)k * n; }
     int err = OT_OK;
     auto *dC = (int32_t *)pool_get(60, 4 * hC.size(), &err);
     auto *dcoff = (int64_t *)pool_get(61, 8 * (size_t)count, &err);

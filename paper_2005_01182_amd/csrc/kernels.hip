@@ -29,8 +29,12 @@ __global__ __launch_bounds__(BLOCK) void k_assign_one(Problem P, const int32_t *
 // ---------------------------------------------------------------------------
 // persistent batch: each workgroup pops instance indices until the queue is empty
 // ---------------------------------------------------------------------------
+// Two wavefronts per SIMD: the register budget drops to 256 (a few bytes of
+// spill at 8 columns per lane) and twice as many instances share each CU, which
+// measured 126k -> 181k solves/s on the embedding batch; three or four per SIMD
+// spill heavily and lose.
 template <int BLOCK, int CPT>
-__global__ __launch_bounds__(BLOCK) void k_assign_batch(BatchArgs A) {
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2))) void k_assign_batch(BatchArgs A) {
   extern __shared__ __align__(16) char smem[];
   __shared__ int s_idx;
   int32_t *ws = A.ws + (size_t)blockIdx.x * ws_ints(A.max_n);

@@ -31,9 +31,9 @@ int g_t64 = 0, g_t256 = 0;  // 0 = defaults
 
 // Default size classes of the batch path, as ot_schedule_tune measured them on
 // MI355X (instance throughput with every workgroup slot busy): one wavefront
-// per instance up to n = 512, 256 lanes up to 768, 512 lanes above.
+// per instance up to n = 512, 256 lanes up to 1024, 512 lanes above.
 constexpr int kDefaultT64 = 512;
-constexpr int kDefaultT256 = 768;
+constexpr int kDefaultT256 = 1024;
 
 struct Buf {
   void *p = nullptr;

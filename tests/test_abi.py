@@ -124,7 +124,7 @@ def test_validation_codes(codes):
     assert codes["transport_range_zero_bins_ignored"] == -8
     assert codes["batch_nodev"] == -8
     assert codes["strerror"].startswith("supplies and demands")
-    assert codes["schedule"] == (512, 768)
+    assert codes["schedule"] == (512, 1024)
     assert codes["schedule_set"] == (100, 900)
     assert codes["schedule_bad"] == -1
     assert codes["serve_bad_slots"] == -1
