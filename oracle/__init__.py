@@ -12,6 +12,9 @@ Functions (all exact, int64 results):
 * ``certify_assign(C, plan, u, v)``   -> 0 if the LP-duality certificate holds
 * ``assign_scaled(C, s)``   -> (plan, cost, u, v)   single scaling factor (Section 2.3.1):
                              ``assign`` on floor(C / s), cost over C, duals times s
+* ``assign_rect(C)``        -> (plan, cost, u, v)   n x m (n != m allowed): the smaller side
+                             matched completely, the larger side at most once
+* ``certify_rect(C, plan, u, v)``     -> 0 if the rectangular LP certificate holds
 * ``transport(C, r, c)``    -> (X, cost, u, v)      unit expansion + ``assign``
 * ``certify_transport(C, r, c, X, u, v)`` -> 0 if the certificate holds
 """
@@ -54,9 +57,12 @@ def _load():
             lib.oracle_assign.argtypes = [_I32P, i32, _I32P, _I64P, _I64P, i64p]
             lib.oracle_brute_force.argtypes = [_I32P, i32, i64p, i64p]
             lib.oracle_certify_assign.argtypes = [_I32P, i32, _I32P, _I64P, _I64P]
+            lib.oracle_assign_rect.argtypes = [_I32P, i32, i32, _I32P, _I64P, _I64P, i64p]
+            lib.oracle_certify_rect.argtypes = [_I32P, i32, i32, _I32P, _I64P, _I64P]
             lib.oracle_transport.argtypes = [_I32P, _I32P, _I32P, i32, i32, _I32P, _I64P, _I64P, i64p]
             lib.oracle_certify_transport.argtypes = [_I32P, _I32P, _I32P, i32, i32, _I32P, _I64P, _I64P]
             for f in (lib.oracle_assign, lib.oracle_brute_force, lib.oracle_certify_assign,
+                      lib.oracle_assign_rect, lib.oracle_certify_rect,
                       lib.oracle_transport, lib.oracle_certify_transport):
                 f.restype = ctypes.c_int
             _lib = lib
@@ -102,6 +108,45 @@ def assign_scaled(C, s: int):
     plan, _, u, v = assign(Cs)
     cost = int(C.astype(np.int64)[np.arange(C.shape[0]), plan].sum())
     return plan, cost, u * int(s), v * int(s)
+
+
+def _matrix(C) -> np.ndarray:
+    C = np.ascontiguousarray(C, dtype=np.int32)
+    if C.ndim != 2 or C.shape[0] == 0 or C.shape[1] == 0:
+        raise ValueError("cost matrix must be 2-D and non-empty")
+    return C
+
+
+def assign_rect(C):
+    """Rectangular assignment of an n x m matrix (Eq. (1) with unit masses, n != m
+    allowed): every vertex of the smaller side is matched, every vertex of the
+    larger side at most once.  Returns (plan int32[n], cost int, u int64[n],
+    v int64[m]); plan[i] = -1 for unmatched rows (only when n > m).  The duals
+    solve the rectangular LP: the larger side's potentials are <= 0 and zero
+    where unmatched."""
+    C = _matrix(C)
+    n, m = C.shape
+    plan = np.empty(n, np.int32)
+    u = np.empty(n, np.int64)
+    v = np.empty(m, np.int64)
+    cost = ctypes.c_int64(0)
+    rc = _load().oracle_assign_rect(C, n, m, plan, u, v, ctypes.byref(cost))
+    if rc:
+        raise RuntimeError("oracle_assign_rect failed: %d" % rc)
+    return plan, int(cost.value), u, v
+
+
+def certify_rect(C, plan, u, v) -> int:
+    """0 when (plan, u, v) certifies an optimal rectangular assignment; else the
+    failing condition (1-5)."""
+    C = _matrix(C)
+    n, m = C.shape
+    plan = np.ascontiguousarray(plan, dtype=np.int32)
+    u = np.ascontiguousarray(u, dtype=np.int64)
+    v = np.ascontiguousarray(v, dtype=np.int64)
+    if plan.shape != (n,) or u.shape != (n,) or v.shape != (m,):
+        return 1
+    return int(_load().oracle_certify_rect(C, n, m, plan, u, v))
 
 
 def brute_force(C):

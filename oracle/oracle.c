@@ -21,6 +21,9 @@
  * Gabow-Tarjan transportation bound, Section 2.3.1), solving, and summing
  * the unit plan back onto bins.
  *
+ * Rectangular matrices (n != m, unit masses) are solved by the same
+ * shortest-augmenting-path method over the longer side (oracle_assign_rect).
+ *
  * All arithmetic is exact in int64.  Every function returns 0 on success or a
  * negative code for invalid input.
  */
@@ -48,43 +51,43 @@ static const int64_t BIG = INT64_MAX / 4;
  * the duals by that amount so the column becomes tight while every tree edge
  * stays tight, and either stops (column unowned: augmenting path found) or
  * adds the column's owner row to the tree.  Then the path is flipped.
+ *
+ * The core takes n rows and m >= n columns (C row-major with stride m); the
+ * square problem is m = n.  On return every row is matched (colof), and the
+ * columns that were never matched still have v_j = 0.
  */
-int oracle_assign(const int32_t *C, int32_t n, int32_t *plan, int64_t *u_out, int64_t *v_out,
-                  int64_t *cost_out)
+static int sap_rows_le_cols(const int32_t *C, int32_t n, int32_t m, int32_t *colof,
+                             int64_t *u, int64_t *v)
 {
-    if (!C || n <= 0) return ORC_EINVAL;
-    int64_t *u = calloc((size_t)n, sizeof *u);
-    int64_t *v = calloc((size_t)n, sizeof *v);
-    int64_t *dist = malloc((size_t)n * sizeof *dist);
-    int32_t *via = malloc((size_t)n * sizeof *via);
-    int32_t *owner = malloc((size_t)n * sizeof *owner);   /* column -> row, -1 free */
-    int32_t *colof = malloc((size_t)n * sizeof *colof);   /* row -> column, -1 free */
-    int32_t *tree = malloc((size_t)n * sizeof *tree);     /* rows in the current tree */
-    unsigned char *settled = malloc((size_t)n);
+    int64_t *dist = malloc((size_t)m * sizeof *dist);
+    int32_t *via = malloc((size_t)m * sizeof *via);
+    int32_t *owner = malloc((size_t)m * sizeof *owner);
+    int32_t *tree = malloc((size_t)n * sizeof *tree);
+    unsigned char *settled = malloc((size_t)m);
     int rc = 0;
-    if (!u || !v || !dist || !via || !owner || !colof || !tree || !settled) { rc = ORC_ENOMEM; goto out; }
-    for (int32_t j = 0; j < n; ++j) owner[j] = -1;
-    for (int32_t i = 0; i < n; ++i) colof[i] = -1;
+    if (!dist || !via || !owner || !tree || !settled) { rc = ORC_ENOMEM; goto out; }
+    for (int32_t i = 0; i < n; ++i) { colof[i] = -1; u[i] = 0; }
+    for (int32_t j = 0; j < m; ++j) { owner[j] = -1; v[j] = 0; }
 
     for (int32_t r = 0; r < n; ++r) {
-        for (int32_t j = 0; j < n; ++j) { dist[j] = BIG; via[j] = -1; settled[j] = 0; }
+        for (int32_t j = 0; j < m; ++j) { dist[j] = BIG; via[j] = -1; settled[j] = 0; }
         int32_t ntree = 0;
         tree[ntree++] = r;
-        int32_t newest = r;     /* the row whose edges have not been relaxed yet */
-        int32_t end = -1;       /* the free column that ends the augmenting path */
+        int32_t newest = r;
+        int32_t end = -1;
         for (;;) {
-            const int32_t *Crow = C + (size_t)newest * (size_t)n;
-            for (int32_t j = 0; j < n; ++j) {
+            const int32_t *Crow = C + (size_t)newest * (size_t)m;
+            for (int32_t j = 0; j < m; ++j) {
                 if (settled[j]) continue;
                 int64_t s = (int64_t)Crow[j] - u[newest] - v[j];
                 if (s < dist[j]) { dist[j] = s; via[j] = newest; }
             }
             int32_t best = -1;
-            for (int32_t j = 0; j < n; ++j)
+            for (int32_t j = 0; j < m; ++j)
                 if (!settled[j] && (best < 0 || dist[j] < dist[best])) best = j;
             int64_t delta = dist[best];
             for (int32_t t = 0; t < ntree; ++t) u[tree[t]] += delta;
-            for (int32_t j = 0; j < n; ++j) {
+            for (int32_t j = 0; j < m; ++j) {
                 if (settled[j]) v[j] -= delta;
                 else dist[j] -= delta;
             }
@@ -93,7 +96,6 @@ int oracle_assign(const int32_t *C, int32_t n, int32_t *plan, int64_t *u_out, in
             newest = owner[best];
             tree[ntree++] = newest;
         }
-        /* flip the path: every row on it takes the column it was reached through */
         for (int32_t j = end;;) {
             int32_t i = via[j];
             int32_t before = colof[i];
@@ -103,15 +105,28 @@ int oracle_assign(const int32_t *C, int32_t n, int32_t *plan, int64_t *u_out, in
             j = before;
         }
     }
-
-    int64_t total = 0;
-    for (int32_t i = 0; i < n; ++i) total += C[(size_t)i * (size_t)n + (size_t)colof[i]];
-    if (plan) memcpy(plan, colof, (size_t)n * sizeof *plan);
-    if (u_out) memcpy(u_out, u, (size_t)n * sizeof *u);
-    if (v_out) memcpy(v_out, v, (size_t)n * sizeof *v);
-    if (cost_out) *cost_out = total;
 out:
-    free(u); free(v); free(dist); free(via); free(owner); free(colof); free(tree); free(settled);
+    free(dist); free(via); free(owner); free(tree); free(settled);
+    return rc;
+}
+
+int oracle_assign(const int32_t *C, int32_t n, int32_t *plan, int64_t *u_out, int64_t *v_out,
+                  int64_t *cost_out)
+{
+    if (!C || n <= 0) return ORC_EINVAL;
+    int32_t *colof = malloc((size_t)n * sizeof *colof);
+    int64_t *u = malloc((size_t)n * sizeof *u);
+    int64_t *v = malloc((size_t)n * sizeof *v);
+    int rc = (!colof || !u || !v) ? ORC_ENOMEM : sap_rows_le_cols(C, n, n, colof, u, v);
+    if (!rc) {
+        int64_t total = 0;
+        for (int32_t i = 0; i < n; ++i) total += C[(size_t)i * (size_t)n + (size_t)colof[i]];
+        if (plan) memcpy(plan, colof, (size_t)n * sizeof *plan);
+        if (u_out) memcpy(u_out, u, (size_t)n * sizeof *u);
+        if (v_out) memcpy(v_out, v, (size_t)n * sizeof *v);
+        if (cost_out) *cost_out = total;
+    }
+    free(colof); free(u); free(v);
     return rc;
 }
 
@@ -301,5 +316,106 @@ int oracle_certify_transport(const int32_t *C, const int32_t *r, const int32_t *
     if (rc) return rc;
     for (int32_t i = 0; i < n; ++i) dual += (int64_t)r[i] * u[i];
     for (int32_t j = 0; j < m; ++j) dual += (int64_t)c[j] * v[j];
+    return primal == dual ? 0 : 5;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Rectangular assignment (n x m, n != m allowed)                             */
+/* ------------------------------------------------------------------------- */
+/*
+ * Eq. (1) is stated for an n x m cost matrix; with unit masses and n != m it
+ * is not balanced, and the reading taken here is the usual one: the smaller
+ * side is matched completely, every vertex of the larger side at most once,
+ * at minimum total cost.
+ *
+ * For n <= m this is the shortest-augmenting-path core above over all m
+ * columns.  A column's dual is lowered only while
+ * it is settled inside a tree, and every settled column except the path's end
+ * is matched, so duals start at 0, columns never matched keep v_j = 0 and all
+ * v_j <= 0: exactly the dual of the rectangular LP (rows = 1, columns <= 1).
+ *
+ * For n > m the problem is solved on the transpose (columns become the rows
+ * that must all be matched) and the answer is read back: plan[i] = -1 for the
+ * n - m rows left unmatched; u and v swap roles (u_i <= 0, u_i = 0 when row i
+ * is unmatched).
+ */
+int oracle_assign_rect(const int32_t *C, int32_t n, int32_t m, int32_t *plan, int64_t *u_out,
+                       int64_t *v_out, int64_t *cost_out)
+{
+    if (!C || n <= 0 || m <= 0 || !plan || !u_out || !v_out || !cost_out) return ORC_EINVAL;
+    int rc = 0;
+    if (n <= m) {
+        rc = sap_rows_le_cols(C, n, m, plan, u_out, v_out);
+    } else {
+        int32_t *CT = malloc((size_t)n * (size_t)m * sizeof *CT);
+        int32_t *rowof = malloc((size_t)m * sizeof *rowof);   /* column -> row */
+        if (!CT || !rowof) { free(CT); free(rowof); return ORC_ENOMEM; }
+        for (int32_t i = 0; i < n; ++i)
+            for (int32_t j = 0; j < m; ++j)
+                CT[(size_t)j * (size_t)n + (size_t)i] = C[(size_t)i * (size_t)m + (size_t)j];
+        rc = sap_rows_le_cols(CT, m, n, rowof, v_out, u_out);
+        if (!rc) {
+            for (int32_t i = 0; i < n; ++i) plan[i] = -1;
+            for (int32_t j = 0; j < m; ++j) plan[rowof[j]] = j;
+        }
+        free(CT); free(rowof);
+    }
+    if (rc) return rc;
+    int64_t total = 0;
+    for (int32_t i = 0; i < n; ++i)
+        if (plan[i] >= 0) total += C[(size_t)i * (size_t)m + (size_t)plan[i]];
+    *cost_out = total;
+    return 0;
+}
+
+/*
+ * Certificate of the rectangular LP.  With k = min(n, m), the primal is
+ * min sum C x over x >= 0 with every vertex of the smaller side covered
+ * exactly once and every vertex of the larger side at most once; its dual
+ * maximises sum u + sum v subject to u_i + v_j <= C_ij, with the potentials
+ * of the larger side <= 0.  Returns 0 when:
+ *   1  plan matches k distinct pairs, covering the smaller side (plan[i] = -1
+ *      marks an unmatched row, allowed only when n > m)
+ *   2  u_i + v_j <= C_ij everywhere
+ *   3  equality on every matched pair
+ *   4  larger-side potentials are <= 0, and == 0 where unmatched
+ *   5  sum of matched costs == sum u + sum v
+ * 1-4 imply optimality by weak duality; 5 catches overflow.
+ */
+int oracle_certify_rect(const int32_t *C, int32_t n, int32_t m, const int32_t *plan,
+                        const int64_t *u, const int64_t *v)
+{
+    if (!C || n <= 0 || m <= 0 || !plan || !u || !v) return ORC_EINVAL;
+    unsigned char *seen = calloc((size_t)m, 1);
+    if (!seen) return ORC_ENOMEM;
+    int32_t matched = 0;
+    for (int32_t i = 0; i < n; ++i) {
+        int32_t j = plan[i];
+        if (j == -1 && n > m) continue;
+        if (j < 0 || j >= m || seen[j]) { free(seen); return 1; }
+        seen[j] = 1;
+        ++matched;
+    }
+    if (matched != (n < m ? n : m)) { free(seen); return 1; }
+    for (int32_t i = 0; i < n; ++i)
+        for (int32_t j = 0; j < m; ++j)
+            if (u[i] + v[j] > (int64_t)C[(size_t)i * (size_t)m + (size_t)j]) { free(seen); return 2; }
+    int64_t primal = 0, dual = 0;
+    for (int32_t i = 0; i < n; ++i) {
+        if (plan[i] < 0) continue;
+        int64_t cij = C[(size_t)i * (size_t)m + (size_t)plan[i]];
+        if (u[i] + v[plan[i]] != cij) { free(seen); return 3; }
+        primal += cij;
+    }
+    if (n <= m) {
+        for (int32_t j = 0; j < m; ++j)
+            if (v[j] > 0 || (!seen[j] && v[j] != 0)) { free(seen); return 4; }
+    } else {
+        for (int32_t i = 0; i < n; ++i)
+            if (u[i] > 0 || (plan[i] < 0 && u[i] != 0)) { free(seen); return 4; }
+    }
+    free(seen);
+    for (int32_t i = 0; i < n; ++i) dual += u[i];
+    for (int32_t j = 0; j < m; ++j) dual += v[j];
     return primal == dual ? 0 : 5;
 }

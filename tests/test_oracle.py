@@ -206,6 +206,129 @@ def test_certificate_rejects_mutations():
         assert oracle.certify_assign(C, swapped, u, v) != 0
 
 
+# ----------------------------------------------------------------------------- rectangular
+# Eq. (1) is n x m; with unit masses and n != m the smaller side is matched
+# completely and the larger side at most once (the usual rectangular reading).
+def py_brute_rect(C):
+    """Plain Python enumeration of every injective map of the smaller side."""
+    n, m = C.shape
+    best = None
+    if n <= m:
+        for q in itertools.permutations(range(m), n):
+            s = sum(int(C[i, q[i]]) for i in range(n))
+            best = s if best is None else min(best, s)
+    else:
+        for q in itertools.permutations(range(n), m):
+            s = sum(int(C[q[j], j]) for j in range(m))
+            best = s if best is None else min(best, s)
+    return best
+
+
+def check_rect(C):
+    plan, cost, u, v = oracle.assign_rect(C)
+    n, m = C.shape
+    assert oracle.certify_rect(C, plan, u, v) == 0
+    rows = np.flatnonzero(plan >= 0)
+    assert len(rows) == min(n, m) and len(set(plan[rows].tolist())) == min(n, m)
+    assert cost == int(C.astype(np.int64)[rows, plan[rows]].sum())
+    return plan, cost, u, v
+
+
+@pytest.mark.parametrize("shape", [(1, 4), (4, 1), (2, 5), (5, 2), (3, 6), (6, 3), (4, 7), (7, 4), (5, 6), (6, 5)])
+@pytest.mark.parametrize("kind", ["ties", "wide", "negative"])
+def test_rect_brute_force(shape, kind):
+    rng = np.random.default_rng(97 * shape[0] + 13 * shape[1] + len(kind))
+    for _ in range(4):
+        if kind == "ties":
+            C = rng.integers(0, 3, shape, endpoint=True)
+        elif kind == "wide":
+            C = rng.integers(0, 1_000_000, shape)
+        else:
+            C = rng.integers(-500, 500, shape)
+        C = C.astype(np.int32)
+        _, cost, _, _ = check_rect(C)
+        assert cost == py_brute_rect(C)
+
+
+@pytest.mark.parametrize("n,m", [(40, 70), (70, 40), (1, 300), (300, 1), (120, 121), (199, 64)])
+def test_rect_against_scipy(n, m):
+    C = np.random.default_rng(n * 1000 + m).integers(-10_000, 10_000, (n, m)).astype(np.int32)
+    _, cost, _, _ = check_rect(C)
+    r_, c_ = linear_sum_assignment(C)
+    assert cost == int(C.astype(np.int64)[r_, c_].sum())
+
+
+def test_rect_against_lp():
+    # HiGHS on the LP itself: equality on the smaller side, <= 1 on the larger
+    rng = np.random.default_rng(5)
+    for n, m in ((6, 9), (9, 6)):
+        C = rng.integers(0, 50, (n, m)).astype(np.int32)
+        _, cost, _, _ = check_rect(C)
+        row = np.zeros((n, n * m)); col = np.zeros((m, n * m))
+        for i in range(n): row[i, i * m:(i + 1) * m] = 1
+        for j in range(m): col[j, j::m] = 1
+        eq, ub = (row, col) if n <= m else (col, row)
+        lp = linprog(C.reshape(-1).astype(float), A_eq=eq, b_eq=np.ones(len(eq)),
+                     A_ub=ub, b_ub=np.ones(len(ub)), bounds=(0, None), method="highs")
+        assert abs(lp.fun - cost) < 1e-6
+
+
+def test_rect_square_and_transpose():
+    rng = np.random.default_rng(8)
+    C = rng.integers(0, 1000, (50, 50)).astype(np.int32)
+    assert check_rect(C)[1] == oracle.assign(C)[1]
+    R = rng.integers(-3000, 3000, (33, 80)).astype(np.int32)
+    pa, ca, ua, va = check_rect(R)
+    pb, cb, ub, vb = check_rect(np.ascontiguousarray(R.T))
+    assert ca == cb
+    assert int(ua.sum() + va.sum()) == int(ub.sum() + vb.sum()) == ca
+    # the same pairs, read from either side
+    assert sorted((i, int(pa[i])) for i in range(33)) == sorted((int(pb[j]), j) for j in range(80) if pb[j] >= 0)
+
+
+def test_rect_closed_forms():
+    rng = np.random.default_rng(9)
+    row = rng.integers(-100, 100, (1, 57)).astype(np.int32)
+    assert check_rect(row)[1] == int(row.min())
+    assert check_rect(np.ascontiguousarray(row.T))[1] == int(row.min())
+    # a planted zero injective map in an otherwise positive matrix is the unique optimum
+    n, m = 12, 30
+    C = rng.integers(1, 100, (n, m)).astype(np.int32)
+    cols = rng.permutation(m)[:n]
+    C[np.arange(n), cols] = 0
+    plan, cost, _, _ = check_rect(C)
+    assert cost == 0 and (plan == cols).all()
+    plan, cost, _, _ = check_rect(np.ascontiguousarray(C.T))
+    assert cost == 0 and (plan[cols] == np.arange(n)).all()
+    assert (np.delete(plan, cols) == -1).all()
+    # extra columns dearer than every existing entry change nothing
+    D = np.concatenate([C, np.full((n, 5), 1000, np.int32)], axis=1)
+    assert check_rect(D)[1] == check_rect(C)[1]
+
+
+def test_rect_certificate_rejects_mutations():
+    rng = np.random.default_rng(12)
+    C = rng.integers(0, 100, (8, 13)).astype(np.int32)
+    plan, cost, u, v = oracle.assign_rect(C)
+    assert oracle.certify_rect(C, plan, u, v) == 0
+    bad = plan.copy(); bad[0] = bad[1]
+    assert oracle.certify_rect(C, bad, u, v) == 1
+    bad = plan.copy(); bad[0] = -1
+    assert oracle.certify_rect(C, bad, u, v) == 1
+    free = [j for j in range(13) if j not in set(plan.tolist())]
+    vv = v.copy(); vv[free[0]] -= 1
+    assert oracle.certify_rect(C, plan, u, vv) == 4
+    # a shift of every potential keeps the square certificate but not the rectangular one
+    assert oracle.certify_rect(C, plan, u - 1, v + 1) == 4
+    uu = u.copy(); uu[2] += 1
+    assert oracle.certify_rect(C, plan, uu, v) in (2, 3)
+    T = np.ascontiguousarray(C.T)
+    p2, c2, u2, v2 = oracle.assign_rect(T)
+    assert oracle.certify_rect(T, p2, u2, v2) == 0
+    uu = u2.copy(); uu[int(np.flatnonzero(p2 < 0)[0])] -= 1
+    assert oracle.certify_rect(T, p2, uu, v2) == 4
+
+
 # ----------------------------------------------------------------------------- transport
 def lp_transport_cost(C, r, c):
     n, m = C.shape

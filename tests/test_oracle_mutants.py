@@ -4,7 +4,7 @@ Each mutant is a copy of oracle/oracle.c with one plausible mistake (a dropped
 term, a flipped sign, a transposed operand, a wrong index).  It is compiled
 into a temporary library and run in a child process against a small subset
 of the pins (Python brute force, scipy's solver, the LP-duality certificate,
-the line-transport closed form and a small HiGHS LP).  Every mutant must be caught.
+rectangular brute force, the line-transport closed form and a small HiGHS LP).  Every mutant must be caught.
 """
 import os
 import subprocess
@@ -24,6 +24,12 @@ MUTANTS = {
     "settle_largest": ("if (!settled[j] && (best < 0 || dist[j] < dist[best])) best = j;",
                        "if (!settled[j] && (best < 0 || dist[j] > dist[best])) best = j;"),
     "dist_not_shifted": ("else dist[j] -= delta;", "else dist[j] -= 0;"),
+    "rect_row_stride": ("const int32_t *Crow = C + (size_t)newest * (size_t)m;",
+                        "const int32_t *Crow = C + (size_t)newest * (size_t)n;"),
+    "rect_untransposed_copy": ("CT[(size_t)j * (size_t)n + (size_t)i] = C[(size_t)i * (size_t)m + (size_t)j];",
+                               "CT[(size_t)i * (size_t)m + (size_t)j] = C[(size_t)i * (size_t)m + (size_t)j];"),
+    "rect_readback": ("for (int32_t j = 0; j < m; ++j) plan[rowof[j]] = j;",
+                      "for (int32_t j = 0; j < m; ++j) plan[j] = rowof[j];"),
     "transport_wrong_colbin": ("int32_t i = rowbin[a], j = colbin[px[a]];", "int32_t i = rowbin[a], j = colbin[a];"),
     "zero_mass_row_sign": ("int64_t s = (int64_t)C[(size_t)i * (size_t)m + (size_t)j] - vb[j];",
                            "int64_t s = (int64_t)C[(size_t)i * (size_t)m + (size_t)j] + vb[j];"),
@@ -59,6 +65,21 @@ CHECK = textwrap.dedent(r"""
     p, c, u, v = assign(C)
     r_, c_ = linear_sum_assignment(C)
     if c != int(C[r_, c_].sum()) or not cert(C, p, u, v): sys.exit(3)
+    lib.oracle_assign_rect.argtypes = [I32, ctypes.c_int32, ctypes.c_int32, I32, I64, I64, ctypes.POINTER(ctypes.c_int64)]
+    for shape in ((3, 5), (5, 3), (4, 6), (6, 4)):
+        C = rng.integers(0, 9, shape).astype(np.int32)
+        n, m = shape
+        p = np.empty(n, np.int32); u = np.empty(n, np.int64); v = np.empty(m, np.int64); c = ctypes.c_int64(0)
+        assert lib.oracle_assign_rect(C, n, m, p, u, v, ctypes.byref(c)) == 0
+        k = min(n, m)
+        if n <= m:
+            best = min(sum(int(C[i, q[i]]) for i in range(n)) for q in itertools.permutations(range(m), n))
+        else:
+            best = min(sum(int(C[q[j], j]) for j in range(m)) for q in itertools.permutations(range(n), m))
+        rows = np.flatnonzero(p >= 0)
+        if c.value != best or len(rows) != k or len(set(p[rows].tolist())) != k: sys.exit(3)
+        if int(C[rows, p[rows]].sum()) != best: sys.exit(3)
+        if (u[:, None] + v[None, :] > C).any() or (u[rows] + v[p[rows]] != C[rows, p[rows]]).any(): sys.exit(3)
     n = 7
     C = np.abs(np.arange(n)[:, None] - np.arange(n)[None, :]).astype(np.int32)
     r = np.array([3, 0, 1, 0, 2, 0, 1], np.int32); cc = np.array([0, 2, 0, 3, 0, 2, 0], np.int32)
