@@ -253,6 +253,61 @@ def bench_scaled(args):
     return out
 
 
+def bench_rect(args):
+    """Rectangular assignment (Eq. (1) with unit masses, n != m): n circle points
+    against m square-perimeter points; the smaller side are the solver's rows."""
+    import torch
+
+    from paper_2005_01182_amd import otkm as ot
+    from paper_2005_01182_amd import workloads as wl
+    n, m = args.rows, args.cols
+    M = max(n, m)
+    C = wl.geometric_rect(n, m, seed=0)
+    dC = torch.from_numpy(C).cuda()
+    stream = torch.cuda.Stream()
+    plan = torch.empty(n, dtype=torch.int32, device="cuda")
+    cost = torch.empty(1, dtype=torch.int64, device="cuda")
+    u = torch.empty(n, dtype=torch.int64, device="cuda")
+    v = torch.empty(m, dtype=torch.int64, device="cuda")
+    st = ot.stats_tensor(args.steps + args.warmup)
+    log("rect %dx%d: warmup %d, steps %d" % (n, m, args.warmup, args.steps))
+    for w in range(args.warmup):
+        ot.ot_assign_rect_dev(dC, plan, cost, u, v, st[w], stream=stream)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0.record(stream)
+    for k in range(args.steps):
+        ev[k][0].record(stream)
+        ot.ot_assign_rect_dev(dC, plan, cost, u, v, st[args.warmup + k], stream=stream)
+        ev[k][1].record(stream)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    per = [a.elapsed_time(b) for a, b in ev]
+    total = t0.elapsed_time(t1)
+    stats = st[args.warmup:].cpu().numpy()
+    if int(np.abs(stats[:, F["status"]]).max()) != 0:
+        raise SystemExit("rect solve status %s" % stats[:, F["status"]])
+    b = alg_bytes(stats, [M] * len(stats))
+    out = base_line(args, args.steps / (total / 1e3), "solves/s", total / args.steps,
+                    {"workload": "rectangular geometric assignment: %d circle points vs %d square-perimeter "
+                                 "points, sigma 0.02, C = rint(1e4 * distance) int32, seed 0" % (n, m),
+                     "n": n, "m": m, "method": "batched KM, rows = the smaller side, column duals from 0",
+                     "optimal_cost": int(cost.item())})
+    out["metric"] = "solves/s, rectangular assignment"
+    out["roofline"] = roofline(float(np.mean(b)), float(np.mean(per)) / 1e3)
+    out["roofline"]["traffic"] = traffic_for("rect_%dx%d" % (n, m))
+    out["latency_ms"] = {"p50": pct(per, 50), "p99": pct(per, 99)}
+    out["solver_counters"] = {**counters(stats), "alg_bytes_per_solve": int(b[0])}
+    if not args.skip_cpu:
+        import oracle
+        rate, done = cpu_rate(oracle.assign_rect, [C] * 3, args.cpu_budget)
+        out["cpu_baseline"] = {"value": round(rate, 5), "unit": "solves/s", "cores": 1, "kind": "oracle",
+                               "sample": "%d solve(s) of the same instance by the single-threaded C oracle "
+                                         "(rectangular shortest augmenting path)" % done}
+    return out
+
+
 def bench_small(args):
     from paper_2005_01182_amd import workloads as wl
     C = wl.uniform_assignment(64, seed=0)
@@ -423,7 +478,7 @@ def main():
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
     ap.add_argument("--mode", default="geometric", choices=["geometric", "small", "transport", "batch", "serve",
-                                                             "copy", "scaled"])
+                                                             "copy", "scaled", "rect"])
     ap.add_argument("--n", type=int, default=2048)
     ap.add_argument("--count", type=int, default=4096, help="batch mode: number of problems")
     ap.add_argument("--plain-steps", type=int, default=3)
@@ -436,9 +491,11 @@ def main():
     ap.add_argument("--duration", type=float, default=5.0, help="serve mode: seconds of the request stream")
     ap.add_argument("--copy-mib", type=int, default=1024, help="copy mode: MiB per buffer")
     ap.add_argument("--scale", type=int, default=100, help="scaled mode: cost scaling factor s")
+    ap.add_argument("--rows", type=int, default=1024, help="rect mode: rows n")
+    ap.add_argument("--cols", type=int, default=2048, help="rect mode: columns m")
     args = ap.parse_args()
     defaults = {"geometric": (20, 3), "small": (2000, 50), "transport": (50, 5), "batch": (5, 1), "serve": (1, 0),
-                "copy": (5, 2), "scaled": (20, 3)}
+                "copy": (5, 2), "scaled": (20, 3), "rect": (10, 2)}
     if args.steps is None:
         args.steps = defaults[args.mode][0]
     if args.warmup is None:
@@ -458,7 +515,8 @@ def main():
         out = serve.bench(args)
     else:
         out = {"geometric": bench_geometric, "small": bench_small, "transport": bench_transport,
-               "batch": bench_batch, "copy": bench_copy, "scaled": bench_scaled}[args.mode](args)
+               "batch": bench_batch, "copy": bench_copy, "scaled": bench_scaled,
+               "rect": bench_rect}[args.mode](args)
     print(json.dumps(out), flush=True)
 
 

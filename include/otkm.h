@@ -96,7 +96,11 @@ typedef struct ot_stats {
 /* Solver options; pass NULL for the defaults (all zero). */
 typedef struct ot_options {
     int32_t max_paths;     /* trees grown at once: 0 = every free row (Batched KM),
-                              1 = one tree at a time (classical KM), k = at most k */
+                              1 = one tree at a time (classical KM), k = at most k.
+                              With a cap the solver's level (the sum of the dual
+                              adjustments) grows over the stages; a solve whose level
+                              would pass 2^31 - 1 stops with OT_EINTERNAL (random
+                              inputs stay near the cost range). */
     int32_t block;         /* workgroup width: 0 = automatic, else 64, 256, 512 or 1024 */
     int32_t flags;         /* OT_FLAG_* bits */
     int32_t scale;         /* cost scaling factor s (Section 2.3.1: one scaling factor turns the
@@ -107,7 +111,7 @@ typedef struct ot_options {
                                 u, v  s * (optimal duals of C'), which are feasible for C
                                       (u_i + v_j <= C_ij), so
                               sum u + sum v <= OPT(C) <= cost <= sum u + sum v + n (s - 1).
-                              Assignment calls only (ot_assign_ex, ot_assign_dev). */
+                              Square assignment calls only (ot_assign_ex, ot_assign_dev). */
     int32_t reserved[4];   /* must be zero */
 } ot_options;
 
@@ -132,6 +136,28 @@ int ot_assign(const int32_t *C, int32_t n, int32_t *plan, int64_t *cost, int64_t
 /* ot_assign with options and counters (opt and stats may be NULL). */
 int ot_assign_ex(const int32_t *C, int32_t n, const ot_options *opt, int32_t *plan, int64_t *cost,
                  int64_t *u, int64_t *v, ot_stats *stats);
+
+/* Rectangular assignment (Eq. (1) with unit masses and n != m allowed): every
+ * vertex of the smaller side is matched, every vertex of the larger side at
+ * most once, at minimum total cost.
+ *   C    [n*m]  int32 costs (row-major, ld = m); max(n, m) <= OT_MAX_N
+ *   plan [n]    out: column of row i, distinct; -1 for the n - m rows left
+ *                    unmatched when n > m
+ *   cost        out: sum over matched rows of C[i, plan[i]]
+ *   u [n], v [m] out (may be NULL): optimal duals of the rectangular LP:
+ *                    u_i + v_j <= C_ij, equality on matched pairs, and the
+ *                    larger side's potentials are <= 0 and equal 0 where
+ *                    unmatched (v when n <= m, u when n > m), so
+ *                    sum u + sum v = cost
+ *   opt (may be NULL): max_paths, block and flags as for ot_assign_ex; scale
+ *                    must be 0 or 1 (OT_EINVAL otherwise).
+ * Solved with the smaller side as the rows (on C^T when n > m), every row a
+ * root of the forest and the column duals started at 0; needs 4 n m bytes of
+ * device workspace for the transpose.
+ * Errors: OT_EINVAL (null pointer, n or m <= 0, bad options), OT_ETOOBIG,
+ * OT_ERANGE (max - min over C > 2^31 - 1); outputs untouched on error. */
+int ot_assign_rect(const int32_t *C, int32_t n, int32_t m, const ot_options *opt, int32_t *plan,
+                   int64_t *cost, int64_t *u, int64_t *v, ot_stats *stats);
 
 /* Integer transport (Eq. (1), Hitchcock-Koopmans case).
  *   C [n*m] int32 costs (ld = m); r [n], c [m] int32 masses, >= 0, equal sums S >= 1.
@@ -166,6 +192,14 @@ int ot_assign_batch(int32_t count, const int32_t *const *C, const int32_t *n, in
  * du [n], dv [n] (du/dv may be NULL), dstats [1] (may be NULL). */
 int ot_assign_dev(const int32_t *dC, int32_t n, int32_t ld, const ot_options *opt, int32_t *dplan,
                   int64_t *dcost, int64_t *du, int64_t *dv, ot_stats *dstats, void *stream);
+
+/* Rectangular assignment on device memory (see ot_assign_rect).  dC [n*ld]
+ * (ld >= m), dplan [n], dcost [1], du [n], dv [m] (du/dv may be NULL), dstats
+ * [1] (may be NULL; status there).  On a data error (cost range, watchdog)
+ * only dstats is written. */
+int ot_assign_rect_dev(const int32_t *dC, int32_t n, int32_t m, int32_t ld, const ot_options *opt,
+                       int32_t *dplan, int64_t *dcost, int64_t *du, int64_t *dv, ot_stats *dstats,
+                       void *stream);
 
 /* Batch on device memory.  Instance k: cost matrix at dC + coff[k] (dense,
  * ld = n[k]), plan/u/v at dplan/du/dv + voff[k]; dcost [count];

@@ -90,23 +90,27 @@ __host__ __device__ inline LdsLayout lds_layout(int n) {
 __host__ __device__ inline size_t ws_ints(int n) { return 2 * (size_t)n; }
 
 struct Problem {
-  const int32_t *C;   // n x n, row stride ld
+  const int32_t *C;   // nr x n (rows x columns), row stride ld
   int n, ld;
-  const int32_t *CT;  // transpose of C (n x n, row stride n), or null; only read to refresh single columns
+  int nr = 0;         // rows, 1 <= nr <= n; 0 = n (square).  With nr < n every row is matched and
+                      // the column duals start at 0 (no column reduction), so they end <= 0 and
+                      // exactly 0 on the columns left unmatched: the rectangular LP's dual
+  const int32_t *CT;  // transpose of C (n x nr, row stride ldt), or null; only read to refresh single columns
+  int ldt = 0;        // row stride of CT; 0 = nr
   const int32_t *Cout;  // costs the reported total is taken over (row stride ldo), or null for C
   int ldo;
   int dscale;         // reported duals are dscale * (duals of C); 1 unless C holds scaled-down costs
   // Optional results of the grid-wide initial sweeps (k_init_rows / k_init_cols /
   // k_init_merge), or null to run them inside the workgroup:
-  const int64_t *init_u;     // [n] row minima u_i = min_j C_ij
+  const int64_t *init_u;     // [nr] row minima u_i = min_j C_ij
   const uint64_t *init_b;    // [n][2] per column the two smallest keys pack(C_ij - u_i, i)
-  const int32_t *init_rmax;  // [n] row maxima (with the row minima: the cost range)
+  const int32_t *init_rmax;  // [nr] row maxima (with the row minima: the cost range)
 
   int max_paths;      // 0 = all free rows
   int flags;          // OT_FLAG_* bits
-  int32_t *plan;      // [n]
+  int32_t *plan;      // [nr]
   int64_t *cost;      // [1]
-  int64_t *u, *v;     // [n] or null
+  int64_t *u, *v;     // [nr], [n] or null
   ot_stats *stats;    // [1] or null
   int32_t *ws;        // [ws_ints(n)]
 };
@@ -208,6 +212,8 @@ struct Engine {
   const int32_t *__restrict__ C;
   const int32_t *__restrict__ CT;
   int n, ld;
+  int nr;    // rows (n columns)
+  int ldt;   // row stride of CT
   // LDS
   int64_t *hrow;
   int32_t *mrow, *mcol, *rtree, *par, *fst, *gcol, *gt1, *gt2, *ctl;
@@ -275,13 +281,13 @@ struct Engine {
         if (REC) {
           const int2 e = ((const int2 *)list)[f + q < cnt ? f + q : cnt - 1];
           r[q] = e.x & 0xffff;
-          if ((unsigned)r[q] >= (unsigned)n) { fail(OT_EINTERNAL); r[q] = 0; }
+          if ((unsigned)r[q] >= (unsigned)nr) { fail(OT_EINTERNAL); r[q] = 0; }
           t[q] = (f + q < cnt && e.x >= 0) ? (e.x >> 16) : -1;  // sign bit: the row's tree has gone
           h32[q] = (uint32_t)e.y;
           h[q] = NARROW ? 0 : hrow[r[q]];
         } else {
           r[q] = f + q < cnt ? list[f + q] : 0;
-          if ((unsigned)r[q] >= (unsigned)n) { fail(OT_EINTERNAL); r[q] = 0; }
+          if ((unsigned)r[q] >= (unsigned)nr) { fail(OT_EINTERNAL); r[q] = 0; }
           t[q] = f + q < cnt ? rtree[r[q]] : -1;
           h[q] = hrow[r[q]];
           h32[q] = (uint32_t)h[q];
@@ -500,7 +506,7 @@ struct Engine {
         const int64_t v = gv[s];
         // column j of C: a contiguous row of the transpose when there is one,
         // else one entry per cost row
-        const int32_t *colp = CT ? CT + (size_t)j * (size_t)n : C + j;
+        const int32_t *colp = CT ? CT + (size_t)j * (size_t)ldt : C + j;
         const size_t cstride = CT ? 1 : (size_t)ld;
         uint64_t a1 = kInf, a2 = kInf;
         int ta1 = -1, ta2 = -1;
@@ -513,7 +519,7 @@ struct Engine {
           for (int q = 0; q < GU; ++q) {
             const int f = f0 + q * stride;
             i[q] = f < nf ? fst[f] : 0;
-            if ((unsigned)i[q] >= (unsigned)n) { fail(OT_EINTERNAL); i[q] = 0; }
+            if ((unsigned)i[q] >= (unsigned)nr) { fail(OT_EINTERNAL); i[q] = 0; }
             t[q] = f < nf ? rtree[i[q]] : -1;
             h[q] = hrow[i[q]];
           }
@@ -561,6 +567,9 @@ struct Engine {
 
   __device__ __forceinline__ void run(const Problem &P, char *smem) {
     C = P.C; CT = P.CT; n = P.n; ld = P.ld;
+    nr = P.nr > 0 && P.nr < P.n ? P.nr : P.n;
+    ldt = P.ldt > 0 ? P.ldt : nr;
+    const bool colred = nr == n;  // column reduction: square problems only
     tid = threadIdx.x; lane = tid & 63; wid = tid >> 6;
     err_local = 0;
     const LdsLayout L = lds_layout(n);
@@ -584,7 +593,7 @@ struct Engine {
     auglist = P.ws;
     bend = P.ws + n;
 
-    const int K = (P.max_paths <= 0 || P.max_paths > n) ? n : P.max_paths;
+    const int K = (P.max_paths <= 0 || P.max_paths > nr) ? nr : P.max_paths;
     int64_t st_levels = 0, st_dual = 0, st_aug = 0, st_paths = 0, st_rows = 0, st_gath = 0, st_resw = 0;
     int64_t st_refresh = 0, st_rcols = 0, tm_refresh = 0;
     int64_t tm_sweep = 0, tm_select = 0, tm_settle = 0, tm_aug = 0;
@@ -596,14 +605,14 @@ struct Engine {
     const bool pre = P.init_u && P.init_b && P.init_rmax;
     int gmin = 0x7fffffff, gmax = (int)0x80000000;
     if (pre) {
-      for (int i = tid; i < n; i += BLOCK) {
+      for (int i = tid; i < nr; i += BLOCK) {
         const int64_t mn = P.init_u[i];
         hrow[i] = mn;
         gmin = min(gmin, (int)mn);
         gmax = max(gmax, P.init_rmax[i]);
       }
     }
-    for (int i = pre ? n : wid; i < n; i += NW) {
+    for (int i = pre ? nr : wid; i < nr; i += NW) {
       const int32_t *row = C + (size_t)i * (size_t)ld;
       int mn = 0x7fffffff, mx = (int)0x80000000;
       for (int j0 = 0; j0 < n; j0 += 64 * 16) {
@@ -642,7 +651,8 @@ struct Engine {
       return;
     }
 
-    // ---- v_j = min_i (C_ij - u_i); with every row a root, keep the two best rows as keys
+    // ---- v_j = min_i (C_ij - u_i) (square; else v_j = 0); with every row a root, keep
+    // the two best rows as keys
     vis = 0;
     stl = 0;
 #pragma unroll
@@ -656,8 +666,8 @@ struct Engine {
         b1[k] = pre ? P.init_b[2 * (size_t)lcol(k)] : kInf;
         b2[k] = pre ? P.init_b[2 * (size_t)lcol(k) + 1] : kInf;
       }
-      int i = pre ? n : 0;
-      for (; i + 4 <= n; i += 4) {
+      int i = pre ? nr : 0;
+      for (; i + 4 <= nr; i += 4) {
         int32_t c[4][CPT];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
@@ -676,7 +686,7 @@ struct Engine {
           }
         }
       }
-      for (; i < n; ++i) {
+      for (; i < nr; ++i) {
         const int32_t *row = C + (size_t)i * (size_t)ld;
         const int64_t h = hrow[i];
         int32_t c[CPT];
@@ -693,26 +703,26 @@ struct Engine {
 #pragma unroll
       for (int k = 0; k < CPT; ++k) {
         if (col(k) >= n) continue;
-        vj[k] = (int32_t)kval(b1[k]);
-        if (K == n) {
-          k1[k] = pack(0, krow(b1[k]));
+        vj[k] = colred ? (int32_t)kval(b1[k]) : 0;
+        if (K == nr) {
+          k1[k] = pack(kval(b1[k]) - vj[k], krow(b1[k]));
           t1[k] = krow(b1[k]);
           if (b2[k] != kInf) { k2[k] = pack(kval(b2[k]) - vj[k], krow(b2[k])); t2[k] = krow(b2[k]); }
         }
       }
     }
-    st_rows = 2 * (int64_t)n;
+    st_rows = 2 * (int64_t)nr;
     int cur = 0;
     if (tid == 0) {
       ctl[CNT0] = 0; ctl[CNT1] = 0; ctl[FCNT] = K;
     }
-    if (K < n) {
+    if (K < nr) {
       for (int i = tid; i < K; i += BLOCK) fr[i] = frontier_rec(i, i, hrow[i]);
       if (tid == 0) ctl[CNT0] = K;
     }
     __syncthreads();
 
-    int nfree = n, nalive = K, cursor = K;
+    int nfree = nr, nalive = K, cursor = K;
     int64_t D = 0;
     const int64_t watchdog = (int64_t)(n + 2) * (int64_t)(n + 2) + 64;
     const bool timers = (P.flags & OT_FLAG_PHASE_TIMERS) != 0;
@@ -753,6 +763,10 @@ struct Engine {
       if (mv == kInf) { fail(OT_EINTERNAL); break; }
       const int64_t level = kval(mv);
       if (level > D) { D = level; ++st_dual; }
+      // With every free row a root from level 0, D never exceeds the cost range;
+      // with a tree cap it adds up over stages and could in principle leave the
+      // 32-bit range of the per-column levels: report that instead of wrapping.
+      if (D > 0x7ffffffell) { fail(OT_EINTERNAL); break; }
       if (++st_levels > watchdog) { fail(OT_EINTERNAL); break; }
       const int64_t t1_ = timers ? now_ticks() : 0;
       tm_select += t1_ - t0;
@@ -799,7 +813,7 @@ struct Engine {
           for (int steps = 0;; ++steps) {
             if (steps > n || (unsigned)j >= (unsigned)n) { fail(OT_EINTERNAL); break; }
             const int p = par[j];
-            if ((unsigned)p >= (unsigned)n) { fail(OT_EINTERNAL); break; }
+            if ((unsigned)p >= (unsigned)nr) { fail(OT_EINTERNAL); break; }
             const int before = mrow[p];
             mrow[p] = j;
             mcol[j] = p;
@@ -814,7 +828,7 @@ struct Engine {
         nalive -= naug;
         __syncthreads();
         // (5) rows and columns of finished trees leave the forest with their duals materialised
-        for (int i = tid; i < n; i += BLOCK) {
+        for (int i = tid; i < nr; i += BLOCK) {
           const int t = rtree[i];
           if (t >= 0 && !alive[t]) { hrow[i] += D; rtree[i] = -1; }
         }
@@ -850,9 +864,9 @@ struct Engine {
         // (6) rebuild the forest list (one LDS atomic per wavefront and 64 rows,
         // each lane's slot from its rank among the lanes that keep a row); with
         // a tree cap, start new trees from the next free rows
-        for (int i0 = wid * 64; i0 < n; i0 += BLOCK) {
+        for (int i0 = wid * 64; i0 < nr; i0 += BLOCK) {
           const int i = i0 + lane;
-          const bool keep = i < n && rtree[i] >= 0;
+          const bool keep = i < nr && rtree[i] >= 0;
           const uint64_t m = __builtin_amdgcn_ballot_w64(keep);
           int base = 0;
           if (lane == 0 && m != 0) base = atomicAdd(&ctl[FCNT], (int)__builtin_popcountll(m));
@@ -860,7 +874,7 @@ struct Engine {
           const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0));
           if (keep) fst[base + rank] = i;
         }
-        const int need = min(K - nalive, n - cursor);
+        const int need = min(K - nalive, nr - cursor);
         if (need > 0) {
           __syncthreads();  // the scan above must not see the new roots
           for (int q = tid; q < need; q += BLOCK) {
@@ -892,7 +906,7 @@ struct Engine {
       int64_t part = 0;
       const int32_t *Cr = P.Cout ? P.Cout : C;
       const size_t ldr = P.Cout ? (size_t)P.ldo : (size_t)ld;
-      for (int i = tid; i < n; i += BLOCK) {
+      for (int i = tid; i < nr; i += BLOCK) {
         const int j = mrow[i];
         P.plan[i] = j;
         if (P.u) P.u[i] = hrow[i] * P.dscale;

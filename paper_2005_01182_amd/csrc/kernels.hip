@@ -87,10 +87,12 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2))) void
 // ---------------------------------------------------------------------------
 // u_i = min_j C_ij and rmax_i = max_j C_ij, one wavefront per row (the cost
 // range min_i u_i .. max_i rmax_i is reduced by the solver; no global atomics).
-__global__ __launch_bounds__(256) void k_init_rows(const int32_t *C, int n, int ld, int64_t *u, int32_t *rmax) {
+// C has nr rows of n columns.
+__global__ __launch_bounds__(256) void k_init_rows(const int32_t *C, int nr, int n, int ld, int64_t *u,
+                                                   int32_t *rmax) {
   const int lane = threadIdx.x & 63;
   const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (i >= n) return;
+  if (i >= nr) return;
   const int32_t *row = C + (size_t)i * (size_t)ld;
   int mn = 0x7fffffff, mx = (int)0x80000000;
   if ((ld & 3) == 0 && ((uintptr_t)C & 15) == 0) {
@@ -130,14 +132,14 @@ __device__ __forceinline__ void two_smallest(uint64_t &b1, uint64_t &b2, uint64_
 // slice y.  A workgroup covers 64 columns; its four wavefronts split the slice
 // (each row a coalesced 256-byte read) and merge through LDS.
 constexpr int kInitSliceRows = 128;
-__global__ __launch_bounds__(256) void k_init_cols(const int32_t *C, int n, int ld, const int64_t *u,
+__global__ __launch_bounds__(256) void k_init_cols(const int32_t *C, int nr, int n, int ld, const int64_t *u,
                                                    uint64_t *part) {
   __shared__ uint64_t sb[4][64][2];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int j = blockIdx.x * 64 + lane;
   const int jc = j < n ? j : n - 1;
   const int i0 = blockIdx.y * kInitSliceRows + w * (kInitSliceRows / 4);
-  const int i1 = min(n, i0 + kInitSliceRows / 4);
+  const int i1 = min(nr, i0 + kInitSliceRows / 4);
   uint64_t b1 = kInf, b2 = kInf;
   int i = i0;
   for (; i + 8 <= i1; i += 8) {
@@ -175,20 +177,20 @@ __global__ __launch_bounds__(256) void k_init_merge(const uint64_t *part, int sl
   b[2 * (size_t)j + 1] = b2;
 }
 
-// CT = C^T (n x n, row stride n) from C (row stride ld): 64 x 64 tiles through
-// LDS so that both the read and the write are coalesced.
-__global__ __launch_bounds__(256) void k_transpose(const int32_t *C, int n, int ld, int32_t *CT) {
+// CT = C^T (n x nr, row stride nr) from C (nr x n, row stride ld): 64 x 64
+// tiles through LDS so that both the read and the write are coalesced.
+__global__ __launch_bounds__(256) void k_transpose(const int32_t *C, int nr, int n, int ld, int32_t *CT) {
   __shared__ int32_t tile[64][65];
   const int bj = blockIdx.x * 64, bi = blockIdx.y * 64;
   const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
   for (int r = ty; r < 64; r += 4) {
     const int i = bi + r, j = bj + tx;
-    if (i < n && j < n) tile[r][tx] = C[(size_t)i * (size_t)ld + j];
+    if (i < nr && j < n) tile[r][tx] = C[(size_t)i * (size_t)ld + j];
   }
   __syncthreads();
   for (int r = ty; r < 64; r += 4) {
     const int j = bj + r, i = bi + tx;
-    if (i < n && j < n) CT[(size_t)j * (size_t)n + i] = tile[tx][r];
+    if (i < nr && j < n) CT[(size_t)j * (size_t)nr + i] = tile[tx][r];
   }
 }
 
@@ -202,6 +204,60 @@ __global__ void k_floor_div(const int32_t *C, int n, int ld, int32_t s, int32_t 
     const int32_t q = c / s;  // truncates toward zero; step down for negative non-multiples
     Cs[(size_t)i * (size_t)n + j] = (c % s != 0 && c < 0) ? q - 1 : q;
   }
+}
+
+// ---------------------------------------------------------------------------
+// rectangular assignment (n x m, n != m): Eq. (1) with unit masses, the smaller
+// side matched completely and the larger side at most once
+// ---------------------------------------------------------------------------
+// The solver runs on rows = the smaller side: C itself when n <= m, else C^T
+// (trans).  Its outputs (plan pq over its rows, duals uq over its rows and vq
+// over its columns, status in sq) become the caller's: when trans, rows and
+// columns swap back, so plan[i] = the column whose solver row took row i, or
+// -1.  Without a column reduction the larger side's potentials end <= 0 and 0
+// where unmatched; with equal sides (square, column-reduced) they are shifted
+// by their maximum V (u += V, v -= V keeps every u_i + v_j and the objective),
+// which gives the same sign condition.  One workgroup.
+__global__ __launch_bounds__(1024) void k_rect_finish(int n, int m, int trans, const int32_t *pq, const int64_t *uq,
+                                                      const int64_t *vq, const int64_t *cq, const ot_stats *sq,
+                                                      int32_t *plan, int64_t *cost, int64_t *u, int64_t *v,
+                                                      ot_stats *stats) {
+  __shared__ int64_t red[1024];
+  const int tid = threadIdx.x;
+  const int status = sq->status;
+  if (stats && tid == 0) *stats = *sq;
+  if (status != 0) return;
+  const int rows = trans ? m : n, cols = trans ? n : m;  // the solver's sides
+  int64_t mx = INT64_MIN;
+  for (int k = tid; k < cols; k += 1024) mx = vq[k] > mx ? vq[k] : mx;
+  red[tid] = mx;
+  __syncthreads();
+  for (int w = 512; w > 0; w >>= 1) {
+    if (tid < w && red[tid + w] > red[tid]) red[tid] = red[tid + w];
+    __syncthreads();
+  }
+  const int64_t V = red[0];  // solver rows' duals + V, solver columns' duals - V
+  if (!trans) {
+    for (int i = tid; i < n; i += 1024) {
+      plan[i] = pq[i];
+      if (u) u[i] = uq[i] + V;
+    }
+    if (v)
+      for (int j = tid; j < m; j += 1024) v[j] = vq[j] - V;
+  } else {
+    for (int i = tid; i < n; i += 1024) {
+      plan[i] = -1;
+      if (u) u[i] = vq[i] - V;
+    }
+    if (v)
+      for (int j = tid; j < m; j += 1024) v[j] = uq[j] + V;
+    __syncthreads();  // the -1 fill is visible to the workgroup before the scatter
+    for (int j = tid; j < m; j += 1024) {
+      const int i = pq[j];
+      if ((unsigned)i < (unsigned)n) plan[i] = j;
+    }
+  }
+  if (tid == 0) *cost = *cq;
 }
 
 __global__ void k_fill_i32(int32_t *p, int32_t value, int64_t count) {
@@ -440,7 +496,7 @@ hipError_t launch_transport(const TransportArgs &T, int block, hipStream_t s) {
   hipLaunchKernelGGL(k_tr_expand, dim3((T.S + 255) / 256, T.S), dim3(256), 0, s, T.C, T.m, T.S, T.rowbin, T.colbin,
                      T.Cx, T.gate);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  if (T.CxT && (e = launch_transpose(T.Cx, T.S, T.S, T.CxT, s)) != hipSuccess) return e;
+  if (T.CxT && (e = launch_transpose(T.Cx, T.S, T.S, T.S, T.CxT, s)) != hipSuccess) return e;
   Problem P;
   P.C = T.Cx; P.n = T.S; P.ld = T.S; P.max_paths = T.max_paths; P.flags = 0; P.CT = T.CxT;
   P.Cout = nullptr; P.ldo = T.S; P.dscale = 1;
@@ -463,17 +519,17 @@ hipError_t launch_transport(const TransportArgs &T, int block, hipStream_t s) {
   return hipGetLastError();
 }
 
-size_t init_part_bytes(int n) {
-  return (size_t)((n + kInitSliceRows - 1) / kInitSliceRows) * (size_t)n * 16;
+size_t init_part_bytes(int nr, int n) {
+  return (size_t)((nr + kInitSliceRows - 1) / kInitSliceRows) * (size_t)n * 16;
 }
 
-hipError_t launch_init_sweeps(const int32_t *C, int n, int ld, int64_t *u, int32_t *rmax, uint64_t *part,
+hipError_t launch_init_sweeps(const int32_t *C, int nr, int n, int ld, int64_t *u, int32_t *rmax, uint64_t *part,
                               uint64_t *b, hipStream_t st) {
   hipError_t e;
-  hipLaunchKernelGGL(k_init_rows, dim3((n + 3) / 4), dim3(256), 0, st, C, n, ld, u, rmax);
+  hipLaunchKernelGGL(k_init_rows, dim3((nr + 3) / 4), dim3(256), 0, st, C, nr, n, ld, u, rmax);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  const int slices = (n + kInitSliceRows - 1) / kInitSliceRows;
-  hipLaunchKernelGGL(k_init_cols, dim3((n + 63) / 64, slices), dim3(256), 0, st, C, n, ld, u, part);
+  const int slices = (nr + kInitSliceRows - 1) / kInitSliceRows;
+  hipLaunchKernelGGL(k_init_cols, dim3((n + 63) / 64, slices), dim3(256), 0, st, C, nr, n, ld, u, part);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(k_init_merge, dim3((n + 255) / 256), dim3(256), 0, st, part, slices, n, b);
   return hipGetLastError();
@@ -485,9 +541,16 @@ hipError_t launch_floor_div(const int32_t *C, int n, int ld, int32_t s, int32_t 
   return hipGetLastError();
 }
 
-hipError_t launch_transpose(const int32_t *C, int n, int ld, int32_t *CT, hipStream_t s) {
-  const int t = (n + 63) / 64;
-  hipLaunchKernelGGL(k_transpose, dim3(t, t), dim3(256), 0, s, C, n, ld, CT);
+hipError_t launch_transpose(const int32_t *C, int nr, int n, int ld, int32_t *CT, hipStream_t s) {
+  hipLaunchKernelGGL(k_transpose, dim3((n + 63) / 64, (nr + 63) / 64), dim3(256), 0, s, C, nr, n, ld, CT);
+  return hipGetLastError();
+}
+
+hipError_t launch_rect_finish(int n, int m, bool trans, const int32_t *pq, const int64_t *uq, const int64_t *vq,
+                              const int64_t *cq, const ot_stats *sq, int32_t *plan, int64_t *cost, int64_t *u,
+                              int64_t *v, ot_stats *stats, hipStream_t s) {
+  hipLaunchKernelGGL(k_rect_finish, dim3(1), dim3(1024), 0, s, n, m, trans ? 1 : 0, pq, uq, vq, cq, sq, plan, cost,
+                     u, v, stats);
   return hipGetLastError();
 }
 

@@ -46,11 +46,14 @@ hipError_t launch_assign_one(const Problem &P, int block, const int32_t *gate, h
 hipError_t launch_assign_batch(const BatchArgs &A, int block, int grid, hipStream_t s);
 hipError_t launch_fill_i32(int32_t *p, int32_t value, int64_t count, hipStream_t s);
 hipError_t launch_transport(const TransportArgs &T, int block, hipStream_t s);
-size_t init_part_bytes(int n);
-hipError_t launch_init_sweeps(const int32_t *C, int n, int ld, int64_t *u, int32_t *rmax, uint64_t *part,
+size_t init_part_bytes(int nr, int n);
+hipError_t launch_init_sweeps(const int32_t *C, int nr, int n, int ld, int64_t *u, int32_t *rmax, uint64_t *part,
                               uint64_t *b, hipStream_t st);
 hipError_t launch_floor_div(const int32_t *C, int n, int ld, int32_t s, int32_t *Cs, hipStream_t st);
-hipError_t launch_transpose(const int32_t *C, int n, int ld, int32_t *CT, hipStream_t s);
+hipError_t launch_transpose(const int32_t *C, int nr, int n, int ld, int32_t *CT, hipStream_t s);
+hipError_t launch_rect_finish(int n, int m, bool trans, const int32_t *pq, const int64_t *uq, const int64_t *vq,
+                              const int64_t *cq, const ot_stats *sq, int32_t *plan, int64_t *cost, int64_t *u,
+                              int64_t *v, ot_stats *stats, hipStream_t s);
 hipError_t launch_grid_cost(const int32_t *ps, const int32_t *pt, int n, int32_t *Cout, hipStream_t s);
 
 }  // namespace otkm

@@ -228,13 +228,13 @@ int ot_assign_ex(const int32_t *C, int32_t n, const ot_options *opt, int32_t *pl
     if ((e = launch_floor_div(dC, n, n, scale, dCs, s)) != hipSuccess) return map_hip(e);
     dsolve = dCs;
   }
-  if ((e = launch_transpose(dsolve, n, n, dCT, s)) != hipSuccess) return map_hip(e);
+  if ((e = launch_transpose(dsolve, n, n, n, dCT, s)) != hipSuccess) return map_hip(e);
   auto *du0 = (int64_t *)pool_get(80, 8 * N, &err);
   auto *drmax = (int32_t *)pool_get(81, 4 * N, &err);
-  auto *dpart = (uint64_t *)pool_get(82, init_part_bytes(n), &err);
+  auto *dpart = (uint64_t *)pool_get(82, init_part_bytes(n, n), &err);
   auto *db = (uint64_t *)pool_get(83, 16 * N, &err);
   if (err) return err;
-  if ((e = launch_init_sweeps(dsolve, n, n, du0, drmax, dpart, db, s)) != hipSuccess) return map_hip(e);
+  if ((e = launch_init_sweeps(dsolve, n, n, n, du0, drmax, dpart, db, s)) != hipSuccess) return map_hip(e);
   Problem P;
   P.C = dsolve; P.n = n; P.ld = n; P.CT = dCT; P.max_paths = max_paths; P.flags = flags;
   P.Cout = dC; P.ldo = n; P.dscale = scale;
@@ -287,19 +287,135 @@ int ot_assign_dev(const int32_t *dC, int32_t n, int32_t ld, const ot_options *op
     dsolve = dCs;
     lds = n;
   }
-  if ((e = launch_transpose(dsolve, n, lds, dCT, s)) != hipSuccess) return map_hip(e);
+  if ((e = launch_transpose(dsolve, n, n, lds, dCT, s)) != hipSuccess) return map_hip(e);
   auto *du0 = (int64_t *)stream_ws(s, 40, 8 * (size_t)n, &err);
   auto *drmax = (int32_t *)stream_ws(s, 41, 4 * (size_t)n, &err);
-  auto *dpart = (uint64_t *)stream_ws(s, 42, init_part_bytes(n), &err);
+  auto *dpart = (uint64_t *)stream_ws(s, 42, init_part_bytes(n, n), &err);
   auto *db = (uint64_t *)stream_ws(s, 43, 16 * (size_t)n, &err);
   if (err) return err;
-  if ((e = launch_init_sweeps(dsolve, n, lds, du0, drmax, dpart, db, s)) != hipSuccess) return map_hip(e);
+  if ((e = launch_init_sweeps(dsolve, n, n, lds, du0, drmax, dpart, db, s)) != hipSuccess) return map_hip(e);
   Problem P;
   P.C = dsolve; P.n = n; P.ld = lds; P.CT = dCT; P.max_paths = max_paths; P.flags = flags;
   P.Cout = dC; P.ldo = ld; P.dscale = scale;
   P.init_u = du0; P.init_b = db; P.init_rmax = drmax;
   P.plan = dplan; P.cost = dcost; P.u = du; P.v = dv; P.stats = dstats; P.ws = dws;
   return map_hip(launch_assign_one(P, block, nullptr, s));
+}
+
+}  // extern "C"
+
+namespace otkm {
+
+// Rectangular solve on device buffers.  The solver's rows are the smaller side:
+// C itself when n <= m (its transpose feeds the single-column refreshes), else
+// C^T materialised in the workspace (and C serves as that matrix's transpose).
+// Then the grid-wide reduction sweeps, the one-instance engine and the
+// rectangular outputs.  `get(slot, bytes)` hands out workspace.
+template <class Get>
+static int rect_pipeline(const int32_t *dC, int n, int m, int ld, int block, int max_paths, int flags, Get get,
+                         hipStream_t s, int32_t *dplan, int64_t *dcost, int64_t *du, int64_t *dv, ot_stats *dstats) {
+  const bool trans = n > m;
+  const int nr = trans ? m : n, nc = trans ? n : m;  // solver rows <= solver columns
+  auto *T = (int32_t *)get(0, 4 * (size_t)n * (size_t)m);
+  auto *ws = (int32_t *)get(2, 4 * ws_ints(nc));
+  auto *pq = (int32_t *)get(3, 4 * (size_t)nr);
+  auto *uq = (int64_t *)get(4, 8 * (size_t)nr);
+  auto *vq = (int64_t *)get(5, 8 * (size_t)nc);
+  auto *cq = (int64_t *)get(6, 8);
+  auto *sq = (ot_stats *)get(7, sizeof(ot_stats));
+  auto *u0 = (int64_t *)get(8, 8 * (size_t)nr);
+  auto *rmax = (int32_t *)get(9, 4 * (size_t)nr);
+  auto *part = (uint64_t *)get(10, init_part_bytes(nr, nc));
+  auto *b = (uint64_t *)get(11, 16 * (size_t)nc);
+  if (!T || !ws || !pq || !uq || !vq || !cq || !sq || !u0 || !rmax || !part || !b) return OT_ENOMEM;
+  hipError_t e;
+  // the transpose of C (m x n, row stride n) is the solver matrix (trans) or its transpose
+  if ((e = launch_transpose(dC, n, m, ld, T, s)) != hipSuccess) return map_hip(e);
+  const int32_t *A = trans ? T : dC;
+  const int lda = trans ? n : ld;
+  if ((e = launch_init_sweeps(A, nr, nc, lda, u0, rmax, part, b, s)) != hipSuccess) return map_hip(e);
+  Problem P;
+  P.C = A; P.n = nc; P.nr = nr; P.ld = lda; P.max_paths = max_paths; P.flags = flags;
+  P.CT = trans ? dC : T; P.ldt = trans ? ld : n;
+  P.Cout = nullptr; P.ldo = lda; P.dscale = 1;
+  P.init_u = u0; P.init_b = b; P.init_rmax = rmax;
+  P.plan = pq; P.cost = cq; P.u = uq; P.v = vq; P.stats = sq; P.ws = ws;
+  if ((e = launch_assign_one(P, block, nullptr, s)) != hipSuccess) return map_hip(e);
+  return map_hip(launch_rect_finish(n, m, trans, pq, uq, vq, cq, sq, dplan, dcost, du, dv, dstats, s));
+}
+
+static int rect_check(int32_t n, int32_t m, const ot_options *opt, int *block, int *max_paths, int *flags) {
+  if (n <= 0 || m <= 0) return OT_EINVAL;
+  const int M = std::max(n, m);
+  if (M > OT_MAX_N) return OT_ETOOBIG;
+  int scale;
+  int rc = check_options(opt, M, block, max_paths, flags, &scale);
+  if (rc) return rc;
+  return scale > 1 ? OT_EINVAL : OT_OK;
+}
+
+}  // namespace otkm
+
+extern "C" {
+
+int ot_assign_rect(const int32_t *C, int32_t n, int32_t m, const ot_options *opt, int32_t *plan, int64_t *cost,
+                   int64_t *u, int64_t *v, ot_stats *stats) {
+  if (!C || !plan || !cost) return OT_EINVAL;
+  int block, max_paths, flags;
+  int rc = rect_check(n, m, opt, &block, &max_paths, &flags);
+  if (rc) return rc;
+  if (!range_ok(C, (int64_t)n * m)) return OT_ERANGE;
+  std::lock_guard<std::mutex> lk(g_mu);
+  if ((rc = init_locked())) return rc;
+  int err = OT_OK;
+  const size_t NM = (size_t)n * (size_t)m;
+  auto *dC = (int32_t *)pool_get(90, 4 * NM, &err);
+  auto *dplan = (int32_t *)pool_get(91, 4 * (size_t)n, &err);
+  auto *du = (int64_t *)pool_get(92, 8 * (size_t)n, &err);
+  auto *dv = (int64_t *)pool_get(93, 8 * (size_t)m, &err);
+  auto *dcost = (int64_t *)pool_get(94, 8, &err);
+  auto *dstats = (ot_stats *)pool_get(95, sizeof(ot_stats), &err);
+  if (err) return err;
+  hipStream_t s = g_stream;
+  hipError_t e = hipMemcpyAsync(dC, C, 4 * NM, hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return map_hip(e);
+  auto get = [&](int slot, size_t bytes) { return pool_get(100 + slot, bytes, &err); };
+  rc = rect_pipeline(dC, n, m, m, block, max_paths, flags, get, s, dplan, dcost, du, dv, dstats);
+  if (err) return err;
+  if (rc) return rc;
+  ot_stats hs;
+  std::vector<int32_t> hplan(n);
+  std::vector<int64_t> hu(n), hv(m);
+  int64_t hcost = 0;
+  if ((e = hipMemcpyAsync(&hs, dstats, sizeof hs, hipMemcpyDeviceToHost, s)) != hipSuccess) return map_hip(e);
+  if ((e = hipMemcpyAsync(hplan.data(), dplan, 4 * (size_t)n, hipMemcpyDeviceToHost, s)) != hipSuccess)
+    return map_hip(e);
+  if ((e = hipMemcpyAsync(hu.data(), du, 8 * (size_t)n, hipMemcpyDeviceToHost, s)) != hipSuccess) return map_hip(e);
+  if ((e = hipMemcpyAsync(hv.data(), dv, 8 * (size_t)m, hipMemcpyDeviceToHost, s)) != hipSuccess) return map_hip(e);
+  if ((e = hipMemcpyAsync(&hcost, dcost, 8, hipMemcpyDeviceToHost, s)) != hipSuccess) return map_hip(e);
+  if ((e = hipStreamSynchronize(s)) != hipSuccess) return map_hip(e);
+  if (hs.status != 0) return (int)hs.status;
+  std::memcpy(plan, hplan.data(), 4 * (size_t)n);
+  *cost = hcost;
+  if (u) std::memcpy(u, hu.data(), 8 * (size_t)n);
+  if (v) std::memcpy(v, hv.data(), 8 * (size_t)m);
+  if (stats) *stats = hs;
+  return OT_OK;
+}
+
+int ot_assign_rect_dev(const int32_t *dC, int32_t n, int32_t m, int32_t ld, const ot_options *opt, int32_t *dplan,
+                       int64_t *dcost, int64_t *du, int64_t *dv, ot_stats *dstats, void *stream) {
+  if (!dC || !dplan || !dcost || ld < m) return OT_EINVAL;
+  int block, max_paths, flags;
+  int rc = rect_check(n, m, opt, &block, &max_paths, &flags);
+  if (rc) return rc;
+  std::lock_guard<std::mutex> lk(g_mu);
+  if ((rc = init_locked())) return rc;
+  hipStream_t s = stream ? (hipStream_t)stream : g_stream;
+  int err = OT_OK;
+  auto get = [&](int slot, size_t bytes) { return stream_ws(s, 100 + slot, bytes, &err); };
+  rc = rect_pipeline(dC, n, m, ld, block, max_paths, flags, get, s, dplan, dcost, du, dv, dstats);
+  return err ? err : rc;
 }
 
 int ot_assign_batch_dev(int32_t count, int32_t max_n, const int32_t *dC, const int64_t *coff, const int32_t *n,

@@ -22,8 +22,8 @@ OT_ETOOBIG, OT_ENOMEM, OT_EDEVICE, OT_ENODEV, OT_EINTERNAL = -5, -6, -7, -8, -9
 OT_MAX_N = 4096
 
 EXPORTS = [
-    "ot_strerror", "ot_init", "ot_assign", "ot_assign_ex", "ot_transport", "ot_assign_batch",
-    "ot_assign_dev", "ot_assign_batch_dev", "ot_transport_dev",
+    "ot_strerror", "ot_init", "ot_assign", "ot_assign_ex", "ot_assign_rect", "ot_transport", "ot_assign_batch",
+    "ot_assign_dev", "ot_assign_rect_dev", "ot_assign_batch_dev", "ot_transport_dev",
     "ot_schedule_get", "ot_schedule_set", "ot_schedule_tune",
     "ot_grid_cost_dev", "ot_serve_open", "ot_serve_submit", "ot_serve_poll", "ot_serve_stats", "ot_serve_close",
 ]
@@ -100,9 +100,11 @@ def load():
         lib.ot_init.argtypes = []
         lib.ot_assign.argtypes = [_VP, _I32, _VP, _VP, _VP, _VP]
         lib.ot_assign_ex.argtypes = [_VP, _I32, _VP, _VP, _VP, _VP, _VP, _VP]
+        lib.ot_assign_rect.argtypes = [_VP, _I32, _I32, _VP, _VP, _VP, _VP, _VP, _VP]
         lib.ot_transport.argtypes = [_VP, _VP, _VP, _I32, _I32, _VP, _VP, _VP, _VP]
         lib.ot_assign_batch.argtypes = [_I32, _VP, _VP, _VP, _VP, _VP, _VP, _VP]
         lib.ot_assign_dev.argtypes = [_VP, _I32, _I32, _VP, _VP, _VP, _VP, _VP, _VP, _VP]
+        lib.ot_assign_rect_dev.argtypes = [_VP, _I32, _I32, _I32, _VP, _VP, _VP, _VP, _VP, _VP, _VP]
         lib.ot_assign_batch_dev.argtypes = [_I32, _I32, _VP, _VP, _VP, _VP, _VP, _I32, _I32, _VP, _VP, _VP, _VP, _VP,
                                             _VP]
         lib.ot_transport_dev.argtypes = [_VP, _VP, _VP, _I32, _I32, _I32, _VP, _VP, _VP, _VP, _VP, _VP]
@@ -177,6 +179,31 @@ def ot_assign(C, max_paths: int = 0, block: int = 0, with_stats: bool = False, t
     rc = load().ot_assign_ex(_p(C), n, ctypes.byref(opt), _p(plan), ctypes.byref(cost), _p(u), _p(v),
                              ctypes.byref(st))
     _check(rc, "ot_assign")
+    out = (plan, int(cost.value), u, v)
+    return out + (st.as_dict(),) if with_stats else out
+
+
+def ot_assign_rect(C, max_paths: int = 0, block: int = 0, with_stats: bool = False, timers: bool = False):
+    """Rectangular assignment of an n x m int32 cost matrix (n != m allowed): the
+    smaller side matched completely, the larger side at most once.
+
+    Returns (plan, cost, u, v) or (plan, cost, u, v, stats_dict); plan[i] = -1
+    for rows left unmatched (n > m), and (u, v) are optimal duals of the
+    rectangular LP (the larger side's potentials <= 0, zero where unmatched).
+    """
+    C = np.ascontiguousarray(C, dtype=np.int32)
+    if C.ndim != 2:
+        raise ValueError("2-D cost matrix required")
+    n, m = C.shape
+    plan = np.empty(n, np.int32)
+    u = np.empty(n, np.int64)
+    v = np.empty(m, np.int64)
+    cost = ctypes.c_int64(0)
+    st = ot_stats()
+    opt = _options(max_paths, block, timers)
+    rc = load().ot_assign_rect(_p(C), n, m, ctypes.byref(opt), _p(plan), ctypes.byref(cost), _p(u), _p(v),
+                               ctypes.byref(st))
+    _check(rc, "ot_assign_rect")
     out = (plan, int(cost.value), u, v)
     return out + (st.as_dict(),) if with_stats else out
 
@@ -266,6 +293,17 @@ def ot_assign_dev(C, plan, cost, u=None, v=None, stats=None, max_paths=0, block=
     rc = load().ot_assign_dev(_tp(C), n, ld, ctypes.byref(opt), _tp(plan), _tp(cost), _tp(u), _tp(v),
                               _tp(stats), _stream(stream))
     _check(rc, "ot_assign_dev")
+
+
+def ot_assign_rect_dev(C, plan, cost, u=None, v=None, stats=None, max_paths=0, block=0, stream=None, ld=None,
+                       timers=False):
+    """Queue a rectangular assignment on device tensors (asynchronous on `stream`)."""
+    n, m = int(C.shape[0]), int(C.shape[1])
+    ld = int(ld if ld is not None else C.stride(0))
+    opt = _options(max_paths, block, timers)
+    rc = load().ot_assign_rect_dev(_tp(C), n, m, ld, ctypes.byref(opt), _tp(plan), _tp(cost), _tp(u), _tp(v),
+                                   _tp(stats), _stream(stream))
+    _check(rc, "ot_assign_rect_dev")
 
 
 def ot_assign_batch_dev(count, max_n, C, coff, n, voff, plan, cost, u=None, v=None, stats=None, order=None,

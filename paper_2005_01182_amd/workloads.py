@@ -65,27 +65,29 @@ def uniform_assignment(n: int = 64, lo: int = 0, hi: int = 1000, seed: int = 0) 
 # --------------------------------------------------------------------------- #
 # Geometric: circle vs. square perimeter (CircleSquare family)
 # --------------------------------------------------------------------------- #
-def geometric_points(n: int, seed: int = 0, sigma: float = 0.02):
+def geometric_points(n: int, seed: int = 0, sigma: float = 0.02, m: int | None = None):
     """Sources on the unit circle, targets on the perimeter of the side-1 square.
 
     Both shapes share the origin as centre (as in the CircleSquare data).
     Sources: angle ~ U[0, 2 pi).  Targets: arclength t ~ U[0, 4) walked
     counter-clockwise from (-1/2, -1/2).  Both get N(0, sigma^2) noise per
-    coordinate.  Returns two (n, 2) float64 arrays.
+    coordinate.  Returns (n, 2) sources and (m, 2) targets (m = n by default),
+    float64; the targets' stream is independent of n.
     """
+    m = n if m is None else m
     ra, rb = rng_for(seed, 2)
     th = ra.uniform(0.0, 2.0 * np.pi, n)
     x = np.stack([np.cos(th), np.sin(th)], axis=1) + ra.normal(0.0, sigma, (n, 2))
-    t = rb.uniform(0.0, 4.0, n)
+    t = rb.uniform(0.0, 4.0, m)
     side = np.minimum(np.floor(t).astype(np.int64), 3)
     f = t - side
-    y = np.empty((n, 2))
+    y = np.empty((m, 2))
     s0, s1, s2, s3 = (side == 0), (side == 1), (side == 2), (side == 3)
     y[s0, 0], y[s0, 1] = -0.5 + f[s0], -0.5
     y[s1, 0], y[s1, 1] = 0.5, -0.5 + f[s1]
     y[s2, 0], y[s2, 1] = 0.5 - f[s2], 0.5
     y[s3, 0], y[s3, 1] = -0.5, 0.5 - f[s3]
-    y += rb.normal(0.0, sigma, (n, 2))
+    y += rb.normal(0.0, sigma, (m, 2))
     return x, y
 
 
@@ -97,6 +99,13 @@ def _euclid_rint(x: np.ndarray, y: np.ndarray, scale: float) -> np.ndarray:
 def geometric_assignment(n: int = 2048, seed: int = 0, scale: float = 1e4) -> np.ndarray:
     """n x n int32 costs C_ij = rint(scale * ||x_i - y_j||_2) (round half to even, fp64)."""
     x, y = geometric_points(n, seed)
+    return _euclid_rint(x, y, scale)
+
+
+def geometric_rect(n: int, m: int, seed: int = 0, scale: float = 1e4) -> np.ndarray:
+    """n x m int32 costs between n circle points and m square-perimeter points
+    (rectangular CircleSquare), C_ij = rint(scale * ||x_i - y_j||_2)."""
+    x, y = geometric_points(n, seed, m=m)
     return _euclid_rint(x, y, scale)
 
 

@@ -23,7 +23,7 @@ def declared_symbols():
 def test_header_declares_boundary():
     syms = declared_symbols()
     for name in ("ot_assign", "ot_transport", "ot_assign_batch", "ot_assign_dev", "ot_transport_dev",
-                 "ot_assign_batch_dev", "ot_strerror"):
+                 "ot_assign_batch_dev", "ot_assign_rect", "ot_assign_rect_dev", "ot_strerror"):
         assert name in syms
 
 
@@ -61,6 +61,22 @@ VALIDATION = textwrap.dedent(r"""
     out["assign_neg_paths"] = code(ot.ot_assign, C, max_paths=-1)
     out["assign_neg_scale"] = code(ot.ot_assign, C, scale=-2)
     out["assign_scale_ok_but_nodev"] = code(ot.ot_assign, C, scale=10)
+    R = np.zeros((3, 5), np.int32)
+    out["rect_ok_but_nodev"] = code(ot.ot_assign_rect, R)
+    out["rect_tall_ok_but_nodev"] = code(ot.ot_assign_rect, np.ascontiguousarray(R.T))
+    out["rect_empty"] = code(ot.ot_assign_rect, np.zeros((0, 4), np.int32))
+    out["rect_too_big"] = code(ot.ot_assign_rect, np.zeros((2, 4097), np.int32))
+    wr = np.zeros((2, 5), np.int32); wr[0, 4] = -2**31; wr[1, 0] = 2**31 - 1
+    out["rect_range"] = code(ot.ot_assign_rect, wr)
+    out["rect_bad_block"] = code(ot.ot_assign_rect, R, block=100)
+    import ctypes
+    o = ot._options(scale=3)
+    p_ = np.zeros(3, np.int32); c_ = ctypes.c_int64(0)
+    out["rect_scale"] = ot.load().ot_assign_rect(ot._p(R), 3, 5, ctypes.byref(o), ot._p(p_), ctypes.byref(c_),
+                                                 None, None, None)
+    out["rect_null"] = ot.load().ot_assign_rect(None, 3, 5, None, ot._p(p_), ctypes.byref(c_), None, None, None)
+    out["rect_dev_bad_ld"] = ot.load().ot_assign_rect_dev(ot._p(R), 3, 5, 4, None, ot._p(p_), ctypes.byref(c_),
+                                                          None, None, None, None)
     r = np.array([1, 1, 2], np.int32); c = np.array([2, 2], np.int32)
     Ct = np.zeros((3, 2), np.int32)
     out["transport_ok_but_nodev"] = code(ot.ot_transport, Ct, r, c)
@@ -115,6 +131,15 @@ def test_validation_codes(codes):
     assert codes["assign_scale_ok_but_nodev"] == -8
     assert codes["assign_block_too_narrow"] == -1
     assert codes["assign_neg_paths"] == -1
+    assert codes["rect_ok_but_nodev"] == -8
+    assert codes["rect_tall_ok_but_nodev"] == -8
+    assert codes["rect_empty"] == -1
+    assert codes["rect_too_big"] == -5
+    assert codes["rect_range"] == -2
+    assert codes["rect_bad_block"] == -1
+    assert codes["rect_scale"] == -1
+    assert codes["rect_null"] == -1
+    assert codes["rect_dev_bad_ld"] == -1
     assert codes["transport_ok_but_nodev"] == -8
     assert codes["transport_unbalanced"] == -3
     assert codes["transport_zero"] == -3

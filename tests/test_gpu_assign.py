@@ -131,6 +131,13 @@ def test_repeat_runs_identical(otkm_gpu):
         assert np.array_equal(again[2], first[2]) and np.array_equal(again[3], first[3])
 
 
+@pytest.mark.parametrize("max_paths", [1, 5])
+def test_plain_km_mode_full_range(otkm_gpu, max_paths):
+    # capped trees: the level adds up over stages; on random inputs it stays near the range
+    C = np.random.default_rng(31).integers(-2**30, 2**30, (200, 200), endpoint=True).astype(np.int32)
+    gpu_vs_oracle(otkm_gpu, C, max_paths=max_paths)
+
+
 @pytest.mark.parametrize("max_paths", [1, 3])
 def test_plain_km_mode_same_cost(otkm_gpu, max_paths):
     C = wl.geometric_assignment(300, seed=2)
