@@ -112,7 +112,13 @@ typedef struct ot_options {
                                       (u_i + v_j <= C_ij), so
                               sum u + sum v <= OPT(C) <= cost <= sum u + sum v + n (s - 1).
                               Square assignment calls only (ot_assign_ex, ot_assign_dev). */
-    int32_t reserved[4];   /* must be zero */
+    int32_t wgs;           /* workgroups per instance (single-instance assignment calls):
+                              0 = automatic, 1 = one workgroup, 2..16 = the columns split
+                              over that many workgroups, which exchange the minimum key
+                              and the settled columns through global memory with a grid
+                              barrier per step (block then 256 or 512, default 512, at
+                              most 4 columns per lane; OT_EINVAL otherwise) */
+    int32_t reserved[3];   /* must be zero */
 } ot_options;
 
 /* Status text for a code; never NULL. */

@@ -51,7 +51,19 @@ constexpr int kNoEnd = 0x7fffffff;
 
 // int control words in LDS
 enum Ctl { CNT0 = 0, CNT1 = 1, NAUG = 2, GCNT = 3, ERR = 4, FCNT = 5, ERRA0 = 6, ERRA1 = 7, ERRB0 = 8, ERRB1 = 9,
-           NCTL = 12 };
+           GAB = 10, LCNT = 11, NCTL = 12 };
+
+// Global state of one instance spread over G <= kMaxWgs workgroups, in 64-bit
+// words (all zero before the launch): barrier arrivals and abort flag; per
+// slot set and workgroup the local minimum pair and a tag word (level << 32 |
+// error); per workgroup gathers and final error; then per level parity and
+// workgroup a list of settled columns: a tag word (level << 32 | count) and at
+// most `per` (columns owned by a workgroup) entries.
+constexpr int kMaxWgs = 16;
+constexpr int kGBar = 0, kGAbort = 1, kGMin = 2, kGGath = kGMin + 4 * kMaxWgs * 3, kGFin = kGGath + kMaxWgs,
+              kGList = 256;
+static_assert(kGFin + kMaxWgs <= kGList, "grid state header overlaps the lists");
+__host__ __device__ inline size_t grid_ws_u64(int G, int per) { return kGList + 2 * (size_t)G * (size_t)(per + 1); }
 
 __host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~size_t(15); }
 __host__ __device__ inline int gather_cap(int n) { return n / 16 < 32 ? 32 : n / 16; }
@@ -112,7 +124,8 @@ struct Problem {
   int64_t *cost;      // [1]
   int64_t *u, *v;     // [nr], [n] or null
   ot_stats *stats;    // [1] or null
-  int32_t *ws;        // [ws_ints(n)]
+  int32_t *ws;        // [ws_ints(n)] per workgroup
+  uint64_t *grid_ws = nullptr;  // several workgroups per instance: [grid_ws_u64(G, per)], zeroed
 };
 
 __device__ __forceinline__ uint64_t pack(int64_t val, int row) {
@@ -204,7 +217,12 @@ __device__ __forceinline__ int64_t now_ticks() { return (int64_t)wall_clock64();
 
 // LONG: also sweep long frontiers in chunks of 2U rows (more registers; used by
 // the one-instance kernel, where occupancy does not matter).
-template <int BLOCK, int CPT, bool LONG = false>
+// GRID: one instance over gridDim.x workgroups.  Rows, matches and the forest
+// are replicated in every workgroup's LDS and updated identically; the columns
+// (keys in registers) are split.  Per level the workgroups exchange their
+// minimum keys and the columns they settled through global memory, with a
+// grid barrier after each.
+template <int BLOCK, int CPT, bool LONG = false, bool GRID = false>
 struct Engine {
   static constexpr int NW = BLOCK / 64;
 
@@ -235,8 +253,15 @@ struct Engine {
   uint32_t stl;   // bit k: k1 is only a lower bound (its tree is gone)
   int tid, lane, wid;
   int err_local;  // this thread's first error (0 = none); reduced at every level
+  // GRID
+  int G, g, epoch;
+  uint32_t lev;  // current level, the tag of this level's exchanges (from 1)
+  uint64_t *gws;
 
-  __device__ __forceinline__ int col(int k) const { return tid + k * BLOCK; }
+  __device__ __forceinline__ int col(int k) const {
+    if constexpr (GRID) return tid + g * BLOCK + k * BLOCK * G;
+    else return tid + k * BLOCK;
+  }
   // Always-valid column for loads: loads are issued unconditionally (a guarded
   // load becomes a branch plus a full wait for memory), values of columns past
   // n are ignored afterwards.
@@ -456,6 +481,91 @@ struct Engine {
     }
     if (err_local != 0) atomicMin(&ctl[es], err_local);  // rare: only lanes that saw an error
   }
+  // GRID: barrier over the instance's workgroups (thread 0 arrives and waits).
+  // Every wait is bounded: one that runs out raises the abort flag, a raised
+  // flag ends every other wait, and the caller leaves its loop, so the kernel
+  // always finishes.  Returns true on abort.
+  static constexpr int kSpinLimit = 1 << 21;  // sleeps of ~64 cycles: ~50 ms
+  __device__ __forceinline__ bool grid_sync() {
+    __syncthreads();
+    if (tid == 0) {
+      int *bar = (int *)(gws + kGBar), *ab = (int *)(gws + kGAbort);
+      int stop = __hip_atomic_load(ab, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (!stop) {
+        ++epoch;
+        __hip_atomic_fetch_add(bar, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        const int target = epoch * G;
+        for (int s = 0; __hip_atomic_load(bar, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target; ++s) {
+          if (__hip_atomic_load(ab, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) { stop = 1; break; }
+          if (s > kSpinLimit) { __hip_atomic_store(ab, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); stop = 1; break; }
+          __builtin_amdgcn_s_sleep(1);
+        }
+      }
+      ctl[GAB] = stop;
+    }
+    __syncthreads();
+    return ctl[GAB] != 0;
+  }
+
+  // GRID exchanges.  Every word a workgroup publishes carries the level it
+  // belongs to, so a reader fetches tags and data in one round and polls until
+  // all of them show the current level: minimum words hold (level mod 2^24) <<
+  // 40 | key value (40 bits), the error word level << 32 | error, settled
+  // columns (level mod 2^28) << 36 | column << 24 | row << 12 | tree, and a
+  // list's count word level << 32 | count.  Polls are bounded and end on the
+  // abort flag.
+  __device__ __forceinline__ bool poll_abort(int s) {
+    int ab = 0;
+    if ((s & 31) == 31) {
+      ab = lane == 0 ? __hip_atomic_load((int *)(gws + kGAbort), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0;
+      ab = __builtin_amdgcn_readfirstlane(ab);
+    }
+    if (s > kSpinLimit) {
+      if (lane == 0) __hip_atomic_store((int *)(gws + kGAbort), 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      ab = 1;
+    }
+    return ab != 0;
+  }
+  static __device__ __forceinline__ uint64_t enc_min(uint64_t key, uint32_t lv) {
+    return ((uint64_t)(lv & 0xffffffu) << 40) | (key >> kRowBits);
+  }
+  static __device__ __forceinline__ uint64_t dec_min(uint64_t w) {
+    const uint64_t v = w & 0xffffffffffull;
+    return v == 0xffffffffffull ? kInf : v << kRowBits;
+  }
+
+  // GRID: publish this workgroup's slot set s (minimum pair, error es), read
+  // every workgroup's, and replace the local values by the minima over all of
+  // them.  The caller has issued the barrier after reduce_min.  Returns true on
+  // abort.
+  __device__ __forceinline__ bool grid_min(int s, int es) {
+    uint64_t *slot = gws + kGMin + ((size_t)s * kMaxWgs) * 3;
+    if (wid == 0) {
+      if (lane == 0) {
+        __hip_atomic_store(&slot[3 * g], enc_min(red[2 * s], lev), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&slot[3 * g + 1], enc_min(red[2 * s + 1], lev), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&slot[3 * g + 2], ((uint64_t)lev << 32) | (uint32_t)ctl[es], __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+      }
+      const int w = lane / 3, k = lane - 3 * (lane / 3);
+      uint64_t x = 0;
+      bool stop = false;
+      for (int it = 0;; ++it) {
+        if (w < G) x = __hip_atomic_load(&slot[3 * w + k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const bool ok = w >= G || (k < 2 ? (uint32_t)(x >> 40) == (lev & 0xffffffu) : (uint32_t)(x >> 32) == lev);
+        if (__builtin_amdgcn_ballot_w64(!ok) == 0) break;
+        if (poll_abort(it)) { stop = true; break; }
+        __builtin_amdgcn_s_sleep(1);
+      }
+      const uint64_t a = wave_min_u64(w < G && k == 0 ? dec_min(x) : kInf);
+      const uint64_t b = wave_min_u64(w < G && k == 1 ? dec_min(x) : kInf);
+      const int ee = wave_min_i32(w < G && k == 2 ? (int)(uint32_t)x : 0);
+      if (lane == 0) { red[2 * s] = a; red[2 * s + 1] = b; ctl[es] = ee; ctl[GAB] = stop ? 1 : 0; }
+    }
+    __syncthreads();
+    return ctl[GAB] != 0;
+  }
+
   __device__ __forceinline__ void reset_slots(int s, int es) {
     red[2 * s] = kInf;
     red[2 * s + 1] = kInf;
@@ -590,8 +700,14 @@ struct Engine {
     red = (uint64_t *)(smem + L.red);
     ctl = (int32_t *)(smem + L.ctl);
     gcap = gather_cap(n);
-    auglist = P.ws;
-    bend = P.ws + n;
+    if constexpr (GRID) {
+      G = gridDim.x; g = blockIdx.x; epoch = 0; lev = 0;
+      gws = P.grid_ws;
+      auglist = P.ws + (size_t)g * ws_ints(n);
+    } else {
+      auglist = P.ws;
+    }
+    bend = auglist + n;
 
     const int K = (P.max_paths <= 0 || P.max_paths > nr) ? nr : P.max_paths;
     int64_t st_levels = 0, st_dual = 0, st_aug = 0, st_paths = 0, st_rows = 0, st_gath = 0, st_resw = 0;
@@ -724,12 +840,14 @@ struct Engine {
 
     int nfree = nr, nalive = K, cursor = K;
     int64_t D = 0;
-    const int64_t watchdog = (int64_t)(n + 2) * (int64_t)(n + 2) + 64;
+    int64_t watchdog = (int64_t)(n + 2) * (int64_t)(n + 2) + 64;
+    if (GRID && watchdog > (1 << 24) - 2) watchdog = (1 << 24) - 2;  // exchange tags hold 24 bits of the level
     const bool timers = (P.flags & OT_FLAG_PHASE_TIMERS) != 0;
     int64_t tprev = timers ? now_ticks() : 0;
 
     while (nfree > 0) {
       const int ps = cur;  // slot parity of this level
+      if constexpr (GRID) ++lev;
       // (1) fold the rows that joined last step into the keys
       const int nf = ctl[cur == 0 ? CNT0 : CNT1];
       st_rows += sweep_frontier(nf);
@@ -738,11 +856,14 @@ struct Engine {
       // (2) smallest key over unreached columns
       reduce_min(ps, ERRA0 + ps);
       if (tid == 0) {
-        ctl[cur == 0 ? CNT1 : CNT0] = 0; ctl[NAUG] = 0; ctl[GCNT] = 0;
+        ctl[cur == 0 ? CNT1 : CNT0] = 0; ctl[NAUG] = 0; ctl[GCNT] = 0; ctl[LCNT] = 0;
         reset_slots(ps ^ 1, ERRA0 + (ps ^ 1));
         reset_slots(2 + (ps ^ 1), ERRB0 + (ps ^ 1));
       }
       __syncthreads();
+      if constexpr (GRID) {
+        if (grid_min(ps, ERRA0 + ps)) { fail(OT_EINTERNAL); break; }
+      }
       uint64_t mv = red[2 * ps], ms = red[2 * ps + 1];
       int berr = ctl[ERRA0 + ps];
       if (berr == 0 && ms != kInf && (mv == kInf || kval(ms) <= kval(mv))) {
@@ -756,6 +877,9 @@ struct Engine {
         if (resweep) { ++st_resw; st_rows += swept; }
         reduce_min(2 + ps, ERRB0 + ps);
         __syncthreads();
+        if constexpr (GRID) {
+          if (grid_min(2 + ps, ERRB0 + ps)) { fail(OT_EINTERNAL); break; }
+        }
         mv = red[2 * (2 + ps)];
         berr = ctl[ERRB0 + ps];
       }
@@ -775,6 +899,98 @@ struct Engine {
       // the next frontier overwrites this one: every wavefront finished
       // reading it before the barrier above
       int *nxtcnt = &ctl[cur == 0 ? CNT1 : CNT0];
+      if constexpr (GRID) {
+        // settle the owned columns, publish them, and apply every workgroup's
+        // list to the replicated state
+        const int per = BLOCK * CPT;
+        uint64_t *lists = gws + kGList + (size_t)ps * G * (per + 1);  // this parity's lists
+        uint64_t *lst = lists + (size_t)g * (per + 1);                // count word, then entries
+        const uint64_t etag = (uint64_t)(lev & 0xfffffffu) << 36;
+#pragma unroll
+        for (int k = 0; k < CPT; ++k) {
+          const int j = col(k);
+          if (j >= n || ((vis >> k) & 1u) || k1[k] == kInf || stale(k) || kval(k1[k]) != D) continue;
+          vis |= 1u << k;
+          dcol[k] = (int32_t)D;
+          ctree[k] = t1[k];
+          const uint64_t e = etag | ((uint64_t)j << 24) | ((uint64_t)krow(k1[k]) << 12) | (uint64_t)(uint32_t)t1[k];
+          __hip_atomic_store(&lst[1 + atomicAdd(&ctl[LCNT], 1)], e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        __syncthreads();
+        // wavefront 0 reads every workgroup's count word and its first L - 1
+        // entries in one round (L lanes per workgroup); later entries, if any,
+        // are polled one by one below
+        const int L = 64 / G;
+        uint64_t *spec = red + 16;     // [G][L - 1] entries read with the counts
+        int *gc = (int *)(red + 112);  // gc[w] = first entry of workgroup w, gc[G] = total
+        if (wid == 0) {
+          if (lane == 0)
+            __hip_atomic_store(lst, ((uint64_t)lev << 32) | (uint32_t)ctl[LCNT], __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+          const int w = lane / L, k = lane - w * L;
+          uint64_t x = 0;
+          int cnt = 0;
+          bool stop = false;
+          for (int it = 0;; ++it) {
+            if (w < G) x = __hip_atomic_load(lists + (size_t)w * (per + 1) + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const uint64_t hdr = __shfl(x, w < G ? w * L : 0, 64);
+            const bool hok = w >= G || (uint32_t)(hdr >> 32) == lev;
+            cnt = (w < G && hok) ? (int)(uint32_t)hdr : 0;
+            const bool ok = hok && (w >= G || k == 0 || k - 1 >= cnt || (x >> 36) == (lev & 0xfffffffu));
+            if (__builtin_amdgcn_ballot_w64(!ok) == 0) break;
+            if (poll_abort(it)) { stop = true; break; }
+            __builtin_amdgcn_s_sleep(1);
+          }
+          if (!stop && w < G && k >= 1 && k - 1 < cnt) spec[w * (L - 1) + (k - 1)] = x;
+          if (lane == 0) {
+            int acc = 0;
+            for (int v = 0; v < G; ++v) {
+              gc[v] = acc;
+              acc += __builtin_amdgcn_readlane(cnt, v * L);
+            }
+            gc[G] = acc;
+            ctl[GAB] = stop ? 1 : 0;
+          }
+        }
+        __syncthreads();
+        if (ctl[GAB]) { fail(OT_EINTERNAL); break; }
+        const int tot = gc[G];
+        for (int q = tid; q < tot; q += BLOCK) {
+          int w = 0;
+          while (w + 1 < G && gc[w + 1] <= q) ++w;
+          const int idx = q - gc[w];
+          if (idx >= per) { fail(OT_EINTERNAL); continue; }
+          uint64_t e;
+          if (idx < L - 1) {
+            e = spec[w * (L - 1) + idx];
+          } else {
+            const uint64_t *src = lists + (size_t)w * (per + 1) + 1 + idx;
+            int it = 0;
+            for (;; ++it) {
+              e = __hip_atomic_load(src, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+              if ((e >> 36) == (lev & 0xfffffffu) || it > kSpinLimit) break;
+              __builtin_amdgcn_s_sleep(1);
+            }
+            if (it > kSpinLimit) { fail(OT_EINTERNAL); continue; }
+          }
+          const int j = (int)((e >> 24) & 0xfff), p = (int)((e >> 12) & 0xfff), tr = (int)(e & 0xfff);
+          if (j >= n || p >= nr || tr >= nr) { fail(OT_EINTERNAL); continue; }
+          par[j] = p;
+          const int mc = mcol[j];
+          if (mc < 0) {
+            if (atomicMin(&bend[tr], j) == kNoEnd) {
+              const int s = atomicAdd(&ctl[NAUG], 1);
+              auglist[s] = tr;
+            }
+          } else {
+            rtree[mc] = tr;
+            const int64_t hm = hrow[mc] - D;
+            hrow[mc] = hm;
+            fr[atomicAdd(nxtcnt, 1)] = frontier_rec(mc, tr, hm);
+            fst[atomicAdd(&ctl[FCNT], 1)] = mc;
+          }
+        }
+      } else {
 #pragma unroll
       for (int k = 0; k < CPT; ++k) {
         const int j = col(k);
@@ -799,6 +1015,7 @@ struct Engine {
           fr[atomicAdd(nxtcnt, 1)] = frontier_rec(mc, tr, hm);
           fst[atomicAdd(&ctl[FCNT], 1)] = mc;
         }
+      }
       }
       __syncthreads();
       const int naug = ctl[NAUG];
@@ -901,8 +1118,32 @@ struct Engine {
     __syncthreads();
     if (err_local != 0) atomicMin(&ctl[ERR], err_local);
     __syncthreads();
-    const int err = ctl[ERR];
-    if (err == 0) {
+    int err = ctl[ERR];
+    if constexpr (GRID) {
+      // one error and the gathers over all workgroups (every workgroup left the
+      // loop at the same level; after an abort the barrier returns at once)
+      if (tid == 0) {
+        __hip_atomic_store(gws + kGFin + g, (uint64_t)(uint32_t)err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(gws + kGGath + g, (uint64_t)st_gath, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+      const bool aborted = grid_sync();
+      if (tid == 0) {
+        int e = aborted ? OT_EINTERNAL : 0;
+        int64_t gath = 0;
+        if (!aborted)
+          for (int w = 0; w < G; ++w) {
+            e = min(e, (int)(uint32_t)__hip_atomic_load(gws + kGFin + w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+            gath += (int64_t)__hip_atomic_load(gws + kGGath + w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          }
+        ctl[ERR] = e;
+        red[0] = (uint64_t)gath;
+      }
+      __syncthreads();
+      err = ctl[ERR];
+      st_gath = (int64_t)red[0];
+      __syncthreads();
+    }
+    if (err == 0 && (!GRID || g == 0)) {
       int64_t part = 0;
       const int32_t *Cr = P.Cout ? P.Cout : C;
       const size_t ldr = P.Cout ? (size_t)P.ldo : (size_t)ld;
@@ -911,11 +1152,6 @@ struct Engine {
         P.plan[i] = j;
         if (P.u) P.u[i] = hrow[i] * P.dscale;
         part += (j >= 0 && j < n) ? (int64_t)Cr[(size_t)i * ldr + j] : 0;
-      }
-      if (P.v) {
-#pragma unroll
-        for (int k = 0; k < CPT; ++k)
-          if (col(k) < n) P.v[col(k)] = (int64_t)vj[k] * P.dscale;
       }
       part = wave_sum_i64(part);
       int64_t *sred = (int64_t *)(red + 16);
@@ -927,7 +1163,12 @@ struct Engine {
         *P.cost = tot;
       }
     }
-    if (P.stats && tid == 0) {
+    if (err == 0 && P.v) {
+#pragma unroll
+      for (int k = 0; k < CPT; ++k)
+        if (col(k) < n) P.v[col(k)] = (int64_t)vj[k] * P.dscale;
+    }
+    if (P.stats && tid == 0 && (!GRID || g == 0)) {
       ot_stats s;
       s.levels = st_levels; s.dual_adjusts = st_dual; s.aug_events = st_aug; s.paths = st_paths;
       s.rows_swept = st_rows; s.gathers = st_gath; s.resweeps = st_resw; s.status = err;

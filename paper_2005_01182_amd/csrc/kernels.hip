@@ -27,6 +27,23 @@ __global__ __launch_bounds__(BLOCK) void k_assign_one(Problem P, const int32_t *
 }
 
 // ---------------------------------------------------------------------------
+// one instance over gridDim.x workgroups (P.grid_ws header zeroed before the
+// launch; the grid is at most kMaxWgs workgroups, one per CU, so all of them
+// are resident at once)
+// ---------------------------------------------------------------------------
+template <int BLOCK, int CPT>
+__global__ __launch_bounds__(BLOCK) void k_assign_grid(Problem P) {
+  extern __shared__ __align__(16) char smem[];
+  Engine<BLOCK, CPT, true, true> E;
+  E.run(P, smem);
+}
+
+__global__ void k_fill_u64(uint64_t *p, uint64_t value, int64_t count) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = value;
+}
+
+// ---------------------------------------------------------------------------
 // persistent batch: each workgroup pops instance indices until the queue is empty
 // ---------------------------------------------------------------------------
 // Two wavefronts per SIMD: the register budget drops to 256 (a few bytes of
@@ -424,9 +441,34 @@ static hipError_t one(const Problem &P, const int32_t *gate, hipStream_t s) {
   return hipGetLastError();
 }
 
+template <int B, int CPT>
+static hipError_t grid(const Problem &P, int wgs, hipStream_t s) {
+  const size_t lds = lds_layout(P.n).total;
+  hipError_t e = allow_lds(k_assign_grid<B, CPT>, lds);
+  if (e != hipSuccess) return e;
+  // every tag word must start below the first level
+  hipLaunchKernelGGL(k_fill_u64, dim3(16), dim3(256), 0, s, P.grid_ws, (uint64_t)0,
+                     (int64_t)grid_ws_u64(wgs, B * CPT));
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL((k_assign_grid<B, CPT>), dim3(wgs), dim3(B), lds, s, P);
+  return hipGetLastError();
+}
+
 int cpt_for(int n, int block) {
   const int need = (n + block - 1) / block;
   return need <= 1 ? 1 : need <= 2 ? 2 : need <= 4 ? 4 : need <= 8 ? 8 : 0;
+}
+
+// One instance over `wgs` workgroups of `block` threads: P.ws holds wgs *
+// ws_ints(n) ints and P.grid_ws grid_ws_u64(wgs, block * cpt) words.
+hipError_t launch_assign_grid(const Problem &P, int block, int wgs, hipStream_t s) {
+  if (wgs < 2 || wgs > kMaxWgs || !P.grid_ws) return hipErrorInvalidValue;
+  const int cpt = cpt_for(P.n, block * wgs);
+#define OTKM_GRID(B, K) if (block == B && cpt == K) return grid<B, K>(P, wgs, s);
+  OTKM_GRID(256, 1) OTKM_GRID(256, 2) OTKM_GRID(256, 4)
+  OTKM_GRID(512, 1) OTKM_GRID(512, 2) OTKM_GRID(512, 4)
+#undef OTKM_GRID
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_assign_one(const Problem &P, int block, const int32_t *gate, hipStream_t s) {

@@ -43,6 +43,7 @@ struct TransportArgs {
 int cpt_for(int n, int block);
 int batch_occupancy(int block, int max_n);
 hipError_t launch_assign_one(const Problem &P, int block, const int32_t *gate, hipStream_t s);
+hipError_t launch_assign_grid(const Problem &P, int block, int wgs, hipStream_t s);
 hipError_t launch_assign_batch(const BatchArgs &A, int block, int grid, hipStream_t s);
 hipError_t launch_fill_i32(int32_t *p, int32_t value, int64_t count, hipStream_t s);
 hipError_t launch_transport(const TransportArgs &T, int block, hipStream_t s);

@@ -148,23 +148,69 @@ static bool range_ok(const int32_t *C, int64_t count) {
   return (int64_t)mx - (int64_t)mn <= 0x7fffffffll;
 }
 
-static int check_options(const ot_options *opt, int n, int *block, int *max_paths, int *flags, int *scale) {
-  *block = default_block(n);
-  *max_paths = 0;
-  *flags = 0;
-  *scale = 1;
-  if (!opt) return OT_OK;
-  for (int k = 0; k < 4; ++k)
-    if (opt->reserved[k] != 0) return OT_EINVAL;
-  if (opt->max_paths < 0 || (opt->flags & ~OT_FLAG_PHASE_TIMERS) != 0 || opt->scale < 0) return OT_EINVAL;
-  *max_paths = opt->max_paths;
-  *flags = opt->flags;
-  *scale = opt->scale > 1 ? opt->scale : 1;
-  if (opt->block != 0) {
-    if (!block_ok(opt->block, n)) return OT_EINVAL;
-    *block = opt->block;
+// Workgroups per single instance when neither ot_options.wgs nor .block is
+// set, as measured on MI355X (geometric instances): the per-step exchange
+// through global memory costs about as much as splitting the sweep saves at
+// n = 2048 (128.8 vs 126.2 ms), and wins above (n = 2560: 295 -> 197 ms,
+// n = 4096: 644 -> 350 ms with 8 workgroups).  Scaled costs make fewer, wider
+// steps, where the split pays from n = 2048 down (s = 100: 76.4 -> 33.3 ms
+// with 4 workgroups).
+static int default_wgs(int n, int scale) {
+  if (scale > 1) return n > 1024 ? 4 : 1;
+  return n > 2048 ? 8 : 1;
+}
+
+struct Opts {
+  int block, max_paths, flags, scale, wgs;
+};
+
+static int check_options(const ot_options *opt, int n, Opts *o) {
+  o->block = default_block(n);
+  o->max_paths = 0;
+  o->flags = 0;
+  o->scale = 1;
+  o->wgs = 1;
+  if (opt) {
+    for (int k = 0; k < 3; ++k)
+      if (opt->reserved[k] != 0) return OT_EINVAL;
+    if (opt->max_paths < 0 || (opt->flags & ~OT_FLAG_PHASE_TIMERS) != 0 || opt->scale < 0 || opt->wgs < 0 ||
+        opt->wgs > kMaxWgs)
+      return OT_EINVAL;
+    o->max_paths = opt->max_paths;
+    o->flags = opt->flags;
+    o->scale = opt->scale > 1 ? opt->scale : 1;
+    if (opt->wgs > 0) o->wgs = opt->wgs;
+    else if (opt->block == 0) o->wgs = default_wgs(n, o->scale);
+    if (o->wgs == 1 && opt->block != 0) {
+      if (!block_ok(opt->block, n)) return OT_EINVAL;
+      o->block = opt->block;
+    }
+  } else {
+    o->wgs = default_wgs(n, 1);
+  }
+  if (o->wgs > 1) {
+    // several workgroups: 256 or 512 threads each, at most 4 columns per lane
+    const int b = (opt && opt->block != 0) ? opt->block : 512;
+    const int cpt = cpt_for(n, b * o->wgs);
+    if ((b != 256 && b != 512) || cpt == 0 || cpt > 4) return OT_EINVAL;
+    o->block = b;
   }
   return OT_OK;
+}
+
+// Device workspace of the one-instance solve: ints of P.ws, and bytes of the
+// grid state (several workgroups only).
+static size_t solve_ws_ints(int n, const Opts &o) { return ws_ints(n) * (size_t)o.wgs; }
+static size_t solve_grid_bytes(int n, const Opts &o) {
+  return o.wgs > 1 ? 8 * grid_ws_u64(o.wgs, o.block * cpt_for(n, o.block * o.wgs)) : 16;
+}
+
+static hipError_t launch_solve(Problem &P, const Opts &o, uint64_t *gws, hipStream_t s) {
+  if (o.wgs > 1) {
+    P.grid_ws = gws;
+    return launch_assign_grid(P, o.block, o.wgs, s);
+  }
+  return launch_assign_one(P, o.block, nullptr, s);
 }
 
 }  // namespace otkm
@@ -201,9 +247,10 @@ int ot_assign_ex(const int32_t *C, int32_t n, const ot_options *opt, int32_t *pl
                  int64_t *v, ot_stats *stats) {
   if (!C || !plan || !cost || n <= 0) return OT_EINVAL;
   if (n > OT_MAX_N) return OT_ETOOBIG;
-  int block, max_paths, flags, scale;
-  int rc = check_options(opt, n, &block, &max_paths, &flags, &scale);
+  Opts o;
+  int rc = check_options(opt, n, &o);
   if (rc) return rc;
+  const int scale = o.scale;
   if (!range_ok(C, (int64_t)n * n)) return OT_ERANGE;
 
   std::lock_guard<std::mutex> lk(g_mu);
@@ -216,7 +263,8 @@ int ot_assign_ex(const int32_t *C, int32_t n, const ot_options *opt, int32_t *pl
   auto *dv = (int64_t *)pool_get(3, 8 * N, &err);
   auto *dcost = (int64_t *)pool_get(4, 8, &err);
   auto *dstats = (ot_stats *)pool_get(5, sizeof(ot_stats), &err);
-  auto *dws = (int32_t *)pool_get(6, 4 * ws_ints(n), &err);
+  auto *dws = (int32_t *)pool_get(6, 4 * solve_ws_ints(n, o), &err);
+  auto *dgws = (uint64_t *)pool_get(84, solve_grid_bytes(n, o), &err);
   auto *dCT = (int32_t *)pool_get(7, 4 * N * N, &err);
   auto *dCs = scale > 1 ? (int32_t *)pool_get(8, 4 * N * N, &err) : nullptr;
   if (err) return err;
@@ -236,11 +284,11 @@ int ot_assign_ex(const int32_t *C, int32_t n, const ot_options *opt, int32_t *pl
   if (err) return err;
   if ((e = launch_init_sweeps(dsolve, n, n, n, du0, drmax, dpart, db, s)) != hipSuccess) return map_hip(e);
   Problem P;
-  P.C = dsolve; P.n = n; P.ld = n; P.CT = dCT; P.max_paths = max_paths; P.flags = flags;
+  P.C = dsolve; P.n = n; P.ld = n; P.CT = dCT; P.max_paths = o.max_paths; P.flags = o.flags;
   P.Cout = dC; P.ldo = n; P.dscale = scale;
   P.init_u = du0; P.init_b = db; P.init_rmax = drmax;
   P.plan = dplan; P.cost = dcost; P.u = du; P.v = dv; P.stats = dstats; P.ws = dws;
-  if ((e = launch_assign_one(P, block, nullptr, s)) != hipSuccess) return map_hip(e);
+  if ((e = launch_solve(P, o, dgws, s)) != hipSuccess) return map_hip(e);
   ot_stats hs;
   std::vector<int32_t> hplan(N);
   std::vector<int64_t> hu(N), hv(N);
@@ -268,14 +316,16 @@ int ot_assign_dev(const int32_t *dC, int32_t n, int32_t ld, const ot_options *op
                   int64_t *du, int64_t *dv, ot_stats *dstats, void *stream) {
   if (!dC || !dplan || !dcost || n <= 0 || ld < n) return OT_EINVAL;
   if (n > OT_MAX_N) return OT_ETOOBIG;
-  int block, max_paths, flags, scale;
-  int rc = check_options(opt, n, &block, &max_paths, &flags, &scale);
+  Opts o;
+  int rc = check_options(opt, n, &o);
   if (rc) return rc;
+  const int scale = o.scale;
   std::lock_guard<std::mutex> lk(g_mu);
   if ((rc = init_locked())) return rc;
   hipStream_t s = stream ? (hipStream_t)stream : g_stream;
   int err = OT_OK;
-  auto *dws = (int32_t *)stream_ws(s, 0, 4 * ws_ints(n), &err);
+  auto *dws = (int32_t *)stream_ws(s, 0, 4 * solve_ws_ints(n, o), &err);
+  auto *dgws = (uint64_t *)stream_ws(s, 44, solve_grid_bytes(n, o), &err);
   auto *dCT = (int32_t *)stream_ws(s, 3, 4 * (size_t)n * (size_t)n, &err);
   auto *dCs = scale > 1 ? (int32_t *)stream_ws(s, 4, 4 * (size_t)n * (size_t)n, &err) : nullptr;
   if (err) return err;
@@ -295,11 +345,11 @@ int ot_assign_dev(const int32_t *dC, int32_t n, int32_t ld, const ot_options *op
   if (err) return err;
   if ((e = launch_init_sweeps(dsolve, n, n, lds, du0, drmax, dpart, db, s)) != hipSuccess) return map_hip(e);
   Problem P;
-  P.C = dsolve; P.n = n; P.ld = lds; P.CT = dCT; P.max_paths = max_paths; P.flags = flags;
+  P.C = dsolve; P.n = n; P.ld = lds; P.CT = dCT; P.max_paths = o.max_paths; P.flags = o.flags;
   P.Cout = dC; P.ldo = ld; P.dscale = scale;
   P.init_u = du0; P.init_b = db; P.init_rmax = drmax;
   P.plan = dplan; P.cost = dcost; P.u = du; P.v = dv; P.stats = dstats; P.ws = dws;
-  return map_hip(launch_assign_one(P, block, nullptr, s));
+  return map_hip(launch_solve(P, o, dgws, s));
 }
 
 }  // extern "C"
@@ -312,12 +362,13 @@ namespace otkm {
 // Then the grid-wide reduction sweeps, the one-instance engine and the
 // rectangular outputs.  `get(slot, bytes)` hands out workspace.
 template <class Get>
-static int rect_pipeline(const int32_t *dC, int n, int m, int ld, int block, int max_paths, int flags, Get get,
-                         hipStream_t s, int32_t *dplan, int64_t *dcost, int64_t *du, int64_t *dv, ot_stats *dstats) {
+static int rect_pipeline(const int32_t *dC, int n, int m, int ld, const Opts &o, Get get, hipStream_t s,
+                         int32_t *dplan, int64_t *dcost, int64_t *du, int64_t *dv, ot_stats *dstats) {
   const bool trans = n > m;
   const int nr = trans ? m : n, nc = trans ? n : m;  // solver rows <= solver columns
   auto *T = (int32_t *)get(0, 4 * (size_t)n * (size_t)m);
-  auto *ws = (int32_t *)get(2, 4 * ws_ints(nc));
+  auto *ws = (int32_t *)get(2, 4 * solve_ws_ints(nc, o));
+  auto *gws = (uint64_t *)get(12, solve_grid_bytes(nc, o));
   auto *pq = (int32_t *)get(3, 4 * (size_t)nr);
   auto *uq = (int64_t *)get(4, 8 * (size_t)nr);
   auto *vq = (int64_t *)get(5, 8 * (size_t)nc);
@@ -327,7 +378,7 @@ static int rect_pipeline(const int32_t *dC, int n, int m, int ld, int block, int
   auto *rmax = (int32_t *)get(9, 4 * (size_t)nr);
   auto *part = (uint64_t *)get(10, init_part_bytes(nr, nc));
   auto *b = (uint64_t *)get(11, 16 * (size_t)nc);
-  if (!T || !ws || !pq || !uq || !vq || !cq || !sq || !u0 || !rmax || !part || !b) return OT_ENOMEM;
+  if (!T || !ws || !gws || !pq || !uq || !vq || !cq || !sq || !u0 || !rmax || !part || !b) return OT_ENOMEM;
   hipError_t e;
   // the transpose of C (m x n, row stride n) is the solver matrix (trans) or its transpose
   if ((e = launch_transpose(dC, n, m, ld, T, s)) != hipSuccess) return map_hip(e);
@@ -335,23 +386,22 @@ static int rect_pipeline(const int32_t *dC, int n, int m, int ld, int block, int
   const int lda = trans ? n : ld;
   if ((e = launch_init_sweeps(A, nr, nc, lda, u0, rmax, part, b, s)) != hipSuccess) return map_hip(e);
   Problem P;
-  P.C = A; P.n = nc; P.nr = nr; P.ld = lda; P.max_paths = max_paths; P.flags = flags;
+  P.C = A; P.n = nc; P.nr = nr; P.ld = lda; P.max_paths = o.max_paths; P.flags = o.flags;
   P.CT = trans ? dC : T; P.ldt = trans ? ld : n;
   P.Cout = nullptr; P.ldo = lda; P.dscale = 1;
   P.init_u = u0; P.init_b = b; P.init_rmax = rmax;
   P.plan = pq; P.cost = cq; P.u = uq; P.v = vq; P.stats = sq; P.ws = ws;
-  if ((e = launch_assign_one(P, block, nullptr, s)) != hipSuccess) return map_hip(e);
+  if ((e = launch_solve(P, o, gws, s)) != hipSuccess) return map_hip(e);
   return map_hip(launch_rect_finish(n, m, trans, pq, uq, vq, cq, sq, dplan, dcost, du, dv, dstats, s));
 }
 
-static int rect_check(int32_t n, int32_t m, const ot_options *opt, int *block, int *max_paths, int *flags) {
+static int rect_check(int32_t n, int32_t m, const ot_options *opt, Opts *o) {
   if (n <= 0 || m <= 0) return OT_EINVAL;
   const int M = std::max(n, m);
   if (M > OT_MAX_N) return OT_ETOOBIG;
-  int scale;
-  int rc = check_options(opt, M, block, max_paths, flags, &scale);
+  int rc = check_options(opt, M, o);
   if (rc) return rc;
-  return scale > 1 ? OT_EINVAL : OT_OK;
+  return o->scale > 1 ? OT_EINVAL : OT_OK;
 }
 
 }  // namespace otkm
@@ -361,8 +411,8 @@ extern "C" {
 int ot_assign_rect(const int32_t *C, int32_t n, int32_t m, const ot_options *opt, int32_t *plan, int64_t *cost,
                    int64_t *u, int64_t *v, ot_stats *stats) {
   if (!C || !plan || !cost) return OT_EINVAL;
-  int block, max_paths, flags;
-  int rc = rect_check(n, m, opt, &block, &max_paths, &flags);
+  Opts o;
+  int rc = rect_check(n, m, opt, &o);
   if (rc) return rc;
   if (!range_ok(C, (int64_t)n * m)) return OT_ERANGE;
   std::lock_guard<std::mutex> lk(g_mu);
@@ -380,7 +430,7 @@ int ot_assign_rect(const int32_t *C, int32_t n, int32_t m, const ot_options *opt
   hipError_t e = hipMemcpyAsync(dC, C, 4 * NM, hipMemcpyHostToDevice, s);
   if (e != hipSuccess) return map_hip(e);
   auto get = [&](int slot, size_t bytes) { return pool_get(100 + slot, bytes, &err); };
-  rc = rect_pipeline(dC, n, m, m, block, max_paths, flags, get, s, dplan, dcost, du, dv, dstats);
+  rc = rect_pipeline(dC, n, m, m, o, get, s, dplan, dcost, du, dv, dstats);
   if (err) return err;
   if (rc) return rc;
   ot_stats hs;
@@ -406,15 +456,15 @@ int ot_assign_rect(const int32_t *C, int32_t n, int32_t m, const ot_options *opt
 int ot_assign_rect_dev(const int32_t *dC, int32_t n, int32_t m, int32_t ld, const ot_options *opt, int32_t *dplan,
                        int64_t *dcost, int64_t *du, int64_t *dv, ot_stats *dstats, void *stream) {
   if (!dC || !dplan || !dcost || ld < m) return OT_EINVAL;
-  int block, max_paths, flags;
-  int rc = rect_check(n, m, opt, &block, &max_paths, &flags);
+  Opts o;
+  int rc = rect_check(n, m, opt, &o);
   if (rc) return rc;
   std::lock_guard<std::mutex> lk(g_mu);
   if ((rc = init_locked())) return rc;
   hipStream_t s = stream ? (hipStream_t)stream : g_stream;
   int err = OT_OK;
   auto get = [&](int slot, size_t bytes) { return stream_ws(s, 100 + slot, bytes, &err); };
-  rc = rect_pipeline(dC, n, m, ld, block, max_paths, flags, get, s, dplan, dcost, du, dv, dstats);
+  rc = rect_pipeline(dC, n, m, ld, o, get, s, dplan, dcost, du, dv, dstats);
   return err ? err : rc;
 }
 

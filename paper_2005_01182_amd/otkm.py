@@ -44,7 +44,7 @@ STATS_FIELDS = [name for name, _ in ot_stats._fields_]
 
 class ot_options(ctypes.Structure):
     _fields_ = [("max_paths", ctypes.c_int32), ("block", ctypes.c_int32), ("flags", ctypes.c_int32),
-                ("scale", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
+                ("scale", ctypes.c_int32), ("wgs", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
 
 
 OT_FLAG_PHASE_TIMERS = 1
@@ -148,18 +148,19 @@ def device_info() -> dict:
             "mem_gb": props.total_memory / 2**30}
 
 
-def _options(max_paths=0, block=0, timers=False, scale=1):
+def _options(max_paths=0, block=0, timers=False, scale=1, wgs=0):
     o = ot_options()
     o.max_paths = int(max_paths)
     o.block = int(block)
     o.flags = OT_FLAG_PHASE_TIMERS if timers else 0
     o.scale = int(scale)
+    o.wgs = int(wgs)
     return o
 
 
 # ----------------------------------------------------------------------------- host calls
 def ot_assign(C, max_paths: int = 0, block: int = 0, with_stats: bool = False, timers: bool = False,
-              scale: int = 1):
+              scale: int = 1, wgs: int = 0):
     """Assignment of a square int32 cost matrix (exact; with scale > 1, optimal for floor(C / scale)).
 
     Returns (plan, cost, u, v) or (plan, cost, u, v, stats_dict).  With scale > 1
@@ -175,7 +176,7 @@ def ot_assign(C, max_paths: int = 0, block: int = 0, with_stats: bool = False, t
     v = np.empty(n, np.int64)
     cost = ctypes.c_int64(0)
     st = ot_stats()
-    opt = _options(max_paths, block, timers, scale)
+    opt = _options(max_paths, block, timers, scale, wgs)
     rc = load().ot_assign_ex(_p(C), n, ctypes.byref(opt), _p(plan), ctypes.byref(cost), _p(u), _p(v),
                              ctypes.byref(st))
     _check(rc, "ot_assign")
@@ -183,7 +184,8 @@ def ot_assign(C, max_paths: int = 0, block: int = 0, with_stats: bool = False, t
     return out + (st.as_dict(),) if with_stats else out
 
 
-def ot_assign_rect(C, max_paths: int = 0, block: int = 0, with_stats: bool = False, timers: bool = False):
+def ot_assign_rect(C, max_paths: int = 0, block: int = 0, with_stats: bool = False, timers: bool = False,
+                   wgs: int = 0):
     """Rectangular assignment of an n x m int32 cost matrix (n != m allowed): the
     smaller side matched completely, the larger side at most once.
 
@@ -200,7 +202,7 @@ def ot_assign_rect(C, max_paths: int = 0, block: int = 0, with_stats: bool = Fal
     v = np.empty(m, np.int64)
     cost = ctypes.c_int64(0)
     st = ot_stats()
-    opt = _options(max_paths, block, timers)
+    opt = _options(max_paths, block, timers, wgs=wgs)
     rc = load().ot_assign_rect(_p(C), n, m, ctypes.byref(opt), _p(plan), ctypes.byref(cost), _p(u), _p(v),
                                ctypes.byref(st))
     _check(rc, "ot_assign_rect")
@@ -285,22 +287,22 @@ def stats_tensor(count=1, device="cuda"):
 
 
 def ot_assign_dev(C, plan, cost, u=None, v=None, stats=None, max_paths=0, block=0, stream=None, ld=None,
-                  timers=False, scale=1):
+                  timers=False, scale=1, wgs=0):
     """Queue an assignment on device tensors (asynchronous on `stream`)."""
     n = int(C.shape[0])
     ld = int(ld if ld is not None else C.stride(0))
-    opt = _options(max_paths, block, timers, scale)
+    opt = _options(max_paths, block, timers, scale, wgs)
     rc = load().ot_assign_dev(_tp(C), n, ld, ctypes.byref(opt), _tp(plan), _tp(cost), _tp(u), _tp(v),
                               _tp(stats), _stream(stream))
     _check(rc, "ot_assign_dev")
 
 
 def ot_assign_rect_dev(C, plan, cost, u=None, v=None, stats=None, max_paths=0, block=0, stream=None, ld=None,
-                       timers=False):
+                       timers=False, wgs=0):
     """Queue a rectangular assignment on device tensors (asynchronous on `stream`)."""
     n, m = int(C.shape[0]), int(C.shape[1])
     ld = int(ld if ld is not None else C.stride(0))
-    opt = _options(max_paths, block, timers)
+    opt = _options(max_paths, block, timers, wgs=wgs)
     rc = load().ot_assign_rect_dev(_tp(C), n, m, ld, ctypes.byref(opt), _tp(plan), _tp(cost), _tp(u), _tp(v),
                                    _tp(stats), _stream(stream))
     _check(rc, "ot_assign_rect_dev")

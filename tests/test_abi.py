@@ -61,6 +61,12 @@ VALIDATION = textwrap.dedent(r"""
     out["assign_neg_paths"] = code(ot.ot_assign, C, max_paths=-1)
     out["assign_neg_scale"] = code(ot.ot_assign, C, scale=-2)
     out["assign_scale_ok_but_nodev"] = code(ot.ot_assign, C, scale=10)
+    out["wgs_ok_but_nodev"] = code(ot.ot_assign, C, wgs=4)
+    out["wgs_too_many"] = code(ot.ot_assign, C, wgs=17)
+    out["wgs_negative"] = code(ot.ot_assign, C, wgs=-1)
+    out["wgs_bad_block"] = code(ot.ot_assign, C, wgs=2, block=1024)
+    out["wgs_too_few_lanes"] = code(ot.ot_assign, np.zeros((4096, 4096), np.int32), wgs=2, block=256)
+    out["rect_wgs_ok_but_nodev"] = code(ot.ot_assign_rect, np.zeros((3, 5), np.int32), wgs=2)
     R = np.zeros((3, 5), np.int32)
     out["rect_ok_but_nodev"] = code(ot.ot_assign_rect, R)
     out["rect_tall_ok_but_nodev"] = code(ot.ot_assign_rect, np.ascontiguousarray(R.T))
@@ -130,6 +136,12 @@ def test_validation_codes(codes):
     assert codes["assign_neg_scale"] == -1
     assert codes["assign_scale_ok_but_nodev"] == -8
     assert codes["assign_block_too_narrow"] == -1
+    assert codes["wgs_ok_but_nodev"] == -8
+    assert codes["wgs_too_many"] == -1
+    assert codes["wgs_negative"] == -1
+    assert codes["wgs_bad_block"] == -1
+    assert codes["wgs_too_few_lanes"] == -1
+    assert codes["rect_wgs_ok_but_nodev"] == -8
     assert codes["assign_neg_paths"] == -1
     assert codes["rect_ok_but_nodev"] == -8
     assert codes["rect_tall_ok_but_nodev"] == -8
