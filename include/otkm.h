@@ -306,6 +306,21 @@ int ot_schedule_get(int32_t *t64, int32_t *t256);
 int ot_schedule_set(int32_t t64, int32_t t256);
 int ot_schedule_tune(int32_t reps);
 
+/* Single-instance split: an exact single-instance solve (ot_assign,
+ * ot_assign_ex, ot_assign_dev, ot_assign_rect*) whose options leave both wgs
+ * and block at 0 runs on `wgs` workgroups when n (the longer side) exceeds
+ * n_split, else on one.  Defaults measured on MI355X: n_split = 2048, wgs = 8.
+ * (Scaled solves split into 4 above n = 1024.)  ot_split_set: n_split >= 0,
+ * wgs 0 or 2..16, 0 restores a default (OT_EINVAL otherwise); n_split =
+ * OT_MAX_N never splits.  ot_split_tune times one exact solve per size of a
+ * ladder (1536 .. 4096) at 1, 4 and 8 workgroups on synthetic geometric
+ * instances, on a private stream, and sets n_split to the largest size up to
+ * which one workgroup stays fastest (a split must win by 2%) and wgs to the
+ * count that wins at 4096.  It takes a few seconds. */
+int ot_split_get(int32_t *n_split, int32_t *wgs);
+int ot_split_set(int32_t n_split, int32_t wgs);
+int ot_split_tune(void);
+
 #ifdef __cplusplus
 }
 #endif

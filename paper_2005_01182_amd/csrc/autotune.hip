@@ -1,4 +1,5 @@
-// autotune.hip -- size-class schedule for the batch path.
+// autotune.hip -- size-class schedule for the batch path, and the split
+// schedule of single instances.
 //
 // For a ladder of instance sizes, time the persistent batch kernel at each
 // eligible workgroup width (64, 256, 512 lanes) on synthetic instances and
@@ -10,6 +11,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdint>
 #include <vector>
 
@@ -115,4 +117,109 @@ extern "C" int ot_schedule_tune(int32_t reps) {
   for (size_t si = 0; si < sizeof(sizes) / sizeof(sizes[0]) && best_w[si] <= 256; ++si) t256 = std::max(t256, sizes[si]);
   schedule_set_locked(std::max(t64, 1), std::max(t256, std::max(t64, 1)));
   return OT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// split schedule: from which n one instance runs on several workgroups
+// ---------------------------------------------------------------------------
+// Times one exact solve per size of a ladder and per workgroup count (1, 4,
+// 8) on a synthetic geometric instance (points on a circle against points on
+// a square's perimeter, cost = rint(1e4 * distance)), through the public
+// device call on a private stream.  n_split = the largest size of the
+// contiguous prefix where one workgroup is fastest; the count is the one that
+// wins at the largest size.  A split has to win by 2% to count.
+namespace {
+
+void geometric_instance(int n, uint64_t seed, std::vector<int32_t> &C) {
+  uint64_t x = seed;
+  auto uni = [&x]() {
+    x = x * 6364136223846793005ull + 1442695040888963407ull;
+    return (double)(x >> 11) * (1.0 / 9007199254740992.0);
+  };
+  std::vector<double> sx(n), sy(n), tx(n), ty(n);
+  for (int i = 0; i < n; ++i) {
+    const double th = 6.283185307179586 * uni();
+    sx[i] = std::cos(th);
+    sy[i] = std::sin(th);
+  }
+  for (int j = 0; j < n; ++j) {
+    const double t = 4.0 * uni();
+    const int side = std::min(3, (int)t);
+    const double f = t - side;
+    const double px[4] = {-0.5 + f, 0.5, 0.5 - f, -0.5}, py[4] = {-0.5, -0.5 + f, 0.5, 0.5 - f};
+    tx[j] = px[side];
+    ty[j] = py[side];
+  }
+  C.resize((size_t)n * n);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j)
+      C[(size_t)i * n + j] = (int32_t)std::lrint(1e4 * std::hypot(sx[i] - tx[j], sy[i] - ty[j]));
+}
+
+}  // namespace
+
+extern "C" int ot_split_tune(void) {
+  {
+    std::lock_guard<std::mutex> lk(lib_mutex());
+    int rc = init_locked();
+    if (rc) return rc;
+  }
+  const int sizes[] = {1536, 2048, 2560, 3072, 4096};
+  const int cands[] = {1, 4, 8};
+  constexpr int NS = sizeof(sizes) / sizeof(sizes[0]), NC = sizeof(cands) / sizeof(cands[0]);
+  const int nmax = sizes[NS - 1];
+  hipStream_t s = nullptr;
+  int32_t *dC = nullptr, *dplan = nullptr;
+  int64_t *dcost = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  int rc = OT_OK;
+  auto fail = [&rc](int code) { if (rc == OT_OK) rc = code; };
+  if (hipStreamCreate(&s) != hipSuccess) return OT_EDEVICE;
+  if (hipMalloc(&dC, 4 * (size_t)nmax * nmax) != hipSuccess || hipMalloc(&dplan, 4 * (size_t)nmax) != hipSuccess ||
+      hipMalloc(&dcost, 8) != hipSuccess || hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    fail(OT_ENOMEM);
+  float ms[NS][NC];
+  std::vector<int32_t> hC;
+  for (int si = NS - 1; si >= 0 && rc == OT_OK; --si) {  // largest first: the workspaces grow once
+    const int n = sizes[si];
+    geometric_instance(n, 0x2545f4914f6cdd1dull + (uint64_t)n, hC);
+    if (hipMemcpyAsync(dC, hC.data(), 4 * hC.size(), hipMemcpyHostToDevice, s) != hipSuccess) { fail(OT_EDEVICE); break; }
+    for (int ci = 0; ci < NC && rc == OT_OK; ++ci) {
+      ot_options o = {};
+      o.wgs = cands[ci];
+      // untimed first solve at the largest size sizes every workspace
+      for (int rep = (si == NS - 1) ? 0 : 1; rep < 2 && rc == OT_OK; ++rep) {
+        if (hipEventRecord(e0, s) != hipSuccess) { fail(OT_EDEVICE); break; }
+        const int r = ot_assign_dev(dC, n, n, &o, dplan, dcost, nullptr, nullptr, nullptr, s);
+        if (r != OT_OK) { fail(r); break; }
+        if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) { fail(OT_EDEVICE); break; }
+        hipEventElapsedTime(&ms[si][ci], e0, e1);
+      }
+    }
+  }
+  if (rc == OT_OK) {
+    auto best_at = [&](int si) {
+      int b = 0;
+      for (int ci = 1; ci < NC; ++ci)
+        if (ms[si][ci] < 0.98f * ms[si][0] && ms[si][ci] < ms[si][b]) b = ci;
+      return b;
+    };
+    int n_split = 0;
+    for (int si = 0; si < NS && best_at(si) == 0; ++si) n_split = sizes[si];
+    const int top = best_at(NS - 1);
+    if (n_split == 0) n_split = sizes[0] - 1;  // splitting wins from the smallest size tried
+    if (top == 0) n_split = OT_MAX_N;           // never split
+    ot_split_set(n_split, top == 0 ? 0 : cands[top]);
+  }
+  if (e0) hipEventDestroy(e0);
+  if (e1) hipEventDestroy(e1);
+  hipFree(dC);
+  hipFree(dplan);
+  hipFree(dcost);
+  {
+    std::lock_guard<std::mutex> lk(lib_mutex());
+    stream_ws_free(s);
+  }
+  hipStreamDestroy(s);
+  return rc;
 }

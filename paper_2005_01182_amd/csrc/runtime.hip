@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cstdlib>
 #include <cstring>
 #include <map>
@@ -28,6 +29,7 @@ int g_dev = 0;
 int g_cus = 0;
 hipStream_t g_stream = nullptr;
 int g_t64 = 0, g_t256 = 0;  // 0 = defaults
+std::atomic<int> g_split_n{0}, g_split_wgs{0};  // 0 = defaults (read without the lock)
 
 // Default size classes of the batch path, as ot_schedule_tune measured them on
 // MI355X (instance throughput with every workgroup slot busy): one wavefront
@@ -115,6 +117,16 @@ void *stream_ws(hipStream_t s, int slot, size_t bytes, int *err) {
   return b.p;
 }
 
+// Free every workspace cached for stream s (before the caller destroys it).
+void stream_ws_free(hipStream_t s) {
+  auto it = g_ws.find(s);
+  if (it == g_ws.end()) return;
+  hipStreamSynchronize(s);
+  for (auto &kv : it->second)
+    if (kv.second.p) hipFree(kv.second.p);
+  g_ws.erase(it);
+}
+
 void schedule_set_locked(int t64, int t256) {
   g_t64 = t64;
   g_t256 = t256;
@@ -149,15 +161,19 @@ static bool range_ok(const int32_t *C, int64_t count) {
 }
 
 // Workgroups per single instance when neither ot_options.wgs nor .block is
-// set, as measured on MI355X (geometric instances): the per-step exchange
-// through global memory costs about as much as splitting the sweep saves at
-// n = 2048 (128.8 vs 126.2 ms), and wins above (n = 2560: 295 -> 197 ms,
-// n = 4096: 644 -> 350 ms with 8 workgroups).  Scaled costs make fewer, wider
-// steps, where the split pays from n = 2048 down (s = 100: 76.4 -> 33.3 ms
-// with 4 workgroups).
+// set.  Exact solves split above the schedule's n_split (ot_split_*); the
+// defaults were measured on MI355X (geometric instances): the per-step
+// exchange through global memory costs about as much as splitting the sweep
+// saves at n = 2048 (128.8 vs 126.2 ms), and wins above (n = 2560: 295 -> 197
+// ms, n = 4096: 644 -> 350 ms with 8 workgroups).  Scaled costs make fewer,
+// wider steps, where the split pays from n = 2048 down (s = 100: 76.4 -> 33.3
+// ms with 4 workgroups).
+constexpr int kDefaultSplitN = 2048, kDefaultSplitWgs = 8;
 static int default_wgs(int n, int scale) {
   if (scale > 1) return n > 1024 ? 4 : 1;
-  return n > 2048 ? 8 : 1;
+  const int sn = g_split_n.load() > 0 ? g_split_n.load() : kDefaultSplitN;
+  const int sw = g_split_wgs.load() > 0 ? g_split_wgs.load() : kDefaultSplitWgs;
+  return n > sn ? sw : 1;
 }
 
 struct Opts {
@@ -708,6 +724,19 @@ int ot_schedule_get(int32_t *t64, int32_t *t256) {
   std::lock_guard<std::mutex> lk(g_mu);
   if (t64) *t64 = g_t64 > 0 ? g_t64 : kDefaultT64;
   if (t256) *t256 = g_t256 > 0 ? g_t256 : kDefaultT256;
+  return OT_OK;
+}
+
+int ot_split_get(int32_t *n_split, int32_t *wgs) {
+  if (n_split) *n_split = g_split_n.load() > 0 ? g_split_n.load() : kDefaultSplitN;
+  if (wgs) *wgs = g_split_wgs.load() > 0 ? g_split_wgs.load() : kDefaultSplitWgs;
+  return OT_OK;
+}
+
+int ot_split_set(int32_t n_split, int32_t wgs) {
+  if (n_split < 0 || wgs < 0 || wgs == 1 || wgs > kMaxWgs) return OT_EINVAL;
+  g_split_n.store(n_split);
+  g_split_wgs.store(wgs);
   return OT_OK;
 }
 

@@ -14,6 +14,7 @@ hipStream_t lib_stream();
 int device_cus();
 void *pool_get(int slot, size_t bytes, int *err);                      // requires lib_mutex()
 void *stream_ws(hipStream_t s, int slot, size_t bytes, int *err);      // requires lib_mutex()
+void stream_ws_free(hipStream_t s);                                    // requires lib_mutex()
 int default_block(int n);
 int schedule_block(int n);
 void schedule_set_locked(int t64, int t256);    // requires lib_mutex()

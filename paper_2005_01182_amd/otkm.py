@@ -24,7 +24,7 @@ OT_MAX_N = 4096
 EXPORTS = [
     "ot_strerror", "ot_init", "ot_assign", "ot_assign_ex", "ot_assign_rect", "ot_transport", "ot_assign_batch",
     "ot_assign_dev", "ot_assign_rect_dev", "ot_assign_batch_dev", "ot_transport_dev",
-    "ot_schedule_get", "ot_schedule_set", "ot_schedule_tune",
+    "ot_schedule_get", "ot_schedule_set", "ot_schedule_tune", "ot_split_get", "ot_split_set", "ot_split_tune",
     "ot_grid_cost_dev", "ot_serve_open", "ot_serve_submit", "ot_serve_poll", "ot_serve_stats", "ot_serve_close",
 ]
 
@@ -111,6 +111,9 @@ def load():
         lib.ot_schedule_get.argtypes = [_VP, _VP]
         lib.ot_schedule_set.argtypes = [_I32, _I32]
         lib.ot_schedule_tune.argtypes = [_I32]
+        lib.ot_split_get.argtypes = [_VP, _VP]
+        lib.ot_split_set.argtypes = [_I32, _I32]
+        lib.ot_split_tune.argtypes = []
         lib.ot_grid_cost_dev.argtypes = [_VP, _VP, _I32, _VP, _VP]
         lib.ot_serve_open.argtypes = [ctypes.POINTER(ctypes.c_void_p), _VP]
         lib.ot_serve_submit.argtypes = [_VP, _VP, _VP, _I32, ctypes.POINTER(ctypes.c_uint64)]
@@ -270,6 +273,23 @@ def ot_schedule_tune(reps: int = 8):
 
 
 # ----------------------------------------------------------------------------- device calls
+def ot_split_get():
+    """(n_split, wgs): exact single-instance solves above n_split use wgs workgroups."""
+    a, b = ctypes.c_int32(0), ctypes.c_int32(0)
+    _check(load().ot_split_get(ctypes.byref(a), ctypes.byref(b)), "ot_split_get")
+    return a.value, b.value
+
+
+def ot_split_set(n_split: int, wgs: int):
+    _check(load().ot_split_set(int(n_split), int(wgs)), "ot_split_set")
+
+
+def ot_split_tune():
+    """Measure the split schedule on the device (a few seconds) and set it."""
+    _check(load().ot_split_tune(), "ot_split_tune")
+    return ot_split_get()
+
+
 def _tp(t):
     return ctypes.c_void_p(t.data_ptr()) if t is not None else None
 

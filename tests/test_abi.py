@@ -99,6 +99,10 @@ VALIDATION = textwrap.dedent(r"""
     out["schedule"] = ot.ot_schedule_get()
     ot.ot_schedule_set(100, 900); out["schedule_set"] = ot.ot_schedule_get()
     out["schedule_bad"] = code(ot.ot_schedule_set, -1, 5)
+    out["split"] = ot.ot_split_get()
+    ot.ot_split_set(3000, 4); out["split_set"] = ot.ot_split_get()
+    ot.ot_split_set(0, 0); out["split_reset"] = ot.ot_split_get()
+    out["split_bad"] = [code(ot.ot_split_set, -1, 8), code(ot.ot_split_set, 100, 1), code(ot.ot_split_set, 100, 17)]
     def serve_code(**kw):
         try:
             ot.Server(**kw).close(); return 0
@@ -164,6 +168,10 @@ def test_validation_codes(codes):
     assert codes["schedule"] == (512, 1024)
     assert codes["schedule_set"] == (100, 900)
     assert codes["schedule_bad"] == -1
+    assert codes["split"] == (2048, 8)
+    assert codes["split_set"] == (3000, 4)
+    assert codes["split_reset"] == (2048, 8)
+    assert codes["split_bad"] == [-1, -1, -1]
     assert codes["serve_bad_slots"] == -1
     assert codes["serve_bad_maxn"] == -1
     assert codes["serve_bad_streams"] == -1

@@ -115,3 +115,20 @@ def test_largest_size_against_scipy(otkm_gpu):
     assert oracle.certify_assign(C, plan, u, v) == 0
     r_, c_ = linear_sum_assignment(C)
     assert cost == int(C.astype(np.int64)[r_, c_].sum())
+
+
+def test_split_tune_then_default_solve(otkm_gpu):
+    from scipy.optimize import linear_sum_assignment
+    say("split tune")
+    n_split, wgs = otkm_gpu.ot_split_tune()
+    say("tuned split: n_split=%d wgs=%d" % (n_split, wgs))
+    try:
+        assert 1 <= n_split <= otkm_gpu.OT_MAX_N and wgs in (4, 8)
+        C = wl.geometric_assignment(3000, seed=7)
+        plan, cost, u, v, st = otkm_gpu.ot_assign(C, with_stats=True)
+        assert st["status"] == 0
+        assert oracle.certify_assign(C, plan, u, v) == 0
+        r_, c_ = linear_sum_assignment(C)
+        assert cost == int(C.astype(np.int64)[r_, c_].sum())
+    finally:
+        otkm_gpu.ot_split_set(0, 0)
