@@ -217,12 +217,14 @@ __device__ __forceinline__ int64_t now_ticks() { return (int64_t)wall_clock64();
 
 // LONG: also sweep long frontiers in chunks of 2U rows (more registers; used by
 // the one-instance kernel, where occupancy does not matter).
+// RECT: the rows may be fewer than the columns (Problem::nr); the batched
+// kernel is square and keeps n in their place.
 // GRID: one instance over gridDim.x workgroups.  Rows, matches and the forest
 // are replicated in every workgroup's LDS and updated identically; the columns
 // (keys in registers) are split.  Per level the workgroups exchange their
 // minimum keys and the columns they settled through global memory, with a
 // grid barrier after each.
-template <int BLOCK, int CPT, bool LONG = false, bool GRID = false>
+template <int BLOCK, int CPT, bool LONG = false, bool GRID = false, bool RECT = false>
 struct Engine {
   static constexpr int NW = BLOCK / 64;
 
@@ -230,8 +232,13 @@ struct Engine {
   const int32_t *__restrict__ C;
   const int32_t *__restrict__ CT;
   int n, ld;
-  int nr;    // rows (n columns)
+  int nr_;   // RECT: rows (n columns)
   int ldt;   // row stride of CT
+  // rows: n unless RECT (the batched kernel is square and saves the register)
+  __device__ __forceinline__ int rows() const {
+    if constexpr (RECT) return nr_;
+    else return n;
+  }
   // LDS
   int64_t *hrow;
   int32_t *mrow, *mcol, *rtree, *par, *fst, *gcol, *gt1, *gt2, *ctl;
@@ -306,13 +313,13 @@ struct Engine {
         if (REC) {
           const int2 e = ((const int2 *)list)[f + q < cnt ? f + q : cnt - 1];
           r[q] = e.x & 0xffff;
-          if ((unsigned)r[q] >= (unsigned)nr) { fail(OT_EINTERNAL); r[q] = 0; }
+          if ((unsigned)r[q] >= (unsigned)rows()) { fail(OT_EINTERNAL); r[q] = 0; }
           t[q] = (f + q < cnt && e.x >= 0) ? (e.x >> 16) : -1;  // sign bit: the row's tree has gone
           h32[q] = (uint32_t)e.y;
           h[q] = NARROW ? 0 : hrow[r[q]];
         } else {
           r[q] = f + q < cnt ? list[f + q] : 0;
-          if ((unsigned)r[q] >= (unsigned)nr) { fail(OT_EINTERNAL); r[q] = 0; }
+          if ((unsigned)r[q] >= (unsigned)rows()) { fail(OT_EINTERNAL); r[q] = 0; }
           t[q] = f + q < cnt ? rtree[r[q]] : -1;
           h[q] = hrow[r[q]];
           h32[q] = (uint32_t)h[q];
@@ -629,7 +636,7 @@ struct Engine {
           for (int q = 0; q < GU; ++q) {
             const int f = f0 + q * stride;
             i[q] = f < nf ? fst[f] : 0;
-            if ((unsigned)i[q] >= (unsigned)nr) { fail(OT_EINTERNAL); i[q] = 0; }
+            if ((unsigned)i[q] >= (unsigned)rows()) { fail(OT_EINTERNAL); i[q] = 0; }
             t[q] = f < nf ? rtree[i[q]] : -1;
             h[q] = hrow[i[q]];
           }
@@ -677,8 +684,9 @@ struct Engine {
 
   __device__ __forceinline__ void run(const Problem &P, char *smem) {
     C = P.C; CT = P.CT; n = P.n; ld = P.ld;
-    nr = P.nr > 0 && P.nr < P.n ? P.nr : P.n;
-    ldt = P.ldt > 0 ? P.ldt : nr;
+    nr_ = (RECT && P.nr > 0 && P.nr < P.n) ? P.nr : P.n;
+    const int nr = rows();
+    ldt = (RECT && P.ldt > 0) ? P.ldt : nr;
     const bool colred = nr == n;  // column reduction: square problems only
     tid = threadIdx.x; lane = tid & 63; wid = tid >> 6;
     err_local = 0;
@@ -887,11 +895,9 @@ struct Engine {
       if (mv == kInf) { fail(OT_EINTERNAL); break; }
       const int64_t level = kval(mv);
       if (level > D) { D = level; ++st_dual; }
-      // With every free row a root from level 0, D never exceeds the cost range;
-      // with a tree cap it adds up over stages and could in principle leave the
-      // 32-bit range of the per-column levels: report that instead of wrapping.
-      if (D > 0x7ffffffell) { fail(OT_EINTERNAL); break; }
-      if (++st_levels > watchdog) { fail(OT_EINTERNAL); break; }
+      // the watchdog; and with a tree cap the level adds up over stages and
+      // could in principle leave the 32-bit range of the per-column levels
+      if (++st_levels > watchdog || D > 0x7ffffffell) { fail(OT_EINTERNAL); break; }
       const int64_t t1_ = timers ? now_ticks() : 0;
       tm_select += t1_ - t0;
 

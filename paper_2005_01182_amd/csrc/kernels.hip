@@ -22,7 +22,7 @@ template <int BLOCK, int CPT>
 __global__ __launch_bounds__(BLOCK) void k_assign_one(Problem P, const int32_t *gate) {
   extern __shared__ __align__(16) char smem[];
   if (gate && *gate != 0) return;  // an earlier stage of this pipeline already failed
-  Engine<BLOCK, CPT, (BLOCK <= 512)> E;  // at 1024 threads the registers are too few
+  Engine<BLOCK, CPT, (BLOCK <= 512), false, true> E;  // at 1024 threads the registers are too few for LONG
   E.run(P, smem);
 }
 
@@ -34,7 +34,7 @@ __global__ __launch_bounds__(BLOCK) void k_assign_one(Problem P, const int32_t *
 template <int BLOCK, int CPT>
 __global__ __launch_bounds__(BLOCK) void k_assign_grid(Problem P) {
   extern __shared__ __align__(16) char smem[];
-  Engine<BLOCK, CPT, true, true> E;
+  Engine<BLOCK, CPT, true, true, true> E;
   E.run(P, smem);
 }
 
