@@ -77,12 +77,12 @@ def base_line(args, value, unit, ms_per_step, config):
             "scaling": "weak", "vs_baseline": None, "dtype": "int64", "data": "synthetic", "config": config}
 
 
-def traffic_for(tag):
-    """Measured HBM bytes per solve of the single-instance kernel, from the committed
-    rocprofv3 counter summary for this size, or None when there is none or when the
-    kernel sources changed after the counters were taken."""
+def traffic_for(tag, kernel="k_assign_one"):
+    """Measured HBM bytes per launch of the dominant kernel, from the committed
+    rocprofv3 counter summary for this workload, or None when there is none or when
+    the kernel sources changed after the counters were taken."""
     from paper_2005_01182_amd import profsum
-    path = os.path.join(ROOT, "profiles", "traffic_k_assign_one_%s.md" % tag)
+    path = os.path.join(ROOT, "profiles", "traffic_%s_%s.md" % (kernel, tag))
     rec = profsum.read_traffic(path)
     if rec is None or rec.get("source_sha256") != profsum.kernel_source_sha():
         return None
@@ -404,11 +404,16 @@ def bench_batch(args):
         idx = idx[np.argsort(-sizes[idx], kind="stable")].astype(np.int32)
         classes.append((block, int(sizes[idx].max()), d(idx)))
     stream = torch.cuda.Stream()
+    # optional transposes for single-column refreshes, made inside every launch
+    dCT = torch.empty_like(dC) if args.ct else None
+    max_all = int(sizes.max())
 
     def launch():
+        if dCT is not None:
+            ot.ot_transpose_batch_dev(count, max_all, dC, dcoff, dn, dCT, stream=stream)
         for block, max_n, order in classes:
             ot.ot_assign_batch_dev(count, max_n, dC, dcoff, dn, dvoff, plan, cost, u, v, st, order=order,
-                                   block=block, stream=stream)
+                                   block=block, stream=stream, CT=dCT)
 
     with torch.cuda.stream(stream):
         launch()  # eager run sizes the workspaces
@@ -432,6 +437,7 @@ def bench_batch(args):
     if int(np.abs(stats[:, F["status"]]).max()) != 0:
         raise SystemExit("batch status nonzero")
     b = alg_bytes(stats, sizes)
+    transpose_bytes = 0 if dCT is None else 8 * int((ns * ns).sum())  # read + write of every matrix
     value = count * args.steps / (total / 1e3)
     out = base_line(args, value, "solves/s", total / args.steps,
                     {"workload": "batched embedding assignments: %d problems, n ~ U{16..512}, 300-d N(0,1) "
@@ -440,8 +446,12 @@ def bench_batch(args):
                      "problems": count, "sum_n2": int((ns * ns).sum()),
                      "schedule": {"wave_max_n": t64, "wg256_max_n": t256},
                      "classes": [[blk, mx, int(o.numel())] for blk, mx, o in classes],
-                     "launch": "hipGraph replay of one persistent kernel per size class"})
-    out["roofline"] = roofline(float(b.sum()), float(np.mean(per)) / 1e3)
+                     "launch": "hipGraph replay of %sone persistent kernel per size class" %
+                               ("the batched transpose and " if dCT is not None else "")})
+    out["roofline"] = roofline(float(b.sum()) + transpose_bytes, float(np.mean(per)) / 1e3)
+    # one size class and no transposes: the launch is one dispatch of the persistent kernel
+    if len(classes) == 1 and dCT is None:
+        out["roofline"]["traffic"] = traffic_for("embedding%d" % count, kernel="k_assign_batch")
     out["batch_latency_ms"] = {"p50": pct(per, 50), "p99": pct(per, 99)}
     # plain comparison: one launch per instance, sequential on one stream, over a prefix of the batch
     k_plain = min(args.plain_count, count)
@@ -462,7 +472,8 @@ def bench_batch(args):
                                  "latency_ms_p50": pct(pl, 50), "latency_ms_p99": pct(pl, 99)}
     out["solver_counters"] = {"levels_total": int(stats[:, F["levels"]].sum()),
                               "rows_swept_total": int(stats[:, F["rows_swept"]].sum()),
-                              "alg_bytes_per_launch": int(b.sum())}
+                              "gathers_total": int(stats[:, F["gathers"]].sum()),
+                              "alg_bytes_per_launch": int(b.sum()) + transpose_bytes}
     if not args.skip_cpu:
         import oracle
         rate, done = cpu_rate(oracle.assign, Cs, args.cpu_budget)
@@ -487,6 +498,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--block", type=int, default=0, help="workgroup width override (0 = library default)")
     ap.add_argument("--tune", action="store_true", help="batch mode: run the size-class autotuner first")
+    ap.add_argument("--ct", action="store_true", help="batch mode: transpose the matrices inside every launch "
+                                                      "(refreshes then read rows of the transposes)")
     ap.add_argument("--phase-timers", action="store_true", help="one extra solve with device phase timers")
     ap.add_argument("--duration", type=float, default=5.0, help="serve mode: seconds of the request stream")
     ap.add_argument("--copy-mib", type=int, default=1024, help="copy mode: MiB per buffer")

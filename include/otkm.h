@@ -208,7 +208,8 @@ int ot_assign_rect_dev(const int32_t *dC, int32_t n, int32_t m, int32_t ld, cons
                        void *stream);
 
 /* Batch on device memory.  Instance k: cost matrix at dC + coff[k] (dense,
- * ld = n[k]), plan/u/v at dplan/du/dv + voff[k]; dcost [count];
+ * ld = n[k]), its transpose at dCT + coff[k] (dCT may be NULL: see below),
+ * plan/u/v at dplan/du/dv + voff[k]; dcost [count];
  * dstats [count] (may be NULL).  coff, voff, n are DEVICE arrays [count].
  * order (device, may be NULL) lists the nq instances this launch solves, in
  * processing order (longest first is best); NULL solves all count instances
@@ -216,11 +217,23 @@ int ot_assign_rect_dev(const int32_t *dC, int32_t n, int32_t m, int32_t ld, cons
  * 0 = from max_n via the schedule); max_n bounds n[k] of every queued
  * instance.  Several launches (for example one per size class) may share the
  * same buffers.  The launch resets its device queue head with a kernel, so
- * the call may be captured into a hipGraph and replayed. */
-int ot_assign_batch_dev(int32_t count, int32_t max_n, const int32_t *dC, const int64_t *coff,
-                        const int32_t *n, const int64_t *voff, const int32_t *order, int32_t nq,
-                        int32_t block, int32_t *dplan, int64_t *dcost, int64_t *du, int64_t *dv,
-                        ot_stats *dstats, void *stream);
+ * the call may be captured into a hipGraph and replayed.  With dCT (same size
+ * and offsets as dC, filled by ot_transpose_batch_dev) the recomputation of a
+ * single stale column reads one contiguous row of the transpose; with NULL it
+ * gathers one entry per row of C, which fetches a whole memory line each.
+ * (On MI355X the transposes cut the embedding batch's HBM traffic from 3.5x
+ * to 1.3x its algorithmic bytes but not its time, which its level chains
+ * bound; NULL is the faster choice there.) */
+int ot_assign_batch_dev(int32_t count, int32_t max_n, const int32_t *dC, const int32_t *dCT,
+                        const int64_t *coff, const int32_t *n, const int64_t *voff,
+                        const int32_t *order, int32_t nq, int32_t block, int32_t *dplan,
+                        int64_t *dcost, int64_t *du, int64_t *dv, ot_stats *dstats, void *stream);
+
+/* dCT + coff[k] = transpose of dC + coff[k] (n[k] x n[k]) for every instance
+ * with 1 <= n[k] <= max_n (others are skipped); asynchronous on `stream`,
+ * graph-capturable.  dCT must be as large as dC. */
+int ot_transpose_batch_dev(int32_t count, int32_t max_n, const int32_t *dC, const int64_t *coff,
+                           const int32_t *n, int32_t *dCT, void *stream);
 
 /* Integer transport on device memory (same semantics as ot_transport).
  * dC [n*m], dr [n], dc [m]; dX [n*m]; dcost [1]; du [n]; dv [m];

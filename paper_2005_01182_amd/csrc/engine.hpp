@@ -492,7 +492,7 @@ struct Engine {
   // Every wait is bounded: one that runs out raises the abort flag, a raised
   // flag ends every other wait, and the caller leaves its loop, so the kernel
   // always finishes.  Returns true on abort.
-  static constexpr int kSpinLimit = 1 << 21;  // sleeps of ~64 cycles: ~50 ms
+  static constexpr int kSpinLimit = 1 << 21;  // polls (a round trip and a short sleep each): about a second
   __device__ __forceinline__ bool grid_sync() {
     __syncthreads();
     if (tid == 0) {

@@ -72,7 +72,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2))) void
     P.C = A.C + A.coff[k];
     P.n = n;
     P.ld = n;
-    P.CT = nullptr;
+    P.CT = A.CT ? A.CT + A.coff[k] : nullptr;
     P.Cout = nullptr;
     P.ldo = n;
     P.dscale = 1;
@@ -208,6 +208,30 @@ __global__ __launch_bounds__(256) void k_transpose(const int32_t *C, int nr, int
   for (int r = ty; r < 64; r += 4) {
     const int j = bj + r, i = bi + tx;
     if (i < nr && j < n) CT[(size_t)j * (size_t)nr + i] = tile[tx][r];
+  }
+}
+
+// The transposes of a batch's matrices (instance k: n[k] x n[k] at offset
+// coff[k] in both buffers), 64 x 64 tiles through LDS; blockIdx.z is the
+// instance, tiles outside it return at once.
+__global__ __launch_bounds__(256) void k_transpose_batch(const int32_t *C, const int64_t *coff, const int32_t *nn,
+                                                         int32_t *CT) {
+  __shared__ int32_t tile[64][65];
+  const int k = blockIdx.z;
+  const int n = nn[k];
+  const int bj = blockIdx.x * 64, bi = blockIdx.y * 64;
+  if (bi >= n || bj >= n) return;
+  const int32_t *A = C + coff[k];
+  int32_t *AT = CT + coff[k];
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  for (int r = ty; r < 64; r += 4) {
+    const int i = bi + r, j = bj + tx;
+    if (i < n && j < n) tile[r][tx] = A[(size_t)i * (size_t)n + j];
+  }
+  __syncthreads();
+  for (int r = ty; r < 64; r += 4) {
+    const int j = bj + r, i = bi + tx;
+    if (i < n && j < n) AT[(size_t)j * (size_t)n + i] = tile[tx][r];
   }
 }
 
@@ -586,6 +610,18 @@ hipError_t launch_floor_div(const int32_t *C, int n, int ld, int32_t s, int32_t 
 hipError_t launch_transpose(const int32_t *C, int nr, int n, int ld, int32_t *CT, hipStream_t s) {
   hipLaunchKernelGGL(k_transpose, dim3((n + 63) / 64, (nr + 63) / 64), dim3(256), 0, s, C, nr, n, ld, CT);
   return hipGetLastError();
+}
+
+hipError_t launch_transpose_batch(const int32_t *C, const int64_t *coff, const int32_t *n, int count, int max_n,
+                                  int32_t *CT, hipStream_t s) {
+  const int t = (max_n + 63) / 64;
+  for (int k0 = 0; k0 < count; k0 += 65535) {  // grid z holds at most 65535 instances per launch
+    const int c = count - k0 < 65535 ? count - k0 : 65535;
+    hipLaunchKernelGGL(k_transpose_batch, dim3(t, t, c), dim3(256), 0, s, C, coff + k0, n + k0, CT);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 hipError_t launch_rect_finish(int n, int m, bool trans, const int32_t *pq, const int64_t *uq, const int64_t *vq,

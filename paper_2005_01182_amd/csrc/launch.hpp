@@ -10,6 +10,7 @@ namespace otkm {
 
 struct BatchArgs {
   const int32_t *C;       // base of all cost matrices
+  const int32_t *CT = nullptr;  // their transposes at the same offsets, or null (refreshes then gather from C)
   const int64_t *coff;    // [count] element offset of instance k's matrix
   const int32_t *n;       // [count]
   const int64_t *voff;    // [count] element offset of instance k's plan/u/v
@@ -52,6 +53,8 @@ hipError_t launch_init_sweeps(const int32_t *C, int nr, int n, int ld, int64_t *
                               uint64_t *b, hipStream_t st);
 hipError_t launch_floor_div(const int32_t *C, int n, int ld, int32_t s, int32_t *Cs, hipStream_t st);
 hipError_t launch_transpose(const int32_t *C, int nr, int n, int ld, int32_t *CT, hipStream_t s);
+hipError_t launch_transpose_batch(const int32_t *C, const int64_t *coff, const int32_t *n, int count, int max_n,
+                                  int32_t *CT, hipStream_t s);
 hipError_t launch_rect_finish(int n, int m, bool trans, const int32_t *pq, const int64_t *uq, const int64_t *vq,
                               const int64_t *cq, const ot_stats *sq, int32_t *plan, int64_t *cost, int64_t *u,
                               int64_t *v, ot_stats *stats, hipStream_t s);

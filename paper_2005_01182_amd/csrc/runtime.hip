@@ -484,9 +484,21 @@ int ot_assign_rect_dev(const int32_t *dC, int32_t n, int32_t m, int32_t ld, cons
   return err ? err : rc;
 }
 
-int ot_assign_batch_dev(int32_t count, int32_t max_n, const int32_t *dC, const int64_t *coff, const int32_t *n,
-                        const int64_t *voff, const int32_t *order, int32_t nq, int32_t block, int32_t *dplan,
-                        int64_t *dcost, int64_t *du, int64_t *dv, ot_stats *dstats, void *stream) {
+int ot_transpose_batch_dev(int32_t count, int32_t max_n, const int32_t *dC, const int64_t *coff, const int32_t *n,
+                           int32_t *dCT, void *stream) {
+  if (count < 0 || !dC || !coff || !n || !dCT || max_n <= 0) return OT_EINVAL;
+  if (max_n > OT_MAX_N) return OT_ETOOBIG;
+  if (count == 0) return OT_OK;
+  std::lock_guard<std::mutex> lk(g_mu);
+  int rc = init_locked();
+  if (rc) return rc;
+  hipStream_t s = stream ? (hipStream_t)stream : g_stream;
+  return map_hip(launch_transpose_batch(dC, coff, n, count, max_n, dCT, s));
+}
+
+int ot_assign_batch_dev(int32_t count, int32_t max_n, const int32_t *dC, const int32_t *dCT, const int64_t *coff,
+                        const int32_t *n, const int64_t *voff, const int32_t *order, int32_t nq, int32_t block,
+                        int32_t *dplan, int64_t *dcost, int64_t *du, int64_t *dv, ot_stats *dstats, void *stream) {
   if (count < 0 || !dC || !coff || !n || !voff || !dplan || !dcost || max_n <= 0) return OT_EINVAL;
   if (!order) nq = count;
   if (nq < 0 || nq > count) return OT_EINVAL;
@@ -508,7 +520,7 @@ int ot_assign_batch_dev(int32_t count, int32_t max_n, const int32_t *dC, const i
   hipError_t e = launch_fill_i32(head, 0, 1, s);
   if (e != hipSuccess) return map_hip(e);
   BatchArgs A;
-  A.C = dC; A.coff = coff; A.n = n; A.voff = voff; A.order = order;
+  A.C = dC; A.CT = dCT; A.coff = coff; A.n = n; A.voff = voff; A.order = order;
   A.count = count; A.nq = nq; A.max_n = max_n; A.max_paths = 0;
   A.plan = dplan; A.cost = dcost; A.u = du; A.v = dv; A.stats = dstats; A.ws = dws; A.head = head; A.done = nullptr; A.tag = 0;
   return map_hip(launch_assign_batch(A, block, grid, s));

@@ -23,7 +23,7 @@ OT_MAX_N = 4096
 
 EXPORTS = [
     "ot_strerror", "ot_init", "ot_assign", "ot_assign_ex", "ot_assign_rect", "ot_transport", "ot_assign_batch",
-    "ot_assign_dev", "ot_assign_rect_dev", "ot_assign_batch_dev", "ot_transport_dev",
+    "ot_assign_dev", "ot_assign_rect_dev", "ot_assign_batch_dev", "ot_transpose_batch_dev", "ot_transport_dev",
     "ot_schedule_get", "ot_schedule_set", "ot_schedule_tune", "ot_split_get", "ot_split_set", "ot_split_tune",
     "ot_grid_cost_dev", "ot_serve_open", "ot_serve_submit", "ot_serve_poll", "ot_serve_stats", "ot_serve_close",
 ]
@@ -105,7 +105,8 @@ def load():
         lib.ot_assign_batch.argtypes = [_I32, _VP, _VP, _VP, _VP, _VP, _VP, _VP]
         lib.ot_assign_dev.argtypes = [_VP, _I32, _I32, _VP, _VP, _VP, _VP, _VP, _VP, _VP]
         lib.ot_assign_rect_dev.argtypes = [_VP, _I32, _I32, _I32, _VP, _VP, _VP, _VP, _VP, _VP, _VP]
-        lib.ot_assign_batch_dev.argtypes = [_I32, _I32, _VP, _VP, _VP, _VP, _VP, _I32, _I32, _VP, _VP, _VP, _VP, _VP,
+        lib.ot_transpose_batch_dev.argtypes = [_I32, _I32, _VP, _VP, _VP, _VP, _VP]
+        lib.ot_assign_batch_dev.argtypes = [_I32, _I32, _VP, _VP, _VP, _VP, _VP, _VP, _I32, _I32, _VP, _VP, _VP, _VP, _VP,
                                             _VP]
         lib.ot_transport_dev.argtypes = [_VP, _VP, _VP, _I32, _I32, _I32, _VP, _VP, _VP, _VP, _VP, _VP]
         lib.ot_schedule_get.argtypes = [_VP, _VP]
@@ -329,17 +330,25 @@ def ot_assign_rect_dev(C, plan, cost, u=None, v=None, stats=None, max_paths=0, b
 
 
 def ot_assign_batch_dev(count, max_n, C, coff, n, voff, plan, cost, u=None, v=None, stats=None, order=None,
-                        block=0, stream=None, nq=None):
+                        block=0, stream=None, nq=None, CT=None):
     """Queue a persistent batch on device tensors (asynchronous on `stream`).
 
     `order` (device int32) lists the `nq` instances to solve (default: all of it).
+    `CT` (optional, same size as C) holds the instances' transposes
+    (ot_transpose_batch_dev), read to recompute single stale columns.
     """
     if order is not None and nq is None:
         nq = int(order.numel())
-    rc = load().ot_assign_batch_dev(int(count), int(max_n), _tp(C), _tp(coff), _tp(n), _tp(voff), _tp(order),
-                                    int(nq or 0), int(block), _tp(plan), _tp(cost), _tp(u), _tp(v), _tp(stats),
-                                    _stream(stream))
+    rc = load().ot_assign_batch_dev(int(count), int(max_n), _tp(C), _tp(CT), _tp(coff), _tp(n), _tp(voff),
+                                    _tp(order), int(nq or 0), int(block), _tp(plan), _tp(cost), _tp(u), _tp(v),
+                                    _tp(stats), _stream(stream))
     _check(rc, "ot_assign_batch_dev")
+
+
+def ot_transpose_batch_dev(count, max_n, C, coff, n, CT, stream=None):
+    """Queue CT + coff[k] = transpose of instance k for every 1 <= n[k] <= max_n."""
+    rc = load().ot_transpose_batch_dev(int(count), int(max_n), _tp(C), _tp(coff), _tp(n), _tp(CT), _stream(stream))
+    _check(rc, "ot_transpose_batch_dev")
 
 
 def ot_transport_dev(C, r, c, S, X, cost, u, v, stats=None, stream=None):

@@ -23,7 +23,8 @@ def declared_symbols():
 def test_header_declares_boundary():
     syms = declared_symbols()
     for name in ("ot_assign", "ot_transport", "ot_assign_batch", "ot_assign_dev", "ot_transport_dev",
-                 "ot_assign_batch_dev", "ot_assign_rect", "ot_assign_rect_dev", "ot_strerror"):
+                 "ot_assign_batch_dev", "ot_transpose_batch_dev", "ot_assign_rect", "ot_assign_rect_dev",
+                 "ot_strerror"):
         assert name in syms
 
 

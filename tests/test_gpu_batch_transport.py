@@ -107,6 +107,54 @@ def test_batch_dev_graph_replay_matches_eager(otkm_gpu):
         assert torch.equal(u, eager[2]) and torch.equal(v, eager[3])
 
 
+def test_batch_dev_with_transposes_matches_without(otkm_gpu):
+    # refreshes that read the transposes give the same keys as gathers down C,
+    # so every output is identical; the transpose is captured in a graph too
+    import torch
+    sizes = wl.embedding_sizes(80, lo=16, hi=512, seed=8)
+    Cs = [wl.embedding_problem(int(n), 8, k) for k, n in enumerate(sizes)]
+    ns, dC, dcoff, dn, dvoff, dorder, vtot = _pack_device(Cs)
+    count, max_n = len(Cs), int(ns.max())
+    outs = []
+    s = torch.cuda.Stream()
+    for with_ct in (False, True):
+        plan = torch.empty(vtot, dtype=torch.int32, device="cuda")
+        cost = torch.empty(count, dtype=torch.int64, device="cuda")
+        u = torch.empty(vtot, dtype=torch.int64, device="cuda")
+        v = torch.empty(vtot, dtype=torch.int64, device="cuda")
+        st = otkm_gpu.stats_tensor(count)
+        dCT = torch.full_like(dC, -1) if with_ct else None
+
+        def launch():
+            if with_ct:
+                otkm_gpu.ot_transpose_batch_dev(count, max_n, dC, dcoff, dn, dCT, stream=s)
+            otkm_gpu.ot_assign_batch_dev(count, max_n, dC, dcoff, dn, dvoff, plan, cost, u, v, st, order=dorder,
+                                         stream=s, CT=dCT)
+        with torch.cuda.stream(s):
+            launch()
+        s.synchronize()
+        assert int(st[:, 7].abs().max()) == 0
+        if with_ct:
+            for k in (0, 7, 33):
+                o, n = int(dcoff[k]), int(ns[k])
+                assert torch.equal(dCT[o:o + n * n].view(n, n).cpu(), torch.from_numpy(Cs[k].T.copy()))
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g, stream=s):
+                launch()
+            for rep in range(2):
+                plan.fill_(-1); cost.fill_(-1); dCT.fill_(-1)
+                torch.cuda.synchronize()
+                g.replay()
+                torch.cuda.synchronize()
+                say("replay with transposes", rep)
+                assert torch.equal(plan, outs[0][0]) and torch.equal(cost, outs[0][1])
+        outs.append((plan.clone(), cost.clone(), u.clone(), v.clone()))
+    for a, b in zip(outs[0], outs[1]):
+        assert torch.equal(a, b)
+    for k in range(0, count, 9):
+        assert int(outs[1][1][k]) == oracle.assign(Cs[k])[1]
+
+
 def test_transport_pixel_config(otkm_gpu):
     C, r, c = wl.pixel_histogram_pair()
     say("transport 784x784, S=1024")
