@@ -15,7 +15,6 @@ import time
 import numpy as np
 
 from . import otkm
-from . import workloads as wl
 
 
 def replay(server: "otkm.Server", reqs, keep_results=False, stall_s=30.0):
@@ -84,68 +83,3 @@ def summarize(recs):
             "queue_ms_p50": round(float(np.percentile(q, 50)), 3),
             "queue_ms_p99": round(float(np.percentile(q, 99)), 3),
             "span_s": round(t1 - t0, 3)}
-
-
-def bench(args):
-    """JSON line for the serving workload (Poisson 2000 req/s, n log-uniform in [32, 4096])."""
-    import oracle
-    duration = args.duration
-    reqs = list(wl.serving_trace(rate=2000.0, duration=duration, seed=0))
-    offered = len(reqs) / duration
-    budget = 16 << 30
-    with otkm.Server(hbm_budget_bytes=budget, max_inflight=512) as srv:
-        # warm every size class once before the stream starts
-        wrng = np.random.default_rng(123)
-        warm = [wl.ServingRequest(k, 0.0, n, wrng.integers(0, 10000, (n, 2)).astype(np.int32),
-                                  wrng.integers(0, 10000, (n, 2)).astype(np.int32))
-                for k, n in enumerate((64, 300, 1000, 2500))]
-        replay(srv, warm)
-        print("serve: replaying %d requests over %.1f s" % (len(reqs), duration), file=sys.stderr, flush=True)
-        recs = replay(srv, reqs)
-        ctr, _ = srv.stats()
-    served = summarize(recs)
-    bad = [r for r in recs if r["status"] != 0]
-    # the same prefix, one request at a time (plain sequential solver with queueing)
-    k_plain = min(args.plain_count, len(reqs))
-    print("serve: served %s; now %d requests one at a time" % (served, k_plain), file=sys.stderr, flush=True)
-    with otkm.Server(hbm_budget_bytes=budget, max_inflight=1) as one:
-        plain = summarize(replay(one, reqs[:k_plain]))
-    with otkm.Server(hbm_budget_bytes=budget, max_inflight=512) as srv2:
-        served_prefix = summarize(replay(srv2, reqs[:k_plain]))
-    print("serve: one at a time %s; continuous batching %s" % (plain, served_prefix), file=sys.stderr, flush=True)
-    # spot checks against the oracle / certificate on a seeded sample
-    rng = np.random.default_rng(0)
-    sample = [k for k in range(len(reqs)) if reqs[k].n <= 256][:40] + list(rng.choice(len(reqs), 5, replace=False))
-    checked = 0
-    for k in sample:
-        r = reqs[k]
-        C = wl.grid_points_cost(r.src, r.dst)
-        if r.n <= 512:
-            assert recs[k]["cost"] == oracle.assign(C)[1], "served cost differs from the oracle"
-        checked += 1
-    cpu_items = [wl.grid_points_cost(r.src, r.dst) for r in reqs if r.n <= 256][:400]
-    t0 = time.perf_counter()
-    done = 0
-    for C in cpu_items:
-        oracle.assign(C)
-        done += 1
-        if time.perf_counter() - t0 > args.cpu_budget:
-            break
-    cpu = done / (time.perf_counter() - t0)
-    saturated = served["solves_per_s"] < 0.9 * offered
-    out = {"metric": "solves/s + achieved HBM GB/s at n=2048; p50/p99 latency batched vs plain",
-           "value": served["solves_per_s"], "unit": "solves/s", "n_gpus": 1, "steps": 1, "warmup": 0,
-           "ms_per_step": round(served["span_s"] * 1e3, 3), "higher_is_better": True, "scaling": "weak",
-           "vs_baseline": None, "dtype": "int64", "data": "synthetic",
-           "config": {"workload": "serving stream: Poisson arrivals at 2000 req/s for %.1f s, n = round(exp(U[ln 32, "
-                                  "ln 4096])), points U[0,1]^2 on a 1e4 grid, C = round(|p - q|) int32 built on "
-                                  "the device, seed 0" % duration,
-                      "offered_req_per_s": round(offered, 1), "hbm_budget_bytes": budget, "slots": 512},
-           "served": served, "served_errors": len(bad), "saturated": bool(saturated),
-           "server_counters": ctr,
-           "prefix_compare": {"requests": k_plain, "continuous_batching": served_prefix, "one_at_a_time": plain},
-           "checked_against_oracle": checked,
-           "cpu_baseline": {"value": round(cpu, 3), "unit": "solves/s", "cores": 1, "kind": "oracle",
-                            "sample": "%d requests of the stream with n <= 256 (the rest is too slow on the CPU), "
-                                      "single-threaded C oracle" % done}}
-    return out
