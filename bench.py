@@ -203,6 +203,10 @@ def bench_scaled(args):
     from paper_2005_01182_amd import workloads as wl
     n, sc = args.n, args.scale
     C = wl.geometric_assignment(n, seed=0)
+    lb0 = None
+    if args.approx > 0:
+        # the factor for a (1 + approx)-approximation, from the reduction's lower bound (on the device)
+        sc, lb0 = ot.ot_scale_for(C, args.approx)
     dC = torch.from_numpy(C).cuda()
     stream = torch.cuda.Stream()
     plan = torch.empty(n, dtype=torch.int32, device="cuda")
@@ -237,7 +241,9 @@ def bench_scaled(args):
     out = base_line(args, args.steps / (total / 1e3), "solves/s", total / args.steps,
                     {"workload": "geometric assignment: circle vs square perimeter, sigma 0.02, C = rint(1e4 * "
                                  "distance) int32, n = %d, seed 0, solved on floor(C / %d)" % (n, sc),
-                     "n": n, "scale": sc, "method": "batched KM on the scaled costs"})
+                     "n": n, "scale": sc, "method": "batched KM on the scaled costs",
+                     "target_approximation": (1 + args.approx) if args.approx > 0 else None,
+                     "reduction_lower_bound": lb0})
     out["metric"] = "solves/s with one scaling factor (approximate regime)"
     out["roofline"] = roofline(float(np.mean(b)), float(np.mean(per)) / 1e3)
     out["latency_ms"] = {"p50": pct(per, 50), "p99": pct(per, 99)}
@@ -568,6 +574,8 @@ def main():
     ap.add_argument("--duration", type=float, default=5.0, help="serve mode: seconds of the request stream")
     ap.add_argument("--copy-mib", type=int, default=1024, help="copy mode: MiB per buffer")
     ap.add_argument("--scale", type=int, default=100, help="scaled mode: cost scaling factor s")
+    ap.add_argument("--approx", type=float, default=0.0,
+                    help="scaled mode: choose s for a (1 + approx)-approximation instead of --scale")
     ap.add_argument("--rows", type=int, default=1024, help="rect mode: rows n")
     ap.add_argument("--cols", type=int, default=2048, help="rect mode: columns m")
     args = ap.parse_args()

@@ -165,6 +165,18 @@ int ot_assign_ex(const int32_t *C, int32_t n, const ot_options *opt, int32_t *pl
 int ot_assign_rect(const int32_t *C, int32_t n, int32_t m, const ot_options *opt, int32_t *plan,
                    int64_t *cost, int64_t *u, int64_t *v, ot_stats *stats);
 
+/* Scaling factor for a target approximation (Section 2.3.1's single scaling
+ * factor; Table 3 fixes the factor of approximation at 1.1, i.e. eps = 0.1).
+ * Runs the KM reduction's two sweeps on the device and returns
+ *   lower_bound = sum_i u_i + sum_j v_j   (u_i = min_j C_ij, v_j = min_i C_ij - u_i,
+ *                                          a feasible dual, so <= OPT)
+ *   scale = 1 + floor(eps * lower_bound / n)   (1 when lower_bound <= 0)
+ * A solve with ot_options.scale = scale then costs at most
+ * OPT + n (scale - 1) <= OPT + eps * lower_bound <= (1 + eps) OPT when the
+ * optimum is positive.  C [n*n] host costs; lower_bound may be NULL.
+ * Errors as ot_assign, and OT_EINVAL for eps < 0 or NaN. */
+int ot_scale_for(const int32_t *C, int32_t n, double eps, int32_t *scale, int64_t *lower_bound);
+
 /* Integer transport (Eq. (1), Hitchcock-Koopmans case).
  *   C [n*m] int32 costs (ld = m); r [n], c [m] int32 masses, >= 0, equal sums S >= 1.
  *   X [n*m] out: int32 optimal plan.   cost out: <C, X>.

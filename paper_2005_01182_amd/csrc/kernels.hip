@@ -235,6 +235,22 @@ __global__ __launch_bounds__(256) void k_transpose_batch(const int32_t *C, const
   }
 }
 
+// lb = sum_i u_i + sum_j v_j for the KM reduction's duals (u_i = row minimum,
+// v_j = smallest C_ij - u_i, the value of the column's best key b[2j]): a
+// feasible dual, so a lower bound on the optimum.  One workgroup.
+__global__ __launch_bounds__(1024) void k_lower_bound(const int64_t *u, const uint64_t *b, int n, int64_t *lb) {
+  __shared__ int64_t red[1024];
+  int64_t s = 0;
+  for (int k = threadIdx.x; k < n; k += 1024) s += u[k] + kval(b[2 * (size_t)k]);
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 512; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *lb = red[0];
+}
+
 // Cs = floor(C / s) element-wise (row stride ld in, n out): the scaled costs of
 // the single-scaling-factor mode.  floor(C/s) * s <= C, so duals feasible for
 // Cs become feasible for C when multiplied by s.
@@ -622,6 +638,11 @@ hipError_t launch_transpose_batch(const int32_t *C, const int64_t *coff, const i
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
+}
+
+hipError_t launch_lower_bound(const int64_t *u, const uint64_t *b, int n, int64_t *lb, hipStream_t s) {
+  hipLaunchKernelGGL(k_lower_bound, dim3(1), dim3(1024), 0, s, u, b, n, lb);
+  return hipGetLastError();
 }
 
 hipError_t launch_rect_finish(int n, int m, bool trans, const int32_t *pq, const int64_t *uq, const int64_t *vq,

@@ -51,6 +51,7 @@ hipError_t launch_transport(const TransportArgs &T, int block, hipStream_t s);
 size_t init_part_bytes(int nr, int n);
 hipError_t launch_init_sweeps(const int32_t *C, int nr, int n, int ld, int64_t *u, int32_t *rmax, uint64_t *part,
                               uint64_t *b, hipStream_t st);
+hipError_t launch_lower_bound(const int64_t *u, const uint64_t *b, int n, int64_t *lb, hipStream_t s);
 hipError_t launch_floor_div(const int32_t *C, int n, int ld, int32_t s, int32_t *Cs, hipStream_t st);
 hipError_t launch_transpose(const int32_t *C, int nr, int n, int ld, int32_t *CT, hipStream_t s);
 hipError_t launch_transpose_batch(const int32_t *C, const int64_t *coff, const int32_t *n, int count, int max_n,

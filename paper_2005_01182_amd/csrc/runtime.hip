@@ -7,6 +7,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <cmath>
 #include <cstdlib>
 #include <cstring>
 #include <map>
@@ -321,6 +322,38 @@ int ot_assign_ex(const int32_t *C, int32_t n, const ot_options *opt, int32_t *pl
   if (u) std::memcpy(u, hu.data(), 8 * N);
   if (v) std::memcpy(v, hv.data(), 8 * N);
   if (stats) *stats = hs;
+  return OT_OK;
+}
+
+int ot_scale_for(const int32_t *C, int32_t n, double eps, int32_t *scale, int64_t *lower_bound) {
+  if (!C || !scale || n <= 0 || !(eps >= 0.0)) return OT_EINVAL;
+  if (n > OT_MAX_N) return OT_ETOOBIG;
+  if (!range_ok(C, (int64_t)n * n)) return OT_ERANGE;
+  std::lock_guard<std::mutex> lk(g_mu);
+  int rc = init_locked();
+  if (rc) return rc;
+  int err = OT_OK;
+  const size_t N = (size_t)n;
+  auto *dC = (int32_t *)pool_get(0, 4 * N * N, &err);
+  auto *du0 = (int64_t *)pool_get(80, 8 * N, &err);
+  auto *drmax = (int32_t *)pool_get(81, 4 * N, &err);
+  auto *dpart = (uint64_t *)pool_get(82, init_part_bytes(n, n), &err);
+  auto *db = (uint64_t *)pool_get(83, 16 * N, &err);
+  auto *dlb = (int64_t *)pool_get(85, 8, &err);
+  if (err) return err;
+  hipStream_t s = g_stream;
+  hipError_t e = hipMemcpyAsync(dC, C, 4 * N * N, hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return map_hip(e);
+  if ((e = launch_init_sweeps(dC, n, n, n, du0, drmax, dpart, db, s)) != hipSuccess) return map_hip(e);
+  if ((e = launch_lower_bound(du0, db, n, dlb, s)) != hipSuccess) return map_hip(e);
+  int64_t lb = 0;
+  if ((e = hipMemcpyAsync(&lb, dlb, 8, hipMemcpyDeviceToHost, s)) != hipSuccess) return map_hip(e);
+  if ((e = hipStreamSynchronize(s)) != hipSuccess) return map_hip(e);
+  // n (s - 1) <= eps * lb <= eps * OPT: the scaled solve's cost is within (1 + eps) OPT
+  double sf = lb > 0 ? 1.0 + std::floor(eps * (double)lb / (double)n) : 1.0;
+  if (sf > 1073741824.0) sf = 1073741824.0;
+  *scale = (int32_t)sf;
+  if (lower_bound) *lower_bound = lb;
   return OT_OK;
 }
 

@@ -22,7 +22,8 @@ OT_ETOOBIG, OT_ENOMEM, OT_EDEVICE, OT_ENODEV, OT_EINTERNAL = -5, -6, -7, -8, -9
 OT_MAX_N = 4096
 
 EXPORTS = [
-    "ot_strerror", "ot_init", "ot_assign", "ot_assign_ex", "ot_assign_rect", "ot_transport", "ot_assign_batch",
+    "ot_strerror", "ot_init", "ot_assign", "ot_assign_ex", "ot_assign_rect", "ot_scale_for", "ot_transport",
+    "ot_assign_batch",
     "ot_assign_dev", "ot_assign_rect_dev", "ot_assign_batch_dev", "ot_transpose_batch_dev", "ot_transport_dev",
     "ot_schedule_get", "ot_schedule_set", "ot_schedule_tune", "ot_split_get", "ot_split_set", "ot_split_tune",
     "ot_grid_cost_dev", "ot_serve_open", "ot_serve_submit", "ot_serve_poll", "ot_serve_stats", "ot_serve_close",
@@ -101,6 +102,7 @@ def load():
         lib.ot_assign.argtypes = [_VP, _I32, _VP, _VP, _VP, _VP]
         lib.ot_assign_ex.argtypes = [_VP, _I32, _VP, _VP, _VP, _VP, _VP, _VP]
         lib.ot_assign_rect.argtypes = [_VP, _I32, _I32, _VP, _VP, _VP, _VP, _VP, _VP]
+        lib.ot_scale_for.argtypes = [_VP, _I32, ctypes.c_double, _VP, _VP]
         lib.ot_transport.argtypes = [_VP, _VP, _VP, _I32, _I32, _VP, _VP, _VP, _VP]
         lib.ot_assign_batch.argtypes = [_I32, _VP, _VP, _VP, _VP, _VP, _VP, _VP]
         lib.ot_assign_dev.argtypes = [_VP, _I32, _I32, _VP, _VP, _VP, _VP, _VP, _VP, _VP]
@@ -212,6 +214,18 @@ def ot_assign_rect(C, max_paths: int = 0, block: int = 0, with_stats: bool = Fal
     _check(rc, "ot_assign_rect")
     out = (plan, int(cost.value), u, v)
     return out + (st.as_dict(),) if with_stats else out
+
+
+def ot_scale_for(C, eps: float):
+    """Scaling factor that makes a scaled solve (1 + eps)-approximate, and the
+    lower bound it comes from: returns (scale, lower_bound)."""
+    C = np.ascontiguousarray(C, dtype=np.int32)
+    if C.ndim != 2 or C.shape[0] != C.shape[1]:
+        raise ValueError("square cost matrix required")
+    sc = ctypes.c_int32(0)
+    lb = ctypes.c_int64(0)
+    _check(load().ot_scale_for(_p(C), C.shape[0], float(eps), ctypes.byref(sc), ctypes.byref(lb)), "ot_scale_for")
+    return int(sc.value), int(lb.value)
 
 
 def ot_transport(C, r, c):

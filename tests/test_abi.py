@@ -62,6 +62,10 @@ VALIDATION = textwrap.dedent(r"""
     out["assign_neg_paths"] = code(ot.ot_assign, C, max_paths=-1)
     out["assign_neg_scale"] = code(ot.ot_assign, C, scale=-2)
     out["assign_scale_ok_but_nodev"] = code(ot.ot_assign, C, scale=10)
+    out["scale_for_nodev"] = code(ot.ot_scale_for, C, 0.1)
+    out["scale_for_neg_eps"] = code(ot.ot_scale_for, C, -0.5)
+    out["scale_for_nan"] = code(ot.ot_scale_for, C, float("nan"))
+    out["scale_for_range"] = code(ot.ot_scale_for, wide, 0.1)
     out["wgs_ok_but_nodev"] = code(ot.ot_assign, C, wgs=4)
     out["wgs_too_many"] = code(ot.ot_assign, C, wgs=17)
     out["wgs_negative"] = code(ot.ot_assign, C, wgs=-1)
@@ -141,6 +145,10 @@ def test_validation_codes(codes):
     assert codes["assign_neg_scale"] == -1
     assert codes["assign_scale_ok_but_nodev"] == -8
     assert codes["assign_block_too_narrow"] == -1
+    assert codes["scale_for_nodev"] == -8
+    assert codes["scale_for_neg_eps"] == -1
+    assert codes["scale_for_nan"] == -1
+    assert codes["scale_for_range"] == -2
     assert codes["wgs_ok_but_nodev"] == -8
     assert codes["wgs_too_many"] == -1
     assert codes["wgs_negative"] == -1

@@ -240,6 +240,29 @@ def test_scaled_device_api_with_row_stride(otkm_gpu):
     assert int(cost.item()) == ref[1]
 
 
+@pytest.mark.parametrize("eps", [0.1, 0.01])
+@pytest.mark.parametrize("n,seed", [(300, 3), (700, 4)])
+def test_scale_for_target_approximation(otkm_gpu, n, seed, eps):
+    # Table 3's regime: a factor of approximation fixed in advance (1.1 for eps = 0.1)
+    C = wl.geometric_assignment(n, seed=seed)
+    s, lb = otkm_gpu.ot_scale_for(C, eps)
+    C64 = C.astype(np.int64)
+    u0 = C64.min(axis=1)
+    v0 = (C64 - u0[:, None]).min(axis=0)
+    assert lb == int(u0.sum() + v0.sum())          # the reduction's duals, written out
+    assert s == 1 + int(np.floor(eps * lb / n))
+    plan, cost, u, v = otkm_gpu.ot_assign(C, scale=s)
+    check_scaled(C, s, plan, cost, u, v)
+    opt = oracle.assign(C)[1]
+    assert lb <= opt and cost <= (1 + eps) * opt
+
+
+def test_scale_for_nonpositive_bound_is_exact(otkm_gpu):
+    C = np.random.default_rng(5).integers(-1000, 10, (80, 80)).astype(np.int32)
+    s, lb = otkm_gpu.ot_scale_for(C, 0.1)
+    assert lb <= 0 and s == 1
+
+
 # ----------------------------------------------------------------------------- grid-wide initial sweeps
 def test_device_range_error_reported(otkm_gpu):
     """Device calls check the cost range on the device (from the initial row sweep)."""
