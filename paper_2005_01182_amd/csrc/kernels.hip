@@ -113,8 +113,19 @@ __global__ __launch_bounds__(256) void k_init_rows(const int32_t *C, int nr, int
   const int32_t *row = C + (size_t)i * (size_t)ld;
   int mn = 0x7fffffff, mx = (int)0x80000000;
   if ((ld & 3) == 0 && ((uintptr_t)C & 15) == 0) {
-    // 16-byte loads: four columns per lane per step, two steps in flight
+    // 16-byte loads: four columns per lane per step, four steps in flight (a
+    // cold matrix comes from HBM, whose latency needs that many bytes in flight)
     int j = lane * 4;
+    for (; j + 768 + 3 < n; j += 1024) {
+      const int4 a = *(const int4 *)(row + j);
+      const int4 b = *(const int4 *)(row + j + 256);
+      const int4 c = *(const int4 *)(row + j + 512);
+      const int4 d = *(const int4 *)(row + j + 768);
+      mn = min(mn, min(min(min(a.x, a.y), min(a.z, a.w)), min(min(b.x, b.y), min(b.z, b.w))));
+      mx = max(mx, max(max(max(a.x, a.y), max(a.z, a.w)), max(max(b.x, b.y), max(b.z, b.w))));
+      mn = min(mn, min(min(min(c.x, c.y), min(c.z, c.w)), min(min(d.x, d.y), min(d.z, d.w))));
+      mx = max(mx, max(max(max(c.x, c.y), max(c.z, c.w)), max(max(d.x, d.y), max(d.z, d.w))));
+    }
     for (; j + 256 + 3 < n; j += 512) {
       const int4 a = *(const int4 *)(row + j);
       const int4 b = *(const int4 *)(row + j + 256);

@@ -293,13 +293,15 @@ int ot_assign_ex(const int32_t *C, int32_t n, const ot_options *opt, int32_t *pl
     if ((e = launch_floor_div(dC, n, n, scale, dCs, s)) != hipSuccess) return map_hip(e);
     dsolve = dCs;
   }
-  if ((e = launch_transpose(dsolve, n, n, n, dCT, s)) != hipSuccess) return map_hip(e);
   auto *du0 = (int64_t *)pool_get(80, 8 * N, &err);
   auto *drmax = (int32_t *)pool_get(81, 4 * N, &err);
   auto *dpart = (uint64_t *)pool_get(82, init_part_bytes(n, n), &err);
   auto *db = (uint64_t *)pool_get(83, 16 * N, &err);
   if (err) return err;
+  // the streaming row sweep reads C first (from HBM when C is cold), the
+  // tiled transpose then finds it in the last-level cache
   if ((e = launch_init_sweeps(dsolve, n, n, n, du0, drmax, dpart, db, s)) != hipSuccess) return map_hip(e);
+  if ((e = launch_transpose(dsolve, n, n, n, dCT, s)) != hipSuccess) return map_hip(e);
   Problem P;
   P.C = dsolve; P.n = n; P.ld = n; P.CT = dCT; P.max_paths = o.max_paths; P.flags = o.flags;
   P.Cout = dC; P.ldo = n; P.dscale = scale;
@@ -386,13 +388,15 @@ int ot_assign_dev(const int32_t *dC, int32_t n, int32_t ld, const ot_options *op
     dsolve = dCs;
     lds = n;
   }
-  if ((e = launch_transpose(dsolve, n, n, lds, dCT, s)) != hipSuccess) return map_hip(e);
   auto *du0 = (int64_t *)stream_ws(s, 40, 8 * (size_t)n, &err);
   auto *drmax = (int32_t *)stream_ws(s, 41, 4 * (size_t)n, &err);
   auto *dpart = (uint64_t *)stream_ws(s, 42, init_part_bytes(n, n), &err);
   auto *db = (uint64_t *)stream_ws(s, 43, 16 * (size_t)n, &err);
   if (err) return err;
+  // the streaming row sweep reads C first (from HBM when C is cold), the
+  // tiled transpose then finds it in the last-level cache
   if ((e = launch_init_sweeps(dsolve, n, n, lds, du0, drmax, dpart, db, s)) != hipSuccess) return map_hip(e);
+  if ((e = launch_transpose(dsolve, n, n, lds, dCT, s)) != hipSuccess) return map_hip(e);
   Problem P;
   P.C = dsolve; P.n = n; P.ld = lds; P.CT = dCT; P.max_paths = o.max_paths; P.flags = o.flags;
   P.Cout = dC; P.ldo = ld; P.dscale = scale;
