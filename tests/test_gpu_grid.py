@@ -132,3 +132,24 @@ def test_split_tune_then_default_solve(otkm_gpu):
         assert cost == int(C.astype(np.int64)[r_, c_].sum())
     finally:
         otkm_gpu.ot_split_set(0, 0)
+
+
+def test_split_schedule_routes_default_solves(otkm_gpu):
+    # a schedule that splits from n = 100 on: default-option solves above it use 4 workgroups
+    C = wl.geometric_assignment(300, seed=13)
+    ref = otkm_gpu.ot_assign(C, wgs=1)
+    st4 = otkm_gpu.ot_assign(C, wgs=4, with_stats=True)[-1]
+    try:
+        otkm_gpu.ot_split_set(100, 4)
+        assert otkm_gpu.ot_split_get() == (100, 4)
+        plan, cost, u, v, st = otkm_gpu.ot_assign(C, with_stats=True)
+        assert st["status"] == 0 and cost == ref[1]
+        assert oracle.certify_assign(C, plan, u, v) == 0
+        # the step counts are those of the 4-workgroup engine (they do not depend on timing)
+        for key in ("levels", "rows_swept", "gathers", "resweeps", "refreshes"):
+            assert st[key] == st4[key], key
+        small = wl.uniform_assignment(64, seed=2)
+        assert otkm_gpu.ot_assign(small)[1] == oracle.assign(small)[1]
+    finally:
+        otkm_gpu.ot_split_set(0, 0)
+    assert otkm_gpu.ot_split_get() == (2048, 8)
