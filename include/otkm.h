@@ -335,7 +335,7 @@ int ot_schedule_tune(int32_t reps);
  * ot_assign_ex, ot_assign_dev, ot_assign_rect*) whose options leave both wgs
  * and block at 0 runs on `wgs` workgroups when n (the longer side) exceeds
  * n_split, else on one.  Defaults measured on MI355X: n_split = 2048, wgs = 8.
- * (Scaled solves split into 4 above n = 1024.)  ot_split_set: n_split >= 0,
+ * (Scaled solves split into 2 above n = 256 and into 4 above n = 1024.)  ot_split_set: n_split >= 0,
  * wgs 0 or 2..16, 0 restores a default (OT_EINVAL otherwise); n_split =
  * OT_MAX_N never splits.  ot_split_tune times one exact solve per size of a
  * ladder (1536 .. 4096) at 1, 4 and 8 workgroups on synthetic geometric

@@ -167,11 +167,12 @@ static bool range_ok(const int32_t *C, int64_t count) {
 // exchange through global memory costs about as much as splitting the sweep
 // saves at n = 2048 (128.8 vs 126.2 ms), and wins above (n = 2560: 295 -> 197
 // ms, n = 4096: 644 -> 350 ms with 8 workgroups).  Scaled costs make fewer,
-// wider steps, where the split pays from n = 2048 down (s = 100: 76.4 -> 33.3
-// ms with 4 workgroups).
+// wider steps, where the split pays far below (s = 100: 4 workgroups at
+// n = 2048, 76.4 -> 33.3 ms; 2 at n = 1024, 17.7 -> 13.3 ms; 2 at n = 512,
+// 10.4 -> 5.0 ms).
 constexpr int kDefaultSplitN = 2048, kDefaultSplitWgs = 8;
 static int default_wgs(int n, int scale) {
-  if (scale > 1) return n > 1024 ? 4 : 1;
+  if (scale > 1) return n > 1024 ? 4 : (n > 256 ? 2 : 1);
   const int sn = g_split_n.load() > 0 ? g_split_n.load() : kDefaultSplitN;
   const int sw = g_split_wgs.load() > 0 ? g_split_wgs.load() : kDefaultSplitWgs;
   return n > sn ? sw : 1;
