@@ -59,6 +59,54 @@ def counters(stats):
                                              "resweeps", "refreshes")}
 
 
+def host_info():
+    """Host CPU threads available to this process and the CPU model (from /proc/cpuinfo)."""
+    try:
+        threads = len(os.sched_getaffinity(0))
+    except AttributeError:
+        threads = os.cpu_count() or 1
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"host_threads": threads, "cpu_model": model}
+
+
+def cpu_baseline(value, unit, cores, sample, **extra):
+    return {"value": round(value, 5), "unit": unit, "cores": cores, "kind": "oracle", "sample": sample,
+            **host_info(), **extra}
+
+
+def _pool_oracle_costs(mats):
+    import oracle
+    return [oracle.assign(C)[1] for C in mats]
+
+
+def cpu_pool_rate(mats, budget_s, workers):
+    """The single-threaded oracle in a process pool of `workers` processes over
+    as many of mats (in order) as finish within about budget_s; returns
+    (solves/s, solves done, their costs)."""
+    import multiprocessing as mp
+    ctx = mp.get_context("spawn")  # fresh interpreters: the workers never touch the GPU
+    chunk = max(1, workers)
+    done, costs = 0, []
+    with ctx.Pool(workers) as pool:
+        pool.map(_pool_oracle_costs, [[np.zeros((1, 1), np.int32)]] * workers)  # start-up outside the clock
+        t0 = time.perf_counter()
+        while done < len(mats) and time.perf_counter() - t0 < budget_s:
+            part = mats[done:done + 4 * chunk]
+            out = pool.map(_pool_oracle_costs, [[C] for C in part], chunksize=1)
+            costs.extend(c[0] for c in out)
+            done += len(part)
+        dt = time.perf_counter() - t0
+    return done / dt, done, costs
+
+
 def cpu_rate(fn, items, budget_s):
     """Run the CPU oracle over items until the budget is spent; returns (items/s, items done)."""
     t0 = time.perf_counter()
@@ -193,10 +241,14 @@ def bench_assign(args, C, workload, cpu_samples, tag):
                                                                           "refresh")}
     if not args.skip_cpu:
         import oracle
+        ref = oracle.assign(C)[1]
+        if ref != cost:
+            raise SystemExit("GPU cost %d differs from the oracle's %d" % (cost, ref))
         rate, done = cpu_rate(oracle.assign, cpu_samples, args.cpu_budget)
-        out["cpu_baseline"] = {"value": round(rate, 5), "unit": "solves/s", "cores": 1, "kind": "oracle",
-                               "sample": "%d solve(s) of the same instance (n=%d) by the single-threaded C "
-                                         "oracle (O(n^3) shortest augmenting path)" % (done, n)}
+        out["cpu_baseline"] = cpu_baseline(rate, "solves/s", 1,
+                                           "%d solve(s) of the same instance (n=%d) by the single-threaded C "
+                                           "oracle (O(n^3) shortest augmenting path)" % (done, n),
+                                           oracle_cost_equal=True)
     return out
 
 
@@ -265,10 +317,17 @@ def bench_scaled(args):
     out["solver_counters"] = {**counters(stats), "alg_bytes_per_solve": int(b[0])}
     if not args.skip_cpu:
         import oracle
+        # plans may differ under ties of the scaled costs: compare the scaled optimum
+        Cs = np.floor_divide(C.astype(np.int64), sc)
+        rplan = oracle.assign_scaled(C, sc)[0]
+        gplan = plan.cpu().numpy()
+        rows = np.arange(n)
+        if int(Cs[rows, gplan].sum()) != int(Cs[rows, rplan].sum()):
+            raise SystemExit("GPU scaled optimum differs from the oracle's")
         rate, done = cpu_rate(lambda c: oracle.assign_scaled(c, sc), [C] * 3, args.cpu_budget)
-        out["cpu_baseline"] = {"value": round(rate, 5), "unit": "solves/s", "cores": 1, "kind": "oracle",
-                               "sample": "%d solve(s) of the same scaled instance by the single-threaded C "
-                                         "oracle" % done}
+        out["cpu_baseline"] = cpu_baseline(rate, "solves/s", 1,
+                                           "%d solve(s) of the same scaled instance by the single-threaded C "
+                                           "oracle" % done, oracle_cost_equal=True)
     return out
 
 
@@ -320,10 +379,12 @@ def bench_rect(args):
     out["solver_counters"] = {**counters(stats), "alg_bytes_per_solve": int(b[0])}
     if not args.skip_cpu:
         import oracle
+        if oracle.assign_rect(C)[1] != int(cost.item()):
+            raise SystemExit("GPU cost differs from the oracle's")
         rate, done = cpu_rate(oracle.assign_rect, [C] * 3, args.cpu_budget)
-        out["cpu_baseline"] = {"value": round(rate, 5), "unit": "solves/s", "cores": 1, "kind": "oracle",
-                               "sample": "%d solve(s) of the same instance by the single-threaded C oracle "
-                                         "(rectangular shortest augmenting path)" % done}
+        out["cpu_baseline"] = cpu_baseline(rate, "solves/s", 1,
+                                           "%d solve(s) of the same instance by the single-threaded C oracle "
+                                           "(rectangular shortest augmenting path)" % done, oracle_cost_equal=True)
     return out
 
 
@@ -377,10 +438,13 @@ def bench_transport(args):
     out["solver_counters"] = {**counters(stats), "alg_bytes_per_solve": int(b[0])}
     if not args.skip_cpu:
         import oracle
+        if oracle.transport(C, r, c)[1] != int(cost.item()):
+            raise SystemExit("GPU transport cost differs from the oracle's")
         rate, done = cpu_rate(lambda _: oracle.transport(C, r, c), range(100), args.cpu_budget)
-        out["cpu_baseline"] = {"value": round(rate, 5), "unit": "solves/s", "cores": 1, "kind": "oracle",
-                               "sample": "%d solve(s) of the same instance by the single-threaded C oracle "
-                                         "(unit expansion + O(S^3) shortest augmenting path)" % done}
+        out["cpu_baseline"] = cpu_baseline(rate, "solves/s", 1,
+                                           "%d solve(s) of the same instance by the single-threaded C oracle "
+                                           "(unit expansion + O(S^3) shortest augmenting path)" % done,
+                                           oracle_cost_equal=True)
     return out
 
 
@@ -495,10 +559,27 @@ def bench_batch(args):
                               "alg_bytes_per_launch": int(b.sum()) + transpose_bytes}
     if not args.skip_cpu:
         import oracle
-        rate, done = cpu_rate(oracle.assign, Cs, args.cpu_budget)
-        out["cpu_baseline"] = {"value": round(rate, 4), "unit": "solves/s", "cores": 1, "kind": "oracle",
-                               "sample": "first %d problems of the batch (sizes as drawn), single-threaded C "
-                                         "oracle" % done}
+        gpu_cost = cost.cpu().numpy()
+        workers = max(1, min(16, host_info()["host_threads"]))
+        log("cpu baseline: oracle pool of %d processes, then single-threaded" % workers)
+        prate, pdone, pcosts = cpu_pool_rate(Cs, args.cpu_budget, workers)
+        t0 = time.perf_counter()
+        sdone = 0
+        for k in range(pdone, count):
+            if oracle.assign(Cs[k])[1] != int(gpu_cost[k]):
+                raise SystemExit("GPU cost of problem %d differs from the oracle's" % k)
+            sdone += 1
+            if time.perf_counter() - t0 > args.cpu_budget:
+                break
+        srate = sdone / (time.perf_counter() - t0)
+        if any(int(gpu_cost[k]) != c for k, c in enumerate(pcosts)):
+            raise SystemExit("GPU cost differs from the oracle's on the pool sample")
+        out["cpu_baseline"] = cpu_baseline(prate, "solves/s", workers,
+                                           "problems 0..%d of the batch (sizes as drawn), the single-threaded C "
+                                           "oracle in a pool of %d processes" % (pdone - 1, workers),
+                                           oracle_cost_equal=pdone + sdone,
+                                           single_thread={"value": round(srate, 4), "cores": 1,
+                                                          "sample": "problems %d..%d" % (pdone, pdone + sdone - 1)})
     return out
 
 
@@ -560,9 +641,10 @@ def bench_serve(args):
             if recs[k]["status"] == 0 and recs[k]["cost"] != c:
                 raise SystemExit("served cost of request %d differs from the oracle" % k)
         out["checked_against_oracle"] = len(costs)
-        out["cpu_baseline"] = {"value": round(cpu, 3), "unit": "solves/s", "cores": 1, "kind": "oracle",
-                               "sample": "%d requests of the stream with n <= 256 (the rest is too slow on the "
-                                         "CPU), single-threaded C oracle" % len(costs)}
+        out["cpu_baseline"] = cpu_baseline(cpu, "solves/s", 1,
+                                           "%d requests of the stream with n <= 256 (the rest is too slow on the "
+                                           "CPU), single-threaded C oracle" % len(costs),
+                                           oracle_cost_equal=len(costs))
     return out
 
 

@@ -331,6 +331,18 @@ int ot_schedule_get(int32_t *t64, int32_t *t256);
 int ot_schedule_set(int32_t t64, int32_t t256);
 int ot_schedule_tune(int32_t reps);
 
+/* The decision rule of ot_schedule_tune on a timing table, host only (no
+ * device needed, nothing is set): sizes [nsizes] strictly increasing, widths
+ * [nwidths] each 64, 256 or 512, ms [nsizes * nwidths] (row-major by size)
+ * the time of each probe, <= 0 or NaN for a probe that was not run or failed.
+ * Per size the fastest width wins (the narrower on a tie); *t64 is the
+ * largest size of the contiguous prefix won by 64 lanes (at least 1), *t256
+ * that of the prefix won by 64 or 256 lanes (at least *t64), so widths never
+ * narrow as n grows.  OT_EINVAL for bad arguments or a size with no
+ * successful probe. */
+int ot_schedule_rule(int32_t nsizes, const int32_t *sizes, int32_t nwidths, const int32_t *widths,
+                     const float *ms, int32_t *t64, int32_t *t256);
+
 /* Single-instance split: an exact single-instance solve (ot_assign,
  * ot_assign_ex, ot_assign_dev, ot_assign_rect*) whose options leave both wgs
  * and block at 0 runs on `wgs` workgroups when n (the longer side) exceeds
@@ -345,6 +357,18 @@ int ot_schedule_tune(int32_t reps);
 int ot_split_get(int32_t *n_split, int32_t *wgs);
 int ot_split_set(int32_t n_split, int32_t wgs);
 int ot_split_tune(void);
+
+/* The decision rule of ot_split_tune on a timing table, host only: sizes
+ * [nsizes] strictly increasing and <= OT_MAX_N, cands [ncands] workgroup
+ * counts with cands[0] == 1 and the others in 2..16, ms [nsizes * ncands]
+ * (row-major by size) all > 0.  A count wins a size when it is faster than
+ * one workgroup by more than 2% and than every other count.  *n_split = the
+ * largest size of the contiguous prefix won by one workgroup (sizes[0] - 1
+ * when a split wins the smallest size; OT_MAX_N when none wins the largest),
+ * *wgs = the count that wins the largest size (0 when none).  OT_EINVAL for
+ * bad arguments. */
+int ot_split_rule(int32_t nsizes, const int32_t *sizes, int32_t ncands, const int32_t *cands,
+                  const float *ms, int32_t *n_split, int32_t *wgs);
 
 #ifdef __cplusplus
 }

@@ -59,13 +59,14 @@ extern "C" int ot_schedule_tune(int32_t reps) {
   std::lock_guard<std::mutex> lk(lib_mutex());
   int rc = init_locked();
   if (rc) return rc;
-  const int sizes[] = {32, 48, 64, 96, 128, 192, 256, 384, 512, 768, 1024};
-  const int widths[] = {64, 256, 512};
+  const int32_t sizes[] = {32, 48, 64, 96, 128, 192, 256, 384, 512, 768, 1024};
+  const int32_t widths[] = {64, 256, 512};
+  constexpr int NS = sizeof(sizes) / sizeof(sizes[0]), NW = sizeof(widths) / sizeof(widths[0]);
   const int64_t budget = 256ll << 20;  // cost entries per probe (1 GiB)
   hipStream_t s = lib_stream();
-  int best_w[sizeof(sizes) / sizeof(sizes[0])];
+  float ms[NS * NW];
   uint64_t lcg = 0x9e3779b97f4a7c15ull;
-  for (size_t si = 0; si < sizeof(sizes) / sizeof(sizes[0]); ++si) {
+  for (int si = 0; si < NS; ++si) {
     const int n = sizes[si];
     int slots = 1;  // workgroup slots of the whole chip at the narrowest eligible width
     for (int w : widths)
@@ -96,26 +97,51 @@ extern "C" int ot_schedule_tune(int32_t reps) {
     hipMemcpyAsync(dcoff, coff.data(), 8 * (size_t)count, hipMemcpyHostToDevice, s);
     hipMemcpyAsync(dvoff, voff.data(), 8 * (size_t)count, hipMemcpyHostToDevice, s);
     hipMemcpyAsync(dn, nn.data(), 4 * (size_t)count, hipMemcpyHostToDevice, s);
-    float best = -1.f;
-    best_w[si] = 1024;
-    for (int w : widths) {
+    for (int wi = 0; wi < NW; ++wi) {
+      const int w = widths[wi];
+      ms[si * NW + wi] = -1.f;
       if (cpt_for(n, w) == 0) continue;
       const int occ = batch_occupancy(w, n);
       if (occ <= 0) continue;
       const int grid = std::max(1, std::min(count, occ * device_cus()));
       auto *dws = (int32_t *)pool_get(67, 4 * ws_ints(n) * (size_t)grid, &err);
       if (err) return err;
-      const float ms = time_batch(w, n, count, dC, dcoff, dn, dvoff, dplan, dcost, head, dws, s);
-      if (ms > 0 && (best < 0 || ms < best)) { best = ms; best_w[si] = w; }
+      ms[si * NW + wi] = time_batch(w, n, count, dC, dcoff, dn, dvoff, dplan, dcost, head, dws, s);
     }
-    if (best < 0) return OT_EDEVICE;
   }
-  // contiguous prefixes: widths must not narrow as n grows
-  int t64 = 0, t256 = 0;
-  for (size_t si = 0; si < sizeof(sizes) / sizeof(sizes[0]) && best_w[si] == 64; ++si) t64 = sizes[si];
-  t256 = t64;
-  for (size_t si = 0; si < sizeof(sizes) / sizeof(sizes[0]) && best_w[si] <= 256; ++si) t256 = std::max(t256, sizes[si]);
-  schedule_set_locked(std::max(t64, 1), std::max(t256, std::max(t64, 1)));
+  int32_t t64 = 0, t256 = 0;
+  if (ot_schedule_rule(NS, sizes, NW, widths, ms, &t64, &t256) != OT_OK) return OT_EDEVICE;
+  schedule_set_locked(t64, t256);
+  return OT_OK;
+}
+
+// The width per size is the fastest probe (the narrower on a tie); the
+// thresholds are the contiguous prefixes of sizes won by one wavefront and by
+// at most 256 lanes, so widths never narrow as n grows.
+extern "C" int ot_schedule_rule(int32_t nsizes, const int32_t *sizes, int32_t nwidths, const int32_t *widths,
+                                const float *ms, int32_t *t64, int32_t *t256) {
+  if (nsizes <= 0 || nwidths <= 0 || !sizes || !widths || !ms || !t64 || !t256) return OT_EINVAL;
+  for (int si = 1; si < nsizes; ++si)
+    if (sizes[si] <= sizes[si - 1]) return OT_EINVAL;
+  for (int wi = 0; wi < nwidths; ++wi)
+    if (widths[wi] != 64 && widths[wi] != 256 && widths[wi] != 512) return OT_EINVAL;
+  std::vector<int> best_w(nsizes);
+  for (int si = 0; si < nsizes; ++si) {
+    float best = -1.f;
+    best_w[si] = 0;
+    for (int wi = 0; wi < nwidths; ++wi) {
+      const float t = ms[(size_t)si * nwidths + wi];
+      if (!(t > 0.f)) continue;  // not run, failed, or NaN
+      if (best < 0.f || t < best || (t == best && widths[wi] < best_w[si])) { best = t; best_w[si] = widths[wi]; }
+    }
+    if (best_w[si] == 0) return OT_EINVAL;  // no probe of this size succeeded
+  }
+  int a = 0, b = 0;
+  for (int si = 0; si < nsizes && best_w[si] == 64; ++si) a = sizes[si];
+  b = a;
+  for (int si = 0; si < nsizes && best_w[si] <= 256; ++si) b = std::max(b, sizes[si]);
+  *t64 = std::max(a, 1);
+  *t256 = std::max(b, *t64);
   return OT_OK;
 }
 
@@ -164,8 +190,8 @@ extern "C" int ot_split_tune(void) {
     int rc = init_locked();
     if (rc) return rc;
   }
-  const int sizes[] = {1536, 2048, 2560, 3072, 4096};
-  const int cands[] = {1, 4, 8};
+  const int32_t sizes[] = {1536, 2048, 2560, 3072, 4096};
+  const int32_t cands[] = {1, 4, 8};
   constexpr int NS = sizeof(sizes) / sizeof(sizes[0]), NC = sizeof(cands) / sizeof(cands[0]);
   const int nmax = sizes[NS - 1];
   hipStream_t s = nullptr;
@@ -198,18 +224,9 @@ extern "C" int ot_split_tune(void) {
     }
   }
   if (rc == OT_OK) {
-    auto best_at = [&](int si) {
-      int b = 0;
-      for (int ci = 1; ci < NC; ++ci)
-        if (ms[si][ci] < 0.98f * ms[si][0] && ms[si][ci] < ms[si][b]) b = ci;
-      return b;
-    };
-    int n_split = 0;
-    for (int si = 0; si < NS && best_at(si) == 0; ++si) n_split = sizes[si];
-    const int top = best_at(NS - 1);
-    if (n_split == 0) n_split = sizes[0] - 1;  // splitting wins from the smallest size tried
-    if (top == 0) n_split = OT_MAX_N;           // never split
-    ot_split_set(n_split, top == 0 ? 0 : cands[top]);
+    int32_t n_split = 0, wgs = 0;
+    rc = ot_split_rule(NS, sizes, NC, cands, &ms[0][0], &n_split, &wgs);
+    if (rc == OT_OK) ot_split_set(n_split, wgs);
   }
   if (e0) hipEventDestroy(e0);
   if (e1) hipEventDestroy(e1);
@@ -222,4 +239,35 @@ extern "C" int ot_split_tune(void) {
   }
   hipStreamDestroy(s);
   return rc;
+}
+
+// The split rule: a candidate count wins a size when it beats one workgroup by
+// more than 2% (and every other candidate); n_split is the largest size of the
+// contiguous prefix won by one workgroup (one below the smallest size when a
+// split wins from the start, OT_MAX_N when none wins at the largest size), and
+// wgs is the count that wins at the largest size (0, the default, when none).
+extern "C" int ot_split_rule(int32_t nsizes, const int32_t *sizes, int32_t ncands, const int32_t *cands,
+                             const float *ms, int32_t *n_split, int32_t *wgs) {
+  if (nsizes <= 0 || ncands <= 0 || !sizes || !cands || !ms || !n_split || !wgs || cands[0] != 1) return OT_EINVAL;
+  for (int si = 1; si < nsizes; ++si)
+    if (sizes[si] <= sizes[si - 1] || sizes[si] > OT_MAX_N) return OT_EINVAL;
+  for (int ci = 1; ci < ncands; ++ci)
+    if (cands[ci] < 2 || cands[ci] > kMaxWgs) return OT_EINVAL;
+  for (int k = 0; k < nsizes * ncands; ++k)
+    if (!(ms[k] > 0.f)) return OT_EINVAL;
+  auto best_at = [&](int si) {
+    const float *t = ms + (size_t)si * ncands;
+    int b = 0;
+    for (int ci = 1; ci < ncands; ++ci)
+      if (t[ci] < 0.98f * t[0] && t[ci] < t[b]) b = ci;
+    return b;
+  };
+  int ns = 0;
+  for (int si = 0; si < nsizes && best_at(si) == 0; ++si) ns = sizes[si];
+  const int top = best_at(nsizes - 1);
+  if (ns == 0) ns = sizes[0] - 1;  // splitting wins from the smallest size tried
+  if (top == 0) ns = OT_MAX_N;     // never split
+  *n_split = ns;
+  *wgs = top == 0 ? 0 : cands[top];
+  return OT_OK;
 }

@@ -516,8 +516,8 @@ struct Engine {
 
   // GRID exchanges.  Every word a workgroup publishes carries the level it
   // belongs to, so a reader fetches tags and data in one round and polls until
-  // all of them show the current level: minimum words hold (level mod 2^24) <<
-  // 40 | key value (40 bits), the error word level << 32 | error, settled
+  // all of them show the current level: minimum words hold (level mod 2^31) <<
+  // 33 | key value (33 bits), the error word level << 32 | error, settled
   // columns (level mod 2^28) << 36 | column << 24 | row << 12 | tree, and a
   // list's count word level << 32 | count.  Polls are bounded and end on the
   // abort flag.
@@ -533,12 +533,17 @@ struct Engine {
     }
     return ab != 0;
   }
+  // A key value is below 3 * 2^31 < 2^33 - 1, so 33 bits hold it with all ones
+  // for "no key", and the remaining 31 bits tag the level.
+  static constexpr uint64_t kMinVal = (1ull << 33) - 1;
+  static constexpr uint32_t kLevTag = 0x7fffffffu;
   static __device__ __forceinline__ uint64_t enc_min(uint64_t key, uint32_t lv) {
-    return ((uint64_t)(lv & 0xffffffu) << 40) | (key >> kRowBits);
+    const uint64_t v = key == kInf ? kMinVal : (key >> kRowBits);
+    return ((uint64_t)(lv & kLevTag) << 33) | v;
   }
   static __device__ __forceinline__ uint64_t dec_min(uint64_t w) {
-    const uint64_t v = w & 0xffffffffffull;
-    return v == 0xffffffffffull ? kInf : v << kRowBits;
+    const uint64_t v = w & kMinVal;
+    return v == kMinVal ? kInf : v << kRowBits;
   }
 
   // GRID: publish this workgroup's slot set s (minimum pair, error es), read
@@ -559,7 +564,7 @@ struct Engine {
       bool stop = false;
       for (int it = 0;; ++it) {
         if (w < G) x = __hip_atomic_load(&slot[3 * w + k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const bool ok = w >= G || (k < 2 ? (uint32_t)(x >> 40) == (lev & 0xffffffu) : (uint32_t)(x >> 32) == lev);
+        const bool ok = w >= G || (k < 2 ? (uint32_t)(x >> 33) == (lev & kLevTag) : (uint32_t)(x >> 32) == lev);
         if (__builtin_amdgcn_ballot_w64(!ok) == 0) break;
         if (poll_abort(it)) { stop = true; break; }
         __builtin_amdgcn_s_sleep(1);
@@ -848,8 +853,9 @@ struct Engine {
 
     int nfree = nr, nalive = K, cursor = K;
     int64_t D = 0;
-    int64_t watchdog = (int64_t)(n + 2) * (int64_t)(n + 2) + 64;
-    if (GRID && watchdog > (1 << 24) - 2) watchdog = (1 << 24) - 2;  // exchange tags hold 24 bits of the level
+    // (n + 2)^2 + 64 <= 16,793,668 for n <= 4096: below every exchange tag's
+    // range (31 bits on minimum words, 28 on settled columns), so tags never wrap
+    const int64_t watchdog = (int64_t)(n + 2) * (int64_t)(n + 2) + 64;
     const bool timers = (P.flags & OT_FLAG_PHASE_TIMERS) != 0;
     int64_t tprev = timers ? now_ticks() : 0;
 

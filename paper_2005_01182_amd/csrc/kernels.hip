@@ -62,10 +62,16 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2))) void
     __syncthreads();
     if (idx >= A.nq) break;  // every workgroup reaches this exit once the queue drains
     const int k = A.order ? A.order[idx] : idx;
-    if ((unsigned)k >= (unsigned)A.count) continue;
+    if ((unsigned)k >= (unsigned)A.count) continue;  // no such instance: nothing to report or flag
     const int n = A.n[k];
     if (n < 1 || n > A.max_n || n > BLOCK * CPT) {
-      if (A.stats && threadIdx.x == 0) { ot_stats s = {}; s.status = OT_EINVAL; A.stats[k] = s; }
+      if (threadIdx.x == 0) {
+        if (A.stats) { ot_stats s = {}; s.status = OT_EINVAL; A.stats[k] = s; }
+        if (A.done) {
+          __threadfence_system();
+          __hip_atomic_store(&A.done[k], A.tag, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+        }
+      }
       continue;
     }
     Problem P;
@@ -295,7 +301,7 @@ __global__ __launch_bounds__(1024) void k_rect_finish(int n, int m, int trans, c
   const int status = sq->status;
   if (stats && tid == 0) *stats = *sq;
   if (status != 0) return;
-  const int rows = trans ? m : n, cols = trans ? n : m;  // the solver's sides
+  const int cols = trans ? n : m;  // the solver's columns
   int64_t mx = INT64_MIN;
   for (int k = tid; k < cols; k += 1024) mx = vq[k] > mx ? vq[k] : mx;
   red[tid] = mx;

@@ -84,7 +84,7 @@ struct Lane {  // one stream; each size class has cfg.streams of them
 
 struct ot_server {
   ot_serve_cfg cfg{};
-  int maxn = OT_MAX_N, slots = 256, cus = 1;
+  int maxn = OT_MAX_N, slots = 256, cus = 1, dev = 0;
   char *arena_base = nullptr;
   std::unique_ptr<otkm::Arena> arena;
   int32_t *d_pts = nullptr;                   // [slots][4 maxn]
@@ -229,7 +229,15 @@ bool retire(ot_server *s) {
   for (int li = 0; li < s->nlanes(); ++li) {
     Lane &L = s->lanes[li];
     if (!L.busy) continue;
-    if (hipEventQuery(L.ev) != hipSuccess) continue;
+    const hipError_t q = hipEventQuery(L.ev);
+    if (q == hipErrorNotReady) continue;
+    if (q != hipSuccess) {
+      // the group's kernel failed: its flags will never arrive, so every waiter
+      // is woken with the error instead of waiting forever
+      if (s->fatal == 0) s->fatal = map_hip(q);
+      changed = true;
+      continue;
+    }
     if (L.outstanding > 0) continue;  // the flags of a finished kernel are visible on the next pass
     L.busy = false;
     changed = true;
@@ -283,7 +291,7 @@ bool admit(ot_server *s) {
 }
 
 void worker_main(ot_server *s) {
-  hipSetDevice(0);
+  hipSetDevice(s->dev);  // the device that was current at ot_serve_open
   std::unique_lock<std::mutex> lk(s->mu);
   for (;;) {
     if (s->fatal) break;
@@ -335,7 +343,10 @@ int ot_serve_open(ot_server **out, const ot_serve_cfg *cfg_in) {
     int rc = init_locked();
     if (rc) return rc;
   }
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return OT_ENODEV;
   auto *s = new ot_server();
+  s->dev = dev;
   s->cfg = cfg;
   s->maxn = cfg.max_n;
   s->slots = cfg.max_inflight;

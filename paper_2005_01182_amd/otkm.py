@@ -25,7 +25,8 @@ EXPORTS = [
     "ot_strerror", "ot_init", "ot_assign", "ot_assign_ex", "ot_assign_rect", "ot_scale_for", "ot_transport",
     "ot_assign_batch",
     "ot_assign_dev", "ot_assign_rect_dev", "ot_assign_batch_dev", "ot_transpose_batch_dev", "ot_transport_dev",
-    "ot_schedule_get", "ot_schedule_set", "ot_schedule_tune", "ot_split_get", "ot_split_set", "ot_split_tune",
+    "ot_schedule_get", "ot_schedule_set", "ot_schedule_tune", "ot_schedule_rule",
+    "ot_split_get", "ot_split_set", "ot_split_tune", "ot_split_rule",
     "ot_grid_cost_dev", "ot_serve_open", "ot_serve_submit", "ot_serve_poll", "ot_serve_stats", "ot_serve_close",
 ]
 
@@ -117,6 +118,8 @@ def load():
         lib.ot_split_get.argtypes = [_VP, _VP]
         lib.ot_split_set.argtypes = [_I32, _I32]
         lib.ot_split_tune.argtypes = []
+        lib.ot_schedule_rule.argtypes = [_I32, _VP, _I32, _VP, _VP, _VP, _VP]
+        lib.ot_split_rule.argtypes = [_I32, _VP, _I32, _VP, _VP, _VP, _VP]
         lib.ot_grid_cost_dev.argtypes = [_VP, _VP, _I32, _VP, _VP]
         lib.ot_serve_open.argtypes = [ctypes.POINTER(ctypes.c_void_p), _VP]
         lib.ot_serve_submit.argtypes = [_VP, _VP, _VP, _I32, ctypes.POINTER(ctypes.c_uint64)]
@@ -285,6 +288,28 @@ def ot_schedule_set(t64: int, t256: int):
 def ot_schedule_tune(reps: int = 8):
     _check(load().ot_schedule_tune(int(reps)), "ot_schedule_tune")
     return ot_schedule_get()
+
+
+def _rule(fn, name, sizes, cands, ms):
+    sizes = np.ascontiguousarray(sizes, dtype=np.int32)
+    cands = np.ascontiguousarray(cands, dtype=np.int32)
+    ms = np.ascontiguousarray(ms, dtype=np.float32)
+    if ms.shape != (sizes.size, cands.size):
+        raise ValueError("timing table must be sizes x candidates")
+    a, b = ctypes.c_int32(0), ctypes.c_int32(0)
+    _check(fn(int(sizes.size), _p(sizes), int(cands.size), _p(cands), _p(ms), ctypes.byref(a), ctypes.byref(b)),
+           name)
+    return int(a.value), int(b.value)
+
+
+def ot_schedule_rule(sizes, widths, ms):
+    """The batch tuner's decision on a timing table ms[size, width] (host only): (t64, t256)."""
+    return _rule(load().ot_schedule_rule, "ot_schedule_rule", sizes, widths, ms)
+
+
+def ot_split_rule(sizes, cands, ms):
+    """The split tuner's decision on a timing table ms[size, count] (host only): (n_split, wgs)."""
+    return _rule(load().ot_split_rule, "ot_split_rule", sizes, cands, ms)
 
 
 # ----------------------------------------------------------------------------- device calls
