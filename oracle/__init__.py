@@ -17,6 +17,8 @@ Functions (all exact, int64 results):
 * ``certify_rect(C, plan, u, v)``     -> 0 if the rectangular LP certificate holds
 * ``transport(C, r, c)``    -> (X, cost, u, v)      unit expansion + ``assign``
 * ``certify_transport(C, r, c, X, u, v)`` -> 0 if the certificate holds
+* ``transport_bins(C, r, c)`` -> (X, cost, u, v)  successive shortest paths on the
+                             bins themselves (no unit expansion; masses up to 2^31 - 1)
 """
 from __future__ import annotations
 
@@ -61,9 +63,10 @@ def _load():
             lib.oracle_certify_rect.argtypes = [_I32P, i32, i32, _I32P, _I64P, _I64P]
             lib.oracle_transport.argtypes = [_I32P, _I32P, _I32P, i32, i32, _I32P, _I64P, _I64P, i64p]
             lib.oracle_certify_transport.argtypes = [_I32P, _I32P, _I32P, i32, i32, _I32P, _I64P, _I64P]
+            lib.oracle_transport_ssp.argtypes = [_I32P, _I32P, _I32P, i32, i32, _I32P, _I64P, _I64P, i64p]
             for f in (lib.oracle_assign, lib.oracle_brute_force, lib.oracle_certify_assign,
                       lib.oracle_assign_rect, lib.oracle_certify_rect,
-                      lib.oracle_transport, lib.oracle_certify_transport):
+                      lib.oracle_transport, lib.oracle_certify_transport, lib.oracle_transport_ssp):
                 f.restype = ctypes.c_int
             _lib = lib
     return _lib
@@ -196,3 +199,22 @@ def certify_transport(C, r, c, X, u, v) -> int:
         C, np.ascontiguousarray(r, dtype=np.int32), np.ascontiguousarray(c, dtype=np.int32), n, m,
         np.ascontiguousarray(X, dtype=np.int32), np.ascontiguousarray(u, dtype=np.int64),
         np.ascontiguousarray(v, dtype=np.int64)))
+
+
+def transport_bins(C, r, c):
+    """Exact integer transport solved on the bins (Eq. (1) as a min-cost flow,
+    successive shortest paths with potentials): returns (X int32[n,m], cost int,
+    u int64[n], v int64[m]); zero-mass bins get the same dual convention as
+    ``transport``.  Total mass up to 2^31 - 1."""
+    C = np.ascontiguousarray(C, dtype=np.int32)
+    r = np.ascontiguousarray(r, dtype=np.int32)
+    c = np.ascontiguousarray(c, dtype=np.int32)
+    n, m = C.shape
+    X = np.empty((n, m), np.int32)
+    u = np.empty(n, np.int64)
+    v = np.empty(m, np.int64)
+    cost = ctypes.c_int64(0)
+    rc = _load().oracle_transport_ssp(C, r, c, n, m, X, u, v, ctypes.byref(cost))
+    if rc:
+        raise RuntimeError("oracle_transport_ssp failed: %d" % rc)
+    return X, int(cost.value), u, v

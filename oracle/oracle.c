@@ -280,6 +280,142 @@ out:
     return rc;
 }
 
+/* ------------------------------------------------------------------------- */
+/* Transport on bins: successive shortest paths (no unit expansion)          */
+/* ------------------------------------------------------------------------- */
+/*
+ * Eq. (1) as a min-cost flow: source -> row bin i (capacity r_i), row i ->
+ * column bin j (unbounded, cost C_ij), column j -> sink (capacity c_j), the
+ * textbook successive-shortest-path method with potentials.  The potentials
+ * are the LP duals u (rows) and v (columns); they start at the reduction
+ * u_i = min_j C_ij, v_j = min_i (C_ij - u_i), which is feasible.
+ *
+ * Each stage runs Dijkstra on reduced costs from every row that still has
+ * supply: a row reaches column j at cost C_ij - u_i - v_j >= 0, and a column
+ * reaches back, at cost 0, every row that already ships to it (the residual
+ * arc of a positive flow, which is tight).  The first column settled that
+ * still has demand ends the stage at distance D.  Every settled row gains
+ * D - dist and every settled column loses D - dist: the duals stay feasible
+ * and the whole path becomes tight.  The path then ships the largest amount
+ * it can: the root's supply left, the end's demand left, and the flow on
+ * every backward arc.  When all supply has shipped, flows sit on tight edges
+ * only, so X and (u, v) are both optimal.  Zero-mass bins get the convention
+ * of oracle_transport.  Masses may sum to 2^31 - 1.
+ */
+int oracle_transport_ssp(const int32_t *C, const int32_t *r, const int32_t *c, int32_t n, int32_t m,
+                         int32_t *X, int64_t *u_out, int64_t *v_out, int64_t *cost_out)
+{
+    if (!C || !r || !c || !X || n <= 0 || m <= 0) return ORC_EINVAL;
+    int64_t sr = 0, sc = 0;
+    for (int32_t i = 0; i < n; ++i) { if (r[i] < 0) return ORC_ENEGMASS; sr += r[i]; }
+    for (int32_t j = 0; j < m; ++j) { if (c[j] < 0) return ORC_ENEGMASS; sc += c[j]; }
+    if (sr != sc || sr < 1) return ORC_EUNBALANCED;
+    if (sr > INT32_MAX) return ORC_EINVAL;
+    const size_t N = (size_t)n, M = (size_t)m;
+    int64_t *u = malloc(N * sizeof *u), *v = malloc(M * sizeof *v);
+    int64_t *rs = malloc(N * sizeof *rs), *rd = malloc(M * sizeof *rd);
+    int64_t *dr = malloc(N * sizeof *dr), *dc = malloc(M * sizeof *dc);
+    char *sr_done = malloc(N), *sc_done = malloc(M);
+    int32_t *pr = malloc(N * sizeof *pr), *pc = malloc(M * sizeof *pc);
+    int rc = 0;
+    if (!u || !v || !rs || !rd || !dr || !dc || !sr_done || !sc_done || !pr || !pc) { rc = ORC_ENOMEM; goto out; }
+    memset(X, 0, N * M * sizeof *X);
+    for (int32_t i = 0; i < n; ++i) {
+        int64_t mn = BIG;
+        for (int32_t j = 0; j < m; ++j) if (C[(size_t)i * M + (size_t)j] < mn) mn = C[(size_t)i * M + (size_t)j];
+        u[i] = mn;
+        rs[i] = r[i];
+    }
+    for (int32_t j = 0; j < m; ++j) {
+        int64_t mn = BIG;
+        for (int32_t i = 0; i < n; ++i) {
+            int64_t s = (int64_t)C[(size_t)i * M + (size_t)j] - u[i];
+            if (s < mn) mn = s;
+        }
+        v[j] = mn;
+        rd[j] = c[j];
+    }
+    for (int64_t left = sr; left > 0;) {
+        for (int32_t i = 0; i < n; ++i) { dr[i] = rs[i] > 0 ? 0 : BIG; sr_done[i] = 0; pr[i] = -1; }
+        for (int32_t j = 0; j < m; ++j) { dc[j] = BIG; sc_done[j] = 0; pc[j] = -1; }
+        int32_t end = -1;
+        int64_t D = 0;
+        for (;;) {
+            /* the unsettled vertex of smallest distance (rows before columns on a tie) */
+            int32_t bi = -1, bj = -1;
+            int64_t best = BIG;
+            for (int32_t i = 0; i < n; ++i) if (!sr_done[i] && dr[i] < best) { best = dr[i]; bi = i; }
+            for (int32_t j = 0; j < m; ++j) if (!sc_done[j] && dc[j] < best) { best = dc[j]; bj = j; bi = -1; }
+            if (bi < 0 && bj < 0) { rc = ORC_EINVAL; goto out; } /* unreachable when balanced */
+            if (bi >= 0) {
+                sr_done[bi] = 1;
+                const int32_t *Crow = C + (size_t)bi * M;
+                for (int32_t j = 0; j < m; ++j) {
+                    if (sc_done[j]) continue;
+                    int64_t d = dr[bi] + (int64_t)Crow[j] - u[bi] - v[j];
+                    if (d < dc[j]) { dc[j] = d; pc[j] = bi; }
+                }
+            } else {
+                sc_done[bj] = 1;
+                if (rd[bj] > 0) { end = bj; D = dc[bj]; break; }
+                for (int32_t i = 0; i < n; ++i) {
+                    if (sr_done[i] || X[(size_t)i * M + (size_t)bj] == 0) continue;
+                    if (dc[bj] < dr[i]) { dr[i] = dc[bj]; pr[i] = bj; }
+                }
+            }
+        }
+        for (int32_t i = 0; i < n; ++i) if (sr_done[i]) u[i] += D - dr[i];
+        for (int32_t j = 0; j < m; ++j) if (sc_done[j]) v[j] -= D - dc[j];
+        /* bottleneck along end <- row <- column <- row ... <- root */
+        int64_t amt = rd[end];
+        for (int32_t i = pc[end];;) {
+            if (pr[i] < 0) { if (rs[i] < amt) amt = rs[i]; break; }
+            int32_t j = pr[i];
+            if (X[(size_t)i * M + (size_t)j] < amt) amt = X[(size_t)i * M + (size_t)j];
+            i = pc[j];
+        }
+        rd[end] -= amt;
+        X[(size_t)pc[end] * M + (size_t)end] += (int32_t)amt;
+        for (int32_t i = pc[end];;) {
+            if (pr[i] < 0) { rs[i] -= amt; break; }
+            int32_t j = pr[i];
+            X[(size_t)i * M + (size_t)j] -= (int32_t)amt;
+            i = pc[j];
+            X[(size_t)i * M + (size_t)j] += (int32_t)amt;
+        }
+        left -= amt;
+    }
+    {
+        int64_t total = 0;
+        for (size_t k = 0; k < N * M; ++k) total += (int64_t)C[k] * X[k];
+        for (int32_t i = 0; i < n; ++i) {
+            if (r[i] > 0) continue;
+            int64_t best = BIG;
+            for (int32_t j = 0; j < m; ++j) {
+                if (c[j] == 0) continue;
+                int64_t s = (int64_t)C[(size_t)i * M + (size_t)j] - v[j];
+                if (s < best) best = s;
+            }
+            u[i] = best;
+        }
+        for (int32_t j = 0; j < m; ++j) {
+            if (c[j] > 0) continue;
+            int64_t best = BIG;
+            for (int32_t i = 0; i < n; ++i) {
+                int64_t s = (int64_t)C[(size_t)i * M + (size_t)j] - u[i];
+                if (s < best) best = s;
+            }
+            v[j] = best;
+        }
+        if (u_out) memcpy(u_out, u, N * sizeof *u);
+        if (v_out) memcpy(v_out, v, M * sizeof *v);
+        if (cost_out) *cost_out = total;
+    }
+out:
+    free(u); free(v); free(rs); free(rd); free(dr); free(dc); free(sr_done); free(sc_done); free(pr); free(pc);
+    return rc;
+}
+
 /*
  * Transport certificate.  Returns 0 when:
  *   1  X >= 0

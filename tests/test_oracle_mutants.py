@@ -31,6 +31,12 @@ MUTANTS = {
     "rect_readback": ("for (int32_t j = 0; j < m; ++j) plan[rowof[j]] = j;",
                       "for (int32_t j = 0; j < m; ++j) plan[j] = rowof[j];"),
     "transport_wrong_colbin": ("int32_t i = rowbin[a], j = colbin[px[a]];", "int32_t i = rowbin[a], j = colbin[a];"),
+    "ssp_skip_backward_bottleneck": ("if (X[(size_t)i * M + (size_t)j] < amt) amt = X[(size_t)i * M + (size_t)j];",
+                                     "if (0) amt = X[(size_t)i * M + (size_t)j];"),
+    "ssp_row_dual_sign": ("if (sr_done[i]) u[i] += D - dr[i];", "if (sr_done[i]) u[i] -= D - dr[i];"),
+    "ssp_end_without_demand": ("if (rd[bj] > 0) { end = bj; D = dc[bj]; break; }",
+                               "if (rd[bj] >= 0) { end = bj; D = dc[bj]; break; }"),
+    "ssp_no_backward_arcs": ("if (sr_done[i] || X[(size_t)i * M + (size_t)bj] == 0) continue;", "if (1) continue;"),
     "zero_mass_row_sign": ("int64_t s = (int64_t)C[(size_t)i * (size_t)m + (size_t)j] - vb[j];",
                            "int64_t s = (int64_t)C[(size_t)i * (size_t)m + (size_t)j] + vb[j];"),
 }
@@ -103,6 +109,29 @@ CHECK = textwrap.dedent(r"""
     red = C - U[:, None] - V[None, :]
     if any(red[i, cc > 0].min() != 0 for i in range(5) if r[i] == 0): sys.exit(3)
     if any(red[:, j].min() != 0 for j in range(6) if cc[j] == 0): sys.exit(3)
+    lib.oracle_transport_ssp.argtypes = lib.oracle_transport.argtypes
+    def ssp_ok(C, r, cc, want):
+        n, m = C.shape
+        X = np.empty((n, m), np.int32); U = np.empty(n, np.int64); V = np.empty(m, np.int64); cost = ctypes.c_int64(0)
+        if lib.oracle_transport_ssp(C, r, cc, n, m, X, U, V, ctypes.byref(cost)) != 0: return False
+        if cost.value != want or int((C.astype(np.int64) * X).sum()) != want: return False
+        if (X < 0).any() or (X.sum(1) != r).any() or (X.sum(0) != cc).any(): return False
+        if (U[:, None] + V[None, :] > C).any() or ((X > 0) & (U[:, None] + V[None, :] != C)).any(): return False
+        return int((r.astype(np.int64) * U).sum() + (cc.astype(np.int64) * V).sum()) == want
+    n = 9
+    C = np.abs(np.arange(n)[:, None] - np.arange(n)[None, :]).astype(np.int32)
+    r = np.array([30, 0, 11, 0, 25, 0, 4, 9, 0], np.int32); cc = np.array([0, 20, 0, 31, 0, 19, 0, 0, 9], np.int32)
+    if not ssp_ok(C, r, cc, int(np.abs(np.cumsum(r) - np.cumsum(cc))[:-1].sum())): sys.exit(3)
+    for trial in range(6):
+        n, m = 6, 7
+        C = rng.integers(0, 40, (n, m)).astype(np.int32)
+        r = rng.integers(0, 15, n).astype(np.int32); cc = rng.integers(0, 15, m).astype(np.int32)
+        r[0] += max(0, int(cc.sum() - r.sum())); cc[0] += max(0, int(r.sum() - cc.sum()))
+        A = np.zeros((n + m, n * m))
+        for i in range(n): A[i, i * m:(i + 1) * m] = 1
+        for j in range(m): A[n + j, j::m] = 1
+        lp = linprog(C.reshape(-1).astype(float), A_eq=A, b_eq=np.concatenate([r, cc]).astype(float), method="highs").fun
+        if not ssp_ok(C, r, cc, int(round(lp))): sys.exit(3)
     sys.exit(0)
 """)
 
