@@ -188,6 +188,27 @@ int ot_scale_for(const int32_t *C, int32_t n, double eps, int32_t *scale, int64_
 int ot_transport(const int32_t *C, const int32_t *r, const int32_t *c, int32_t n, int32_t m,
                  int32_t *X, int64_t *cost, int64_t *u, int64_t *v);
 
+/* Integer transport on the bins themselves (Eq. (1), Hitchcock-Koopmans
+ * case), without expanding units, so the total mass S = sum r may be as large
+ * as 2^31 - 1.  The primal-dual (Hungarian) method for transportation in the
+ * form of Batched KM (Section 2.3.1): trees grow at once from every supply bin
+ * with mass left over tight edges, a column bin is left through every row
+ * that already ships to it, a tree that reaches a demand bin with mass left
+ * ships the largest amount its path allows, and the duals move across the cut
+ * when no tree can grow.
+ *   C [n*m] int32 costs (ld = m); r [n], c [m] int32 masses >= 0 with equal
+ *   sums S, 1 <= S <= 2^31 - 1; n, m <= OT_MAX_BINS (one workgroup holds both
+ *   sides' state in LDS).
+ *   X [n*m] out: int32 optimal plan;  cost out: <C, X>.
+ *   u [n], v [m] out (may be NULL): optimal bin duals, zero-mass bins by the
+ *   convention of ot_transport.  stats (may be NULL): paths = augmentations.
+ * Errors: OT_EINVAL, OT_ENEGMASS, OT_EUNBALANCED, OT_ETOOBIG (a side above
+ * OT_MAX_BINS or S above 2^31 - 1), OT_ERANGE (max(C) - min(C) over the whole
+ * matrix > 2^31 - 1); outputs untouched on error. */
+#define OT_MAX_BINS 3072
+int ot_transport_bins(const int32_t *C, const int32_t *r, const int32_t *c, int32_t n, int32_t m,
+                      int32_t *X, int64_t *cost, int64_t *u, int64_t *v, ot_stats *stats);
+
 /* Many independent assignments in one persistent launch.
  *   C[k] [n[k]*n[k]], plan[k] [n[k]], u[k], v[k] [n[k]] (u, v arrays or their
  *   entries may be NULL); cost [count]; status [count] per-instance ot_status.
@@ -247,6 +268,15 @@ int ot_assign_batch_dev(int32_t count, int32_t max_n, const int32_t *dC, const i
 int ot_transpose_batch_dev(int32_t count, int32_t max_n, const int32_t *dC, const int64_t *coff,
                            const int32_t *n, int32_t *dCT, void *stream);
 
+/* Bin-level transport on device memory (see ot_transport_bins): dC [n*ld]
+ * (ld >= m), dr [n], dc [m], dX [n*m], dcost [1], du [n], dv [m]; dstats [1]
+ * may be NULL.  The masses are checked on the device (OT_ENEGMASS,
+ * OT_EUNBALANCED, OT_ETOOBIG and the cost range OT_ERANGE go to
+ * dstats->status; the outputs are then not written). */
+int ot_transport_bins_dev(const int32_t *dC, const int32_t *dr, const int32_t *dc, int32_t n, int32_t m,
+                          int32_t ld, int32_t *dX, int64_t *dcost, int64_t *du, int64_t *dv,
+                          ot_stats *dstats, void *stream);
+
 /* Integer transport on device memory (same semantics as ot_transport).
  * dC [n*m], dr [n], dc [m]; dX [n*m]; dcost [1]; du [n]; dv [m];
  * dstats [1] may be NULL.  S = sum r must be passed (the host knows it when
@@ -264,13 +294,17 @@ int ot_transport_dev(const int32_t *dC, const int32_t *dr, const int32_t *dc, in
  * (exact integer rounding, ties cannot occur) is built on the device, so only
  * the points cross PCIe.  A server thread admits queued requests in arrival
  * order while the device bytes of the admitted ones (4 n^2 + 64 n per
- * request) stay within hbm_budget_bytes and a slot is free, and launches the
- * newly admitted requests of each size class as one persistent batch on that
- * class's stream.  Each request completes on its own (the device releases a
- * completion flag per request), not when its whole batch does.
- * Requests that arrive while others run are admitted as memory and slots
- * free up, so their work overlaps on the device.  Results are identical to
- * a solve of the same request alone (the solver is deterministic). */
+ * request) stay within hbm_budget_bytes and a slot is free, builds their cost
+ * matrices, and publishes each into its size class's live queue (n <= 512,
+ * 2048, 4096: one, four and eight wavefronts per request).  Each class runs one
+ * persistent kernel whose workgroups take requests from that queue while the
+ * server keeps appending to it: a request that arrives while its class's
+ * kernel runs joins the running kernel as soon as a workgroup is free
+ * (counted in ot_serve_counters.joined), and the kernel starts again only if
+ * it left before taking every published request.  Each request completes on
+ * its own (the device releases a completion flag per request).  Results are
+ * identical to a solve of the same request alone (the solver is
+ * deterministic). */
 typedef struct ot_server ot_server;
 
 /* Device cost builder used by the server, exposed on its own:
@@ -281,9 +315,10 @@ int ot_grid_cost_dev(const int32_t *dsrc, const int32_t *ddst, int32_t n, int32_
 typedef struct ot_serve_cfg {
     int64_t hbm_budget_bytes;  /* device bytes admitted requests may hold; 0 = 8 GiB */
     int32_t max_inflight;      /* request slots (1..1024); 0 = 256; 1 = one request at a time */
-    int32_t streams;           /* streams per size class (n <= 128, 512, 2048, 4096), 1..8; 0 = 1.
-                                  Each stream runs one group of admitted requests at a time, so up
-                                  to this many groups of one class overlap on the device */
+    int32_t streams;           /* live queues per size class (n <= 512, 2048, 4096), 1..8; 0 = 1.
+                                  Each queue has its own kernel stream; a request goes to the
+                                  class's queue with the fewest outstanding requests.  More than
+                                  one share the device's hardware queues with each other */
     int32_t max_n;             /* largest n accepted (<= OT_MAX_N); 0 = OT_MAX_N */
     int32_t reserved[5];       /* must be zero */
 } ot_serve_cfg;
@@ -298,7 +333,10 @@ typedef struct ot_result {
 } ot_result;
 
 typedef struct ot_serve_counters {
-    int64_t submitted, admitted, completed, groups, peak_inflight_bytes, peak_inflight;
+    int64_t submitted, admitted, completed;
+    int64_t groups;                /* kernel launches (a class's kernel starts again only after it left) */
+    int64_t peak_inflight_bytes, peak_inflight;
+    int64_t joined;                /* requests published while their class's kernel ran and completed by it */
 } ot_serve_counters;
 
 /* Start a server on the current device.  Returns OT_OK and *out, or an error. */

@@ -13,7 +13,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libotkm.so")
-SOURCES = ["kernels.hip", "runtime.hip", "autotune.hip", "serve.hip"]
+SOURCES = ["solve_one_lo.hip", "solve_one_hi.hip", "solve_batch_lo.hip", "solve_batch_hi.hip", "solve_grid.hip",
+           "kernels.hip", "runtime.hip", "autotune.hip", "serve.hip", "bins.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
@@ -25,14 +26,14 @@ FLAGS = [
 ]
 
 
-def _obj(src: str) -> str:
-    return os.path.join(CSRC, "_build", os.path.splitext(src)[0] + ".o")
+def _obj(src: str, tag: str = "") -> str:
+    return os.path.join(CSRC, "_build" + tag, os.path.splitext(src)[0] + ".o")
 
 
-def _compile(src: str) -> str:
-    out = _obj(src)
+def _compile(src: str, extra=(), tag: str = "") -> str:
+    out = _obj(src, tag)
     os.makedirs(os.path.dirname(out), exist_ok=True)
-    cmd = [HIPCC, *FLAGS, "-c", os.path.join(CSRC, src), "-o", out]
+    cmd = [HIPCC, *FLAGS, *extra, "-c", os.path.join(CSRC, src), "-o", out]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)
@@ -40,21 +41,24 @@ def _compile(src: str) -> str:
     return out
 
 
-def build(verbose: bool = True) -> str:
-    """Compile every HIP source and link libotkm.so next to this file."""
+def build(verbose: bool = True, extra=(), out: str = LIB) -> str:
+    """Compile every HIP source and link libotkm.so next to this file (or, with
+    extra compiler flags, a variant of it at `out`)."""
     srcs = [s for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
-    with ThreadPoolExecutor(max_workers=min(4, len(srcs))) as ex:
-        objs = list(ex.map(_compile, srcs))
-    tmp = LIB + ".tmp%d" % os.getpid()
+    tag = "" if out == LIB else "_" + os.path.basename(out).replace(".", "_")
+    with ThreadPoolExecutor(max_workers=min(max(2, os.cpu_count() or 2), len(srcs))) as ex:
+        objs = list(ex.map(lambda src: _compile(src, extra, tag), srcs))
+    LIB_OUT = out
+    tmp = LIB_OUT + ".tmp%d" % os.getpid()
     cmd = [HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", *objs, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)
         raise RuntimeError("link of libotkm.so failed")
-    os.replace(tmp, LIB)
+    os.replace(tmp, LIB_OUT)
     if verbose:
-        print("built", LIB)
-    return LIB
+        print("built", LIB_OUT)
+    return LIB_OUT
 
 
 if __name__ == "__main__":

@@ -249,6 +249,10 @@ struct Engine {
   int gcap;
   // global scratch
   int32_t *auglist, *bend;
+  // buffer resource over C and the byte offset of every owned column (clamped
+  // to the last column) for the narrow sweep's loads
+  __amdgpu_buffer_rsrc_t crsrc;
+  int voff[CPT];
   // per-column registers
   uint64_t k1[CPT], k2[CPT];
   int t1[CPT], t2[CPT], ctree[CPT];
@@ -299,6 +303,114 @@ struct Engine {
   // list holds frontier records (row, tree and the low word of h, written when
   // the row joined, so no dependent LDS read of rtree / hrow is needed in the
   // narrow case); otherwise plain row ids.
+  // Narrow cost range: one chunk of up to UN rows, all of its loads in flight
+  // at once.  A row's record is the same for every lane, so the row, its tree
+  // and -h live in scalar registers: a cost row is a buffer load with the row
+  // offset in the scalar offset, and a reduced cost is one three-operand add,
+  // exact in 32-bit modular arithmetic because every key value is below 2^32
+  // here.  The chunk is reduced per column to its own top-2 (best, then best
+  // from another tree) on 32-bit values with the row and tree beside them
+  // (ties keep the earlier row), and merged once into the column's keys.
+  static constexpr int UN = CPT >= 8 ? 4 : (CPT >= 4 ? 8 : 16);
+  template <int S, bool REC>
+  __device__ __forceinline__ int sweep_chunk_narrow(const int32_t *list, int f, int cnt) {
+    constexpr int UN = S;
+    const int nv = min(UN, cnt - f);  // uniform
+    uint32_t id[UN], nh[UN];
+    int soff[UN];
+    bool live[UN];
+    int32_t c[UN][CPT];
+    int used = 0, first = -1;
+#pragma unroll
+    for (int q = 0; q < UN; ++q) {
+      live[q] = false; id[q] = 0; nh[q] = 0; soff[q] = 0;
+      if (q >= nv) continue;
+      int row, tr;
+      uint32_t h32;
+      if (REC) {
+        const int2 e = ((const int2 *)list)[f + q];
+        row = __builtin_amdgcn_readfirstlane(e.x & 0xffff);
+        tr = __builtin_amdgcn_readfirstlane(e.x >> 16);  // negative: the row's tree has gone
+        h32 = (uint32_t)__builtin_amdgcn_readfirstlane(e.y);
+      } else {
+        row = __builtin_amdgcn_readfirstlane(list[f + q]);
+        if ((unsigned)row >= (unsigned)rows()) row = 0;
+        tr = __builtin_amdgcn_readfirstlane(rtree[row]);
+        h32 = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)hrow[row]);
+      }
+      if ((unsigned)row >= (unsigned)rows()) { fail(OT_EINTERNAL); row = 0; tr = -1; }
+      live[q] = tr >= 0;
+      used += live[q];
+      if (live[q] && first < 0) first = q;
+      id[q] = ((uint32_t)row << 16) | (uint32_t)tr;  // rows are distinct: ids order as rows
+      nh[q] = 0u - h32;
+      soff[q] = row * ld * 4;
+    }
+    if (first < 0) return 0;  // every row of the chunk left the forest
+    // A slot without a live row repeats the first live one: a duplicate of a
+    // candidate changes neither the best nor the best from another tree, so
+    // the reduction below needs no per-slot predicate.
+#pragma unroll
+    for (int q = 0; q < UN; ++q) {
+      if (!live[q]) { id[q] = id[first]; nh[q] = nh[first]; soff[q] = soff[first]; }
+#pragma unroll
+      for (int k = 0; k < CPT; ++k)
+        c[q][k] = __builtin_amdgcn_raw_buffer_load_b32(crsrc, voff[k], __builtin_amdgcn_readfirstlane(soff[q]), 0);
+    }
+    uint32_t clr = 0;
+#pragma unroll
+    for (int k = 0; k < CPT; ++k) {
+      const uint32_t nvj = 0u - (uint32_t)vj[k];
+      uint32_t v[UN];
+      uint32_t b1 = ~0u, b2 = ~0u, i1 = ~0u, i2 = ~0u;
+#pragma unroll
+      for (int q = 0; q < UN; ++q) {
+        // (value, row) order, as the packed keys: the result does not depend on
+        // the order of the rows in the chunk, or on how a sweep is chunked
+        v[q] = (uint32_t)c[q][k] + nh[q] + nvj;
+        const bool lt = (v[q] < b1) | ((v[q] == b1) & (id[q] < i1));
+        b1 = lt ? v[q] : b1;
+        i1 = lt ? id[q] : i1;
+      }
+      const uint32_t ti1 = i1 & 0xffffu;
+#pragma unroll
+      for (int q = 0; q < UN; ++q) {
+        const bool ok = ((id[q] & 0xffffu) != ti1) & ((v[q] < b2) | ((v[q] == b2) & (id[q] < i2)));
+        b2 = ok ? v[q] : b2;
+        i2 = ok ? id[q] : i2;
+      }
+      // merge (b1, b2) into (k1, k2): the smaller best wins, and the second is
+      // the better of the loser's best (when it is from another tree) or its
+      // second, and the winner's second
+      const uint64_t c1 = b1 == ~0u ? kInf : (((uint64_t)b1 << kRowBits) | (i1 >> 16));
+      const uint64_t c2 = b2 == ~0u ? kInf : (((uint64_t)b2 << kRowBits) | (i2 >> 16));
+      const int tb1 = b1 == ~0u ? -1 : (int)(i1 & 0xffffu), tb2 = b2 == ~0u ? -1 : (int)(i2 & 0xffffu);
+      const bool sw = c1 < k1[k];
+      const uint64_t x1 = sw ? c1 : k1[k], x2 = sw ? c2 : k2[k];
+      const int tx1 = sw ? tb1 : t1[k], tx2 = sw ? tb2 : t2[k];
+      const uint64_t y1 = sw ? k1[k] : c1, y2 = sw ? k2[k] : c2;
+      const int ty1 = sw ? t1[k] : tb1, ty2 = sw ? t2[k] : tb2;
+      const bool d = ty1 != tx1;
+      const uint64_t cc = d ? y1 : y2;
+      const int tc = d ? ty1 : ty2;
+      const bool lt = cc < x2;
+      k1[k] = x1; t1[k] = tx1;
+      k2[k] = lt ? cc : x2; t2[k] = lt ? tc : tx2;
+      clr |= sw ? (1u << k) : 0u;  // best key now from a live tree
+    }
+    stl &= ~clr;
+    return used;
+  }
+
+  // The last rows of a sweep go in the smallest chunk that holds them.
+  template <int S, bool REC>
+  __device__ __forceinline__ int sweep_narrow_tail(const int32_t *list, int f, int cnt) {
+    if constexpr (S > 1) {
+      if (cnt - f <= S / 2) return sweep_narrow_tail<S / 2, REC>(list, f, cnt);
+    }
+    return sweep_chunk_narrow<S, REC>(list, f, cnt);
+  }
+
   template <bool NARROW, int UU, bool REC>
   __device__ __forceinline__ int sweep_chunk(const int32_t *list, int f, int cnt) {
     int used = 0;
@@ -431,6 +543,14 @@ struct Engine {
   __device__ __forceinline__ int sweep_t(const int32_t *list, int cnt) {
     int used = 0;
     int f = 0;
+#ifndef OTKM_SWEEP32
+#define OTKM_SWEEP32 0
+#endif
+    if constexpr (NARROW && OTKM_SWEEP32) {
+      for (; f + UN <= cnt; f += UN) used += sweep_chunk_narrow<UN, REC>(list, f, cnt);
+      if (f < cnt) used += sweep_narrow_tail<UN, REC>(list, f, cnt);
+      return used;
+    }
     if (LONG)
       for (; f + UB <= cnt; f += UB) used += sweep_chunk<NARROW, UB, REC>(list, f, cnt);
     for (; f < cnt; f += U) used += sweep_chunk<NARROW, U, REC>(list, f, cnt);
@@ -694,6 +814,13 @@ struct Engine {
     ldt = (RECT && P.ldt > 0) ? P.ldt : nr;
     const bool colred = nr == n;  // column reduction: square problems only
     tid = threadIdx.x; lane = tid & 63; wid = tid >> 6;
+    {
+      // the row offset goes in the (unchecked) scalar offset and the clamped
+      // column in the checked vector offset, so the extent only bounds columns
+      const int64_t extent = ((int64_t)(nr - 1) * ld + n) * 4;
+      crsrc = __builtin_amdgcn_make_buffer_rsrc((void *)C, (short)0, (int)(extent < 0x7fffffff ? extent : 0x7fffffff),
+                                                0x00020000);
+    }
     err_local = 0;
     const LdsLayout L = lds_layout(n);
     hrow = (int64_t *)(smem + L.hrow);
@@ -720,6 +847,8 @@ struct Engine {
     } else {
       auglist = P.ws;
     }
+#pragma unroll
+    for (int k = 0; k < CPT; ++k) voff[k] = lcol(k) * 4;
     bend = auglist + n;
 
     const int K = (P.max_paths <= 0 || P.max_paths > nr) ? nr : P.max_paths;

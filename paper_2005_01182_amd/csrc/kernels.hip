@@ -1,7 +1,7 @@
 // kernels.hip -- gfx950 kernels around the batched-KM engine and their launchers.
 //
-//   k_assign_one      one instance, one workgroup (the whole solve on chip)
-//   k_assign_batch    persistent workgroups pull instances from a device queue
+// The engine's own kernels live in solve_kernels.hpp (instantiated by the
+// solve_*.hip files); this file dispatches to them and holds the rest:
 //   k_fill_i32        queue/flag reset (a kernel, so launches stay graph-capturable)
 //   k_tr_prep         transport: check masses, unit -> bin maps (Eq. (1), r/c integer)
 //   k_tr_expand       transport: S x S unit cost matrix
@@ -14,95 +14,6 @@
 #include "launch.hpp"
 
 namespace otkm {
-
-// ---------------------------------------------------------------------------
-// single instance
-// ---------------------------------------------------------------------------
-template <int BLOCK, int CPT>
-__global__ __launch_bounds__(BLOCK) void k_assign_one(Problem P, const int32_t *gate) {
-  extern __shared__ __align__(16) char smem[];
-  if (gate && *gate != 0) return;  // an earlier stage of this pipeline already failed
-  Engine<BLOCK, CPT, (BLOCK <= 512), false, true> E;  // at 1024 threads the registers are too few for LONG
-  E.run(P, smem);
-}
-
-// ---------------------------------------------------------------------------
-// one instance over gridDim.x workgroups (P.grid_ws header zeroed before the
-// launch; the grid is at most kMaxWgs workgroups, one per CU, so all of them
-// are resident at once)
-// ---------------------------------------------------------------------------
-template <int BLOCK, int CPT>
-__global__ __launch_bounds__(BLOCK) void k_assign_grid(Problem P) {
-  extern __shared__ __align__(16) char smem[];
-  Engine<BLOCK, CPT, true, true, true> E;
-  E.run(P, smem);
-}
-
-__global__ void k_fill_u64(uint64_t *p, uint64_t value, int64_t count) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
-    p[i] = value;
-}
-
-// ---------------------------------------------------------------------------
-// persistent batch: each workgroup pops instance indices until the queue is empty
-// ---------------------------------------------------------------------------
-// Two wavefronts per SIMD: the register budget drops to 256 (a few bytes of
-// spill at 8 columns per lane) and twice as many instances share each CU, which
-// measured 126k -> 181k solves/s on the embedding batch; three or four per SIMD
-// spill heavily and lose.
-template <int BLOCK, int CPT>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2))) void k_assign_batch(BatchArgs A) {
-  extern __shared__ __align__(16) char smem[];
-  __shared__ int s_idx;
-  int32_t *ws = A.ws + (size_t)blockIdx.x * ws_ints(A.max_n);
-  for (;;) {
-    if (threadIdx.x == 0) s_idx = atomicAdd(A.head, 1);
-    __syncthreads();
-    const int idx = s_idx;
-    __syncthreads();
-    if (idx >= A.nq) break;  // every workgroup reaches this exit once the queue drains
-    const int k = A.order ? A.order[idx] : idx;
-    if ((unsigned)k >= (unsigned)A.count) continue;  // no such instance: nothing to report or flag
-    const int n = A.n[k];
-    if (n < 1 || n > A.max_n || n > BLOCK * CPT) {
-      if (threadIdx.x == 0) {
-        if (A.stats) { ot_stats s = {}; s.status = OT_EINVAL; A.stats[k] = s; }
-        if (A.done) {
-          __threadfence_system();
-          __hip_atomic_store(&A.done[k], A.tag, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
-        }
-      }
-      continue;
-    }
-    Problem P;
-    P.C = A.C + A.coff[k];
-    P.n = n;
-    P.ld = n;
-    P.CT = A.CT ? A.CT + A.coff[k] : nullptr;
-    P.Cout = nullptr;
-    P.ldo = n;
-    P.dscale = 1;
-    P.init_u = nullptr; P.init_b = nullptr; P.init_rmax = nullptr;
-    P.max_paths = A.max_paths;
-    P.flags = 0;
-    P.plan = A.plan + A.voff[k];
-    P.cost = A.cost + k;
-    P.u = A.u ? A.u + A.voff[k] : nullptr;
-    P.v = A.v ? A.v + A.voff[k] : nullptr;
-    P.stats = A.stats ? A.stats + k : nullptr;
-    P.ws = ws;
-    Engine<BLOCK, CPT> E;
-    E.run(P, smem);
-    if (A.done) {
-      // outputs may live in host memory: make every thread's writes visible
-      // system-wide before the completion flag is released
-      __threadfence_system();
-      __syncthreads();
-      if (threadIdx.x == 0) __hip_atomic_store(&A.done[k], A.tag, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
-    }
-    __syncthreads();
-  }
-}
 
 // ---------------------------------------------------------------------------
 // grid-wide initial sweeps of one instance (the two full passes over C that the
@@ -484,100 +395,25 @@ __global__ void k_grid_cost(const int32_t *ps, const int32_t *pt, int n, int32_t
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-template <typename K>
-static hipError_t allow_lds(K kernel, size_t bytes) {
-  return hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-}
-
-template <int B, int CPT>
-static hipError_t one(const Problem &P, const int32_t *gate, hipStream_t s) {
-  const size_t lds = lds_layout(P.n).total;
-  hipError_t e = allow_lds(k_assign_one<B, CPT>, lds);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_assign_one<B, CPT>), dim3(1), dim3(B), lds, s, P, gate);
-  return hipGetLastError();
-}
-
-template <int B, int CPT>
-static hipError_t grid(const Problem &P, int wgs, hipStream_t s) {
-  const size_t lds = lds_layout(P.n).total;
-  hipError_t e = allow_lds(k_assign_grid<B, CPT>, lds);
-  if (e != hipSuccess) return e;
-  // every tag word must start below the first level
-  hipLaunchKernelGGL(k_fill_u64, dim3(16), dim3(256), 0, s, P.grid_ws, (uint64_t)0,
-                     (int64_t)grid_ws_u64(wgs, B * CPT));
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL((k_assign_grid<B, CPT>), dim3(wgs), dim3(B), lds, s, P);
-  return hipGetLastError();
-}
-
 int cpt_for(int n, int block) {
   const int need = (n + block - 1) / block;
   return need <= 1 ? 1 : need <= 2 ? 2 : need <= 4 ? 4 : need <= 8 ? 8 : 0;
 }
 
-// One instance over `wgs` workgroups of `block` threads: P.ws holds wgs *
-// ws_ints(n) ints and P.grid_ws grid_ws_u64(wgs, block * cpt) words.
-hipError_t launch_assign_grid(const Problem &P, int block, int wgs, hipStream_t s) {
-  if (wgs < 2 || wgs > kMaxWgs || !P.grid_ws) return hipErrorInvalidValue;
-  const int cpt = cpt_for(P.n, block * wgs);
-#define OTKM_GRID(B, K) if (block == B && cpt == K) return grid<B, K>(P, wgs, s);
-  OTKM_GRID(256, 1) OTKM_GRID(256, 2) OTKM_GRID(256, 4)
-  OTKM_GRID(512, 1) OTKM_GRID(512, 2) OTKM_GRID(512, 4)
-#undef OTKM_GRID
-  return hipErrorInvalidValue;
-}
-
 hipError_t launch_assign_one(const Problem &P, int block, const int32_t *gate, hipStream_t s) {
   const int cpt = cpt_for(P.n, block);
-#define OTKM_ONE(B, K) if (block == B && cpt == K) return one<B, K>(P, gate, s);
-  OTKM_ONE(64, 1) OTKM_ONE(64, 2) OTKM_ONE(64, 4) OTKM_ONE(64, 8)
-  OTKM_ONE(256, 1) OTKM_ONE(256, 2) OTKM_ONE(256, 4) OTKM_ONE(256, 8)
-  OTKM_ONE(512, 1) OTKM_ONE(512, 2) OTKM_ONE(512, 4) OTKM_ONE(512, 8)
-  OTKM_ONE(1024, 1) OTKM_ONE(1024, 2) OTKM_ONE(1024, 4)
-#undef OTKM_ONE
-  return hipErrorInvalidValue;
-}
-
-template <int B, int CPT>
-static hipError_t batch(const BatchArgs &A, int grid, hipStream_t s) {
-  const size_t lds = lds_layout(A.max_n).total;
-  hipError_t e = allow_lds(k_assign_batch<B, CPT>, lds);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_assign_batch<B, CPT>), dim3(grid), dim3(B), lds, s, A);
-  return hipGetLastError();
-}
-
-template <int B, int CPT>
-static int occ(int max_n) {
-  int blocks = 0;
-  const size_t lds = lds_layout(max_n).total;
-  if (allow_lds(k_assign_batch<B, CPT>, lds) != hipSuccess) return 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, (const void *)k_assign_batch<B, CPT>, B, lds) != hipSuccess)
-    return 0;
-  return blocks;
+  return block <= 256 ? launch_assign_one_lo(P, block, cpt, gate, s) : launch_assign_one_hi(P, block, cpt, gate, s);
 }
 
 int batch_occupancy(int block, int max_n) {
   const int cpt = cpt_for(max_n, block);
-#define OTKM_OCC(B, K) if (block == B && cpt == K) return occ<B, K>(max_n);
-  OTKM_OCC(64, 1) OTKM_OCC(64, 2) OTKM_OCC(64, 4) OTKM_OCC(64, 8)
-  OTKM_OCC(256, 1) OTKM_OCC(256, 2) OTKM_OCC(256, 4) OTKM_OCC(256, 8)
-  OTKM_OCC(512, 1) OTKM_OCC(512, 2) OTKM_OCC(512, 4) OTKM_OCC(512, 8)
-  OTKM_OCC(1024, 1) OTKM_OCC(1024, 2) OTKM_OCC(1024, 4)
-#undef OTKM_OCC
-  return 0;
+  const int o = block <= 256 ? batch_occupancy_lo(block, cpt, max_n) : batch_occupancy_hi(block, cpt, max_n);
+  return o < 0 ? 0 : o;
 }
 
 hipError_t launch_assign_batch(const BatchArgs &A, int block, int grid, hipStream_t s) {
   const int cpt = cpt_for(A.max_n, block);
-#define OTKM_BATCH(B, K) if (block == B && cpt == K) return batch<B, K>(A, grid, s);
-  OTKM_BATCH(64, 1) OTKM_BATCH(64, 2) OTKM_BATCH(64, 4) OTKM_BATCH(64, 8)
-  OTKM_BATCH(256, 1) OTKM_BATCH(256, 2) OTKM_BATCH(256, 4) OTKM_BATCH(256, 8)
-  OTKM_BATCH(512, 1) OTKM_BATCH(512, 2) OTKM_BATCH(512, 4) OTKM_BATCH(512, 8)
-  OTKM_BATCH(1024, 1) OTKM_BATCH(1024, 2) OTKM_BATCH(1024, 4)
-#undef OTKM_BATCH
-  return hipErrorInvalidValue;
+  return block <= 256 ? launch_assign_batch_lo(A, block, cpt, grid, s) : launch_assign_batch_hi(A, block, cpt, grid, s);
 }
 
 hipError_t launch_fill_i32(int32_t *p, int32_t value, int64_t count, hipStream_t s) {

@@ -25,6 +25,14 @@ struct BatchArgs {
   int32_t *head;          // queue head (reset to 0 before the launch)
   int32_t *done;          // [count] or null: done[k] = tag once instance k's outputs are visible to the host
   int32_t tag;
+  // Live queue (serving): with live_tail set, order is a ring of qcap entries
+  // the host fills while the kernel runs (entry p at order[p % qcap], published
+  // once *live_tail > p, host memory), head is the first entry not yet taken
+  // (set before the launch), nq is unused, and done[k] = p + 1 for entry p.
+  const int32_t *live_tail = nullptr;
+  const int32_t *live_stop = nullptr;  // host flag: leave when the queue is empty
+  int32_t qcap = 0;
+  int32_t linger = 0;                  // empty polls (a few microseconds each) before a workgroup leaves
 };
 
 struct TransportArgs {
@@ -42,6 +50,13 @@ struct TransportArgs {
 };
 
 int cpt_for(int n, int block);
+// per-file dispatchers of the engine's instantiations (solve_*.hip)
+hipError_t launch_assign_one_lo(const Problem &P, int block, int cpt, const int32_t *gate, hipStream_t s);
+hipError_t launch_assign_one_hi(const Problem &P, int block, int cpt, const int32_t *gate, hipStream_t s);
+hipError_t launch_assign_batch_lo(const BatchArgs &A, int block, int cpt, int grid, hipStream_t s);
+hipError_t launch_assign_batch_hi(const BatchArgs &A, int block, int cpt, int grid, hipStream_t s);
+int batch_occupancy_lo(int block, int cpt, int max_n);
+int batch_occupancy_hi(int block, int cpt, int max_n);
 int batch_occupancy(int block, int max_n);
 hipError_t launch_assign_one(const Problem &P, int block, const int32_t *gate, hipStream_t s);
 hipError_t launch_assign_grid(const Problem &P, int block, int wgs, hipStream_t s);

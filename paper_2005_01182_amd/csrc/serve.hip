@@ -1,21 +1,27 @@
 // serve.hip -- continuous-batching request server (C-ABI in otkm.h).
 //
 // Requests (n source and n target grid points) queue on the host.  A server
-// thread admits them as request slots and device bytes free up, builds each
-// request's cost matrix on the device from its points, and launches every
-// newly admitted group as one persistent batch kernel.  Each size class has
-// its own stream, so a group of large requests never holds back small ones,
-// and groups launched while others run overlap on the device.  The engine
+// thread admits them in arrival order as request slots and device bytes free
+// up, builds each admitted request's cost matrix on the device from its
+// points (on one build stream), and publishes it into its size class's live
+// queue: a ring of request slots in host memory plus a tail counter the
+// device reads.  Each class runs one persistent batch kernel at a time; its
+// workgroups take entries from the queue while the host keeps appending, so a
+// request that arrives while its class's kernel runs joins that kernel as
+// soon as a workgroup is free, and workgroups that find the queue empty wait
+// a short, bounded while before they leave.  When the kernel has left with
+// entries still unclaimed (they arrived after its last workgroup looked), the
+// server launches it again from the first unclaimed entry.  The engine
 // writes each request's plan and duals straight into pinned host memory and
-// then releases a per-request completion flag, so a request completes as soon
-// as its own solve does, not when its whole group does.
+// then releases a per-request completion flag, so a request completes as
+// soon as its own solve does.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
 #include <deque>
-#include <map>
 #include <memory>
 #include <mutex>
 #include <thread>
@@ -31,16 +37,17 @@ using namespace otkm;
 
 namespace {
 
-constexpr int kClasses = 4;
+constexpr int kClasses = 3;
 constexpr int kMaxLanesPerClass = 8;
-// One stream per class by default: on the serving workload (Poisson 2000/s,
-// n log-uniform in [32, 4096]) four streams per class halved the throughput
-// (1493 -> 752 solves/s): concurrent persistent kernels of one class split the
-// chip instead of draining one queue longest-first.
 constexpr int kDefaultLanesPerClass = 1;
-// size classes: (largest n, workgroup width)
-constexpr int kClassMaxN[kClasses] = {128, 512, 2048, OT_MAX_N};
-constexpr int kClassBlock[kClasses] = {64, 64, 256, 512};
+// size classes: (largest n, workgroup width).  Three kernel streams and one
+// build stream: the four hardware queues a process gets by default, so no
+// stream waits behind another's long kernel.
+constexpr int kClassMaxN[kClasses] = {512, 2048, OT_MAX_N};
+constexpr int kClassBlock[kClasses] = {64, 256, 512};
+// Empty-queue polls before a workgroup leaves: each is a read of the tail in
+// host memory and a short sleep, a few microseconds together.
+constexpr int kLinger = 24;
 
 int class_of(int n) {
   for (int c = 0; c < kClasses; ++c)
@@ -52,46 +59,56 @@ int64_t request_bytes(int n) { return 4ll * n * n + 64ll * n; }
 
 struct Req {
   uint64_t id = 0;
-  int32_t n = 0, cls = 0, slot = -1, pos = -1, status = 0;
+  int32_t n = 0, cls = 0, slot = -1, status = 0;
+  int lane = -1;
+  int32_t pos = -1;       // position in the lane's queue (the completion tag is pos + 1)
+  int64_t launch = -1;    // the lane's launch that was running when the request was published, or -1
   int64_t off = -1, abytes = 0, bytes = 0, cost = 0;  // arena offset and size of C; admitted bytes
   double t_submit = 0, t_admit = 0, t_done = 0;
   bool done = false;
-  int stream = -1;
-  uint32_t tag = 0;
   std::vector<int32_t> pts;  // src (2n) then dst (2n)
   std::vector<int32_t> plan;
   std::vector<int64_t> u, v;
 };
 
-struct Lane {  // one stream; each size class has cfg.streams of them
-  hipStream_t s = nullptr;
+struct Build {  // requests of one lane whose cost matrices were queued on the build stream together
   hipEvent_t ev = nullptr;
-  bool busy = false;
-  uint32_t tag = 0;
-  std::vector<Req *> group;  // requests admitted for the next launch (cleared once launched)
-  int outstanding = 0;       // requests of the launched group not yet retired
-  // descriptors of the group in flight (device and pinned staging)
-  int64_t *d_coff = nullptr, *d_voff = nullptr, *h_coff = nullptr, *h_voff = nullptr;
-  int32_t *d_n = nullptr, *d_order = nullptr, *h_n = nullptr, *h_order = nullptr;
+  std::vector<Req *> reqs;
+};
+
+struct Lane {  // one size class's queue and kernel stream
+  int cls = 0, max_n = 1, block = 64, grid_max = 1;
+  hipStream_t s = nullptr;
+  hipEvent_t ev = nullptr;  // the running kernel's completion
+  bool running = false;
+  int64_t launches = 0;
+  int32_t tail = 0;     // entries published (host copy of *h_tail)
+  int32_t base = 0;     // first entry the next launch starts from
+  int outstanding = 0;  // admitted requests of this lane not yet retired
+  int32_t *h_tail = nullptr;           // mapped: published entries, read by the device
+  int32_t *h_ring = nullptr;           // mapped: entry p -> request slot, at p % qcap
   int32_t *d_head = nullptr, *d_ws = nullptr;
-  // per-position results written by the device into pinned memory
-  int64_t *h_cost = nullptr;
-  ot_stats *h_stats = nullptr;
-  int32_t *h_done = nullptr;
+  std::deque<Build> building;
 };
 
 }  // namespace
 
 struct ot_server {
   ot_serve_cfg cfg{};
-  int maxn = OT_MAX_N, slots = 256, cus = 1, dev = 0;
+  int maxn = OT_MAX_N, slots = 256, cus = 1, dev = 0, qcap = 512;
   char *arena_base = nullptr;
   std::unique_ptr<otkm::Arena> arena;
+  hipStream_t sb = nullptr;                   // builds every admitted request's cost matrix
   int32_t *d_pts = nullptr;                   // [slots][4 maxn]
   int32_t *h_pts = nullptr;                   // pinned staging [slots][4 maxn]
-  int32_t *h_plan = nullptr;                  // pinned [slots][maxn]
-  int64_t *h_u = nullptr, *h_v = nullptr;     // pinned [slots][maxn]
+  int32_t *h_plan = nullptr;                  // mapped [slots][maxn]
+  int64_t *h_u = nullptr, *h_v = nullptr;     // mapped [slots][maxn]
+  // mapped per request slot: descriptor (read by the device) and results
+  int64_t *h_coff = nullptr, *h_voff = nullptr, *h_cost = nullptr;
+  int32_t *h_n = nullptr, *h_done = nullptr, *h_stop = nullptr;
+  ot_stats *h_stats = nullptr;
   std::vector<int> free_slots;
+  std::vector<hipEvent_t> free_events;
   Lane lanes[kClasses * kMaxLanesPerClass];  // lane c * lpc + l: class c, stream l
   int lpc = kDefaultLanesPerClass;
   int nlanes() const { return kClasses * lpc; }
@@ -99,7 +116,7 @@ struct ot_server {
   std::condition_variable cv_work, cv_done;
   std::deque<Req *> pending;
   std::unordered_map<uint64_t, std::unique_ptr<Req>> reqs;
-  std::vector<Req *> running;
+  std::vector<Req *> running;  // published requests not yet complete
   uint64_t next_id = 1;
   int64_t inflight_bytes = 0;
   int inflight = 0;
@@ -119,101 +136,79 @@ namespace {
 void free_server(ot_server *s) {
   for (auto &L : s->lanes) {
     if (L.s) hipStreamSynchronize(L.s);
+    if (s->sb) hipStreamSynchronize(s->sb);
+    for (auto &b : L.building) hipEventDestroy(b.ev);
     if (L.ev) hipEventDestroy(L.ev);
     if (L.s) hipStreamDestroy(L.s);
-    hipFree(L.d_coff); hipFree(L.d_voff); hipFree(L.d_n); hipFree(L.d_order); hipFree(L.d_head); hipFree(L.d_ws);
-    hipHostFree(L.h_coff); hipHostFree(L.h_voff); hipHostFree(L.h_n); hipHostFree(L.h_order);
-    hipHostFree(L.h_cost); hipHostFree(L.h_stats); hipHostFree(L.h_done);
+    hipFree(L.d_head); hipFree(L.d_ws);
+    hipHostFree(L.h_tail); hipHostFree(L.h_ring);
   }
+  for (hipEvent_t e : s->free_events) hipEventDestroy(e);
+  if (s->sb) hipStreamDestroy(s->sb);
   hipFree(s->arena_base);
   hipFree(s->d_pts);
   hipHostFree(s->h_pts);
   hipHostFree(s->h_plan);
   hipHostFree(s->h_u);
   hipHostFree(s->h_v);
+  hipHostFree(s->h_coff); hipHostFree(s->h_voff); hipHostFree(s->h_cost);
+  hipHostFree(s->h_n); hipHostFree(s->h_done); hipHostFree(s->h_stop); hipHostFree(s->h_stats);
   delete s;
 }
 
 template <typename T>
-T *dptr(T *host) {  // device address of pinned host memory
+T *dptr(T *host) {  // device address of mapped host memory
   void *d = nullptr;
   if (hipHostGetDevicePointer(&d, host, 0) != hipSuccess) return nullptr;
   return (T *)d;
 }
 
-// Launch the group collected in lane li.  Requires s->mu.
-int launch_group(ot_server *s, int li) {
+// (Re)start lane li's kernel from entry L.base.  Requires s->mu.
+int launch_lane(ot_server *s, int li) {
   Lane &L = s->lanes[li];
-  const int c = li / s->lpc;
-  const int G = (int)L.group.size();
-  const size_t M = (size_t)s->maxn;
   hipError_t e;
-  int max_n = 1;
-  for (int k = 0; k < G; ++k) {
-    Req *r = L.group[k];
-    r->pos = k;
-    r->stream = li;
-    r->tag = L.tag;
-    max_n = std::max(max_n, r->n);
-    int32_t *hp = s->h_pts + (size_t)r->slot * 4 * M;
-    std::memcpy(hp, r->pts.data(), sizeof(int32_t) * 4 * (size_t)r->n);
-    int32_t *dp = s->d_pts + (size_t)r->slot * 4 * M;
-    if ((e = hipMemcpyAsync(dp, hp, sizeof(int32_t) * 4 * (size_t)r->n, hipMemcpyHostToDevice, L.s)) != hipSuccess)
-      return map_hip(e);
-    int32_t *Cr = (int32_t *)(s->arena_base + r->off);
-    if ((e = launch_grid_cost(dp, dp + 2 * r->n, r->n, Cr, L.s)) != hipSuccess) return map_hip(e);
-    L.h_coff[k] = r->off / 4;
-    L.h_voff[k] = (int64_t)r->slot * (int64_t)M;
-    L.h_n[k] = r->n;
-    L.h_order[k] = k;
-    L.h_done[k] = 0;
-  }
-  // longest first inside the group
-  std::stable_sort(L.h_order, L.h_order + G, [&](int a, int b) { return L.h_n[a] > L.h_n[b]; });
-  if ((e = hipMemcpyAsync(L.d_coff, L.h_coff, 8 * (size_t)G, hipMemcpyHostToDevice, L.s)) != hipSuccess) return map_hip(e);
-  if ((e = hipMemcpyAsync(L.d_voff, L.h_voff, 8 * (size_t)G, hipMemcpyHostToDevice, L.s)) != hipSuccess) return map_hip(e);
-  if ((e = hipMemcpyAsync(L.d_n, L.h_n, 4 * (size_t)G, hipMemcpyHostToDevice, L.s)) != hipSuccess) return map_hip(e);
-  if ((e = hipMemcpyAsync(L.d_order, L.h_order, 4 * (size_t)G, hipMemcpyHostToDevice, L.s)) != hipSuccess) return map_hip(e);
-  if ((e = launch_fill_i32(L.d_head, 0, 1, L.s)) != hipSuccess) return map_hip(e);
-  const int block = kClassBlock[c];
-  const int occ = batch_occupancy(block, max_n);
-  if (occ <= 0) return OT_ETOOBIG;
-  const int grid = std::max(1, std::min(G, occ * s->cus));
+  if ((e = launch_fill_i32(L.d_head, L.base, 1, L.s)) != hipSuccess) return map_hip(e);
+  const int waiting = L.tail - L.base;
+  // room for the waiting entries and as many again for requests that arrive meanwhile
+  const int grid = std::max(1, std::min(L.grid_max, std::max(8, 2 * waiting)));
   BatchArgs A;
   A.C = (const int32_t *)s->arena_base;
-  A.coff = L.d_coff; A.n = L.d_n; A.voff = L.d_voff; A.order = L.d_order;
-  A.count = G; A.nq = G; A.max_n = max_n; A.max_paths = 0;
-  A.plan = dptr(s->h_plan); A.cost = dptr(L.h_cost); A.u = dptr(s->h_u); A.v = dptr(s->h_v);
-  A.stats = dptr(L.h_stats); A.ws = L.d_ws; A.head = L.d_head; A.done = dptr(L.h_done); A.tag = (int32_t)L.tag;
-  if (!A.plan || !A.cost || !A.u || !A.v || !A.stats || !A.done) return OT_EDEVICE;
-  if ((e = launch_assign_batch(A, block, grid, L.s)) != hipSuccess) return map_hip(e);
+  A.coff = dptr(s->h_coff); A.n = dptr(s->h_n); A.voff = dptr(s->h_voff); A.order = dptr(L.h_ring);
+  A.count = s->slots; A.nq = 0; A.max_n = L.max_n; A.max_paths = 0;
+  A.plan = dptr(s->h_plan); A.cost = dptr(s->h_cost); A.u = dptr(s->h_u); A.v = dptr(s->h_v);
+  A.stats = dptr(s->h_stats); A.ws = L.d_ws; A.head = L.d_head; A.done = dptr(s->h_done); A.tag = 0;
+  A.live_tail = dptr(L.h_tail); A.live_stop = dptr(s->h_stop); A.qcap = s->qcap; A.linger = kLinger;
+  if (!A.coff || !A.n || !A.voff || !A.order || !A.plan || !A.cost || !A.u || !A.v || !A.stats || !A.done ||
+      !A.live_tail || !A.live_stop)
+    return OT_EDEVICE;
+  if ((e = launch_assign_batch(A, L.block, grid, L.s)) != hipSuccess) return map_hip(e);
   if ((e = hipEventRecord(L.ev, L.s)) != hipSuccess) return map_hip(e);
-  L.busy = true;
-  // A retired request may be handed back and freed by ot_serve_poll before this
-  // lane's event completes, so the lane keeps a count, never the pointers.
-  L.outstanding = G;
-  L.group.clear();
+  L.running = true;
+  ++L.launches;
   ++s->ctr.groups;
   return OT_OK;
 }
 
-// Retire finished requests; returns true when anything changed.  Requires s->mu.
+// Retire finished requests and finished kernels.  Returns true when anything
+// changed.  Requires s->mu.
 bool retire(ot_server *s) {
   bool changed = false;
   const size_t M = (size_t)s->maxn;
   for (size_t i = 0; i < s->running.size();) {
     Req *r = s->running[i];
-    Lane &L = s->lanes[r->stream];
-    const int32_t flag = __atomic_load_n(&L.h_done[r->pos], __ATOMIC_ACQUIRE);
-    if (flag != (int32_t)r->tag) { ++i; continue; }
-    const ot_stats st = L.h_stats[r->pos];
+    const int32_t flag = __atomic_load_n(&s->h_done[r->slot], __ATOMIC_ACQUIRE);
+    if (flag != r->pos + 1) { ++i; continue; }
+    Lane &L = s->lanes[r->lane];
+    const ot_stats st = s->h_stats[r->slot];
     r->status = (int32_t)st.status;
-    r->cost = L.h_cost[r->pos];
+    r->cost = s->h_cost[r->slot];
     if (r->status == 0) {
       r->plan.assign(s->h_plan + (size_t)r->slot * M, s->h_plan + (size_t)r->slot * M + r->n);
       r->u.assign(s->h_u + (size_t)r->slot * M, s->h_u + (size_t)r->slot * M + r->n);
       r->v.assign(s->h_v + (size_t)r->slot * M, s->h_v + (size_t)r->slot * M + r->n);
     }
+    // published while the lane's kernel ran, and completed by that same kernel
+    if (r->launch >= 0 && r->launch == L.launches && L.running) ++s->ctr.joined;
     r->t_done = s->now();
     r->done = true;
     --L.outstanding;
@@ -228,64 +223,133 @@ bool retire(ot_server *s) {
   }
   for (int li = 0; li < s->nlanes(); ++li) {
     Lane &L = s->lanes[li];
-    if (!L.busy) continue;
+    if (!L.running) continue;
     const hipError_t q = hipEventQuery(L.ev);
     if (q == hipErrorNotReady) continue;
     if (q != hipSuccess) {
-      // the group's kernel failed: its flags will never arrive, so every waiter
-      // is woken with the error instead of waiting forever
+      // the kernel failed: its flags will never arrive, so every waiter is
+      // woken with the error instead of waiting forever
       if (s->fatal == 0) s->fatal = map_hip(q);
       changed = true;
       continue;
     }
-    if (L.outstanding > 0) continue;  // the flags of a finished kernel are visible on the next pass
-    L.busy = false;
+    L.running = false;
     changed = true;
+    // the kernel took a prefix of the published entries and completed each
+    // one it took: the next launch starts after the last completed one
+    while (L.base < L.tail) {
+      const int32_t sl = L.h_ring[L.base % s->qcap];
+      if (__atomic_load_n(&s->h_done[sl], __ATOMIC_ACQUIRE) != L.base + 1) break;
+      ++L.base;
+    }
   }
   return changed;
 }
 
-// Admit queued requests into free lanes and launch them.  Requires s->mu.
+// Admit queued requests (arrival order, within the budget and the slots) and
+// queue their cost matrices on the build stream.  Requires s->mu.
 bool admit(ot_server *s) {
   bool any = false;
-  // this round's target lane of each class: its first idle stream, if any
-  int target[kClasses];
-  for (int c = 0; c < kClasses; ++c) {
-    target[c] = -1;
-    for (int l = 0; l < s->lpc && target[c] < 0; ++l)
-      if (!s->lanes[c * s->lpc + l].busy) target[c] = c * s->lpc + l;
-  }
+  const size_t M = (size_t)s->maxn;
+  std::vector<Req *> batch[kClasses * kMaxLanesPerClass];
   int scanned = 0;
   for (auto it = s->pending.begin(); it != s->pending.end() && scanned < 4096; ++scanned) {
     Req *r = *it;
-    if (target[r->cls] < 0) { ++it; continue; }
     if (s->free_slots.empty() || s->inflight >= s->cfg.max_inflight) break;
     if (s->inflight_bytes + r->bytes > s->cfg.hbm_budget_bytes) { ++it; continue; }
     const int64_t abytes = 4ll * r->n * r->n;
     const int64_t off = s->arena->alloc(abytes);
     if (off < 0) { ++it; continue; }
+    // the class's lane with the fewest outstanding requests
+    int li = r->cls * s->lpc;
+    for (int l = 1; l < s->lpc; ++l) {
+      const int c = r->cls * s->lpc + l;
+      if (s->lanes[c].outstanding < s->lanes[li].outstanding) li = c;
+    }
     r->off = off;
     r->abytes = abytes;
     r->slot = s->free_slots.back();
     s->free_slots.pop_back();
+    r->lane = li;
     r->t_admit = s->now();
     s->inflight_bytes += r->bytes;
     ++s->inflight;
+    ++s->lanes[li].outstanding;
     s->ctr.peak_inflight_bytes = std::max(s->ctr.peak_inflight_bytes, s->inflight_bytes);
     s->ctr.peak_inflight = std::max<int64_t>(s->ctr.peak_inflight, s->inflight);
     ++s->ctr.admitted;
-    s->lanes[target[r->cls]].group.push_back(r);
-    s->running.push_back(r);
+    batch[li].push_back(r);
     it = s->pending.erase(it);
     any = true;
   }
-  for (int c = 0; c < kClasses; ++c) {
-    if (target[c] < 0) continue;
-    Lane &L = s->lanes[target[c]];
-    if (L.group.empty()) continue;
-    ++L.tag;
-    const int rc = launch_group(s, target[c]);
-    if (rc != OT_OK) { s->fatal = rc; return any; }
+  for (int li = 0; li < s->nlanes(); ++li) {
+    if (batch[li].empty()) continue;
+    Lane &L = s->lanes[li];
+    hipError_t e;
+    for (Req *r : batch[li]) {
+      int32_t *hp = s->h_pts + (size_t)r->slot * 4 * M;
+      std::memcpy(hp, r->pts.data(), sizeof(int32_t) * 4 * (size_t)r->n);
+      int32_t *dp = s->d_pts + (size_t)r->slot * 4 * M;
+      if ((e = hipMemcpyAsync(dp, hp, sizeof(int32_t) * 4 * (size_t)r->n, hipMemcpyHostToDevice, s->sb)) != hipSuccess ||
+          (e = launch_grid_cost(dp, dp + 2 * r->n, r->n, (int32_t *)(s->arena_base + r->off), s->sb)) != hipSuccess) {
+        s->fatal = map_hip(e);
+        return any;
+      }
+    }
+    Build b;
+    if (!s->free_events.empty()) {
+      b.ev = s->free_events.back();
+      s->free_events.pop_back();
+    } else if ((e = hipEventCreateWithFlags(&b.ev, hipEventDisableTiming)) != hipSuccess) {
+      s->fatal = map_hip(e);
+      return any;
+    }
+    if ((e = hipEventRecord(b.ev, s->sb)) != hipSuccess) { s->fatal = map_hip(e); return any; }
+    b.reqs = std::move(batch[li]);
+    L.building.push_back(std::move(b));
+  }
+  return any;
+}
+
+// Publish the requests whose cost matrices are built, and start the kernel of
+// every lane with unclaimed entries and no kernel running.  Requires s->mu.
+bool publish(ot_server *s) {
+  bool any = false;
+  const size_t M = (size_t)s->maxn;
+  for (int li = 0; li < s->nlanes(); ++li) {
+    Lane &L = s->lanes[li];
+    bool published = false;
+    while (!L.building.empty()) {
+      Build &b = L.building.front();
+      const hipError_t q = hipEventQuery(b.ev);
+      if (q == hipErrorNotReady) break;
+      if (q != hipSuccess) { s->fatal = map_hip(q); return any; }
+      for (Req *r : b.reqs) {
+        const int sl = r->slot;
+        s->h_coff[sl] = r->off / 4;
+        s->h_voff[sl] = (int64_t)sl * (int64_t)M;
+        s->h_n[sl] = r->n;
+        r->pos = L.tail;
+        r->launch = L.running ? L.launches : -1;
+        L.h_ring[L.tail % s->qcap] = sl;
+        ++L.tail;
+        s->running.push_back(r);
+      }
+      s->free_events.push_back(b.ev);
+      L.building.pop_front();
+      published = true;
+    }
+    if (published) {
+      // the descriptors and ring entries above become visible before the tail
+      std::atomic_thread_fence(std::memory_order_release);
+      __atomic_store_n(L.h_tail, L.tail, __ATOMIC_RELEASE);
+      any = true;
+    }
+    if (!L.running && L.base < L.tail) {
+      const int rc = launch_lane(s, li);
+      if (rc != OT_OK) { s->fatal = rc; return any; }
+      any = true;
+    }
   }
   return any;
 }
@@ -298,9 +362,10 @@ void worker_main(ot_server *s) {
     bool progressed = retire(s);
     if (progressed) s->cv_done.notify_all();
     progressed = admit(s) || progressed;
+    progressed = publish(s) || progressed;
     if (s->stop && s->pending.empty() && s->running.empty()) {
       bool idle = true;
-      for (auto &L : s->lanes) idle = idle && !L.busy;
+      for (int li = 0; li < s->nlanes(); ++li) idle = idle && !s->lanes[li].running && s->lanes[li].building.empty();
       if (idle) break;
     }
     if (!progressed) s->cv_work.wait_for(lk, std::chrono::microseconds(20));
@@ -350,42 +415,53 @@ int ot_serve_open(ot_server **out, const ot_serve_cfg *cfg_in) {
   s->cfg = cfg;
   s->maxn = cfg.max_n;
   s->slots = cfg.max_inflight;
+  // more ring entries than slots: an entry's ring position is reused only after
+  // every earlier entry has been taken (at most `slots` wait at a time)
+  s->qcap = 2 * s->slots;
   s->cus = device_cus();
   s->t0 = std::chrono::steady_clock::now();
   const size_t M = (size_t)s->maxn, SL = (size_t)s->slots;
   hipError_t e = hipSuccess;
   auto chk = [&](hipError_t x) { if (e == hipSuccess) e = x; };
+  const unsigned mapped = hipHostMallocMapped | hipHostMallocCoherent;
   chk(hipMalloc(&s->arena_base, (size_t)cfg.hbm_budget_bytes));
   chk(hipMalloc(&s->d_pts, 4 * 4 * M * SL));
   chk(hipHostMalloc(&s->h_pts, 4 * 4 * M * SL, hipHostMallocDefault));
-  chk(hipHostMalloc(&s->h_plan, 4 * M * SL, hipHostMallocMapped | hipHostMallocCoherent));
-  chk(hipHostMalloc(&s->h_u, 8 * M * SL, hipHostMallocMapped | hipHostMallocCoherent));
-  chk(hipHostMalloc(&s->h_v, 8 * M * SL, hipHostMallocMapped | hipHostMallocCoherent));
-  const int ws_grid = std::min<int>(s->slots, 8 * s->cus);
+  chk(hipHostMalloc(&s->h_plan, 4 * M * SL, mapped));
+  chk(hipHostMalloc(&s->h_u, 8 * M * SL, mapped));
+  chk(hipHostMalloc(&s->h_v, 8 * M * SL, mapped));
+  chk(hipHostMalloc(&s->h_coff, 8 * SL, mapped));
+  chk(hipHostMalloc(&s->h_voff, 8 * SL, mapped));
+  chk(hipHostMalloc(&s->h_cost, 8 * SL, mapped));
+  chk(hipHostMalloc(&s->h_n, 4 * SL, mapped));
+  chk(hipHostMalloc(&s->h_done, 4 * SL, mapped));
+  chk(hipHostMalloc(&s->h_stop, 64, mapped));
+  chk(hipHostMalloc(&s->h_stats, sizeof(ot_stats) * SL, mapped));
   s->lpc = cfg.streams;
+  chk(hipStreamCreateWithFlags(&s->sb, hipStreamNonBlocking));
   for (int li = 0; li < s->nlanes() && e == hipSuccess; ++li) {
-    const int c = li / s->lpc;
     Lane &L = s->lanes[li];
+    L.cls = li / s->lpc;
+    L.max_n = std::min(kClassMaxN[L.cls], s->maxn);
+    L.block = kClassBlock[L.cls];
+    const int occ = batch_occupancy(L.block, L.max_n);
+    if (occ <= 0) { e = hipErrorInvalidValue; break; }
+    L.grid_max = std::max(1, std::min<int>(s->slots, occ * s->cus));
     chk(hipStreamCreateWithFlags(&L.s, hipStreamNonBlocking));
     chk(hipEventCreateWithFlags(&L.ev, hipEventDisableTiming));
-    chk(hipMalloc(&L.d_coff, 8 * SL)); chk(hipMalloc(&L.d_voff, 8 * SL));
-    chk(hipMalloc(&L.d_n, 4 * SL)); chk(hipMalloc(&L.d_order, 4 * SL));
     chk(hipMalloc(&L.d_head, 256));
-    chk(hipMalloc(&L.d_ws, 4 * ws_ints(std::min(kClassMaxN[c], s->maxn)) * (size_t)std::max(ws_grid, s->slots)));
-    chk(hipHostMalloc(&L.h_coff, 8 * SL, hipHostMallocDefault));
-    chk(hipHostMalloc(&L.h_voff, 8 * SL, hipHostMallocDefault));
-    chk(hipHostMalloc(&L.h_n, 4 * SL, hipHostMallocDefault));
-    chk(hipHostMalloc(&L.h_order, 4 * SL, hipHostMallocDefault));
-    chk(hipHostMalloc(&L.h_cost, 8 * SL, hipHostMallocMapped | hipHostMallocCoherent));
-    chk(hipHostMalloc(&L.h_stats, sizeof(ot_stats) * SL, hipHostMallocMapped | hipHostMallocCoherent));
-    chk(hipHostMalloc(&L.h_done, 4 * SL, hipHostMallocMapped | hipHostMallocCoherent));
+    chk(hipMalloc(&L.d_ws, 4 * ws_ints(L.max_n) * (size_t)L.grid_max));
+    chk(hipHostMalloc(&L.h_tail, 64, mapped));
+    chk(hipHostMalloc(&L.h_ring, 4 * (size_t)s->qcap, mapped));
   }
   if (e != hipSuccess) {
     const int rc = map_hip(e);
     free_server(s);
     return rc;
   }
-  for (int li = 0; li < s->nlanes(); ++li) std::memset(s->lanes[li].h_done, 0, 4 * SL);
+  std::memset(s->h_done, 0, 4 * SL);
+  std::memset(s->h_stop, 0, 64);
+  for (int li = 0; li < s->nlanes(); ++li) std::memset(s->lanes[li].h_tail, 0, 64);
   s->arena.reset(new otkm::Arena(cfg.hbm_budget_bytes));
   for (int k = s->slots - 1; k >= 0; --k) s->free_slots.push_back(k);
   s->worker = std::thread(worker_main, s);
@@ -459,6 +535,8 @@ int ot_serve_close(ot_server *s) {
   }
   s->cv_work.notify_all();
   if (s->worker.joinable()) s->worker.join();
+  // kernels still waiting on an empty queue leave at once
+  __atomic_store_n(s->h_stop, 1, __ATOMIC_RELEASE);
   const int rc = s->fatal;
   free_server(s);
   return rc;

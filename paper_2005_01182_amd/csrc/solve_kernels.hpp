@@ -1,0 +1,201 @@
+// solve_kernels.hpp -- the engine's kernels (one instance per workgroup, one
+// instance over several workgroups, persistent batch) and their launch
+// helpers.  Each solve_*.hip file instantiates a share of the widths so that
+// the library builds in parallel.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "engine.hpp"
+#include "launch.hpp"
+
+namespace otkm {
+
+// ---------------------------------------------------------------------------
+// single instance
+// ---------------------------------------------------------------------------
+template <int BLOCK, int CPT>
+__global__ __launch_bounds__(BLOCK) void k_assign_one(Problem P, const int32_t *gate) {
+  extern __shared__ __align__(16) char smem[];
+  if (gate && *gate != 0) return;  // an earlier stage of this pipeline already failed
+  Engine<BLOCK, CPT, (BLOCK <= 512), false, true> E;  // at 1024 threads the registers are too few for LONG
+  E.run(P, smem);
+}
+
+// ---------------------------------------------------------------------------
+// one instance over gridDim.x workgroups (P.grid_ws header zeroed before the
+// launch; the grid is at most kMaxWgs workgroups, one per CU, so all of them
+// are resident at once)
+// ---------------------------------------------------------------------------
+template <int BLOCK, int CPT>
+__global__ __launch_bounds__(BLOCK) void k_assign_grid(Problem P) {
+  extern __shared__ __align__(16) char smem[];
+  Engine<BLOCK, CPT, true, true, true> E;
+  E.run(P, smem);
+}
+
+// ---------------------------------------------------------------------------
+// persistent batch: each workgroup pops instance indices until the queue is empty
+// ---------------------------------------------------------------------------
+// Two wavefronts per SIMD: the register budget drops to 256 (a few bytes of
+// spill at 8 columns per lane) and twice as many instances share each CU, which
+// measured 126k -> 181k solves/s on the embedding batch; three or four per SIMD
+// spill heavily and lose.
+template <int BLOCK, int CPT>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2))) void k_assign_batch(BatchArgs A) {
+  extern __shared__ __align__(16) char smem[];
+  __shared__ int s_idx, s_k, s_n;
+  __shared__ int64_t s_coff, s_voff;
+  int32_t *ws = A.ws + (size_t)blockIdx.x * ws_ints(A.max_n);
+  const bool live = A.live_tail != nullptr;
+  for (;;) {
+    if (threadIdx.x == 0) {
+      int idx = -1, k = -1;
+      if (!live) {
+        idx = atomicAdd(A.head, 1);
+        if (idx < A.nq) k = A.order ? A.order[idx] : idx;
+        else idx = -1;
+      } else {
+        // Live queue: the host publishes entries [0, *live_tail) while the
+        // kernel runs; an entry is taken by advancing the head past it.  An
+        // empty queue is polled `linger` times (a short sleep each) before the
+        // workgroup leaves, or not at all once the host raised the stop flag:
+        // every wait is bounded.
+        for (int spin = 0;; ++spin) {
+          const int h = __hip_atomic_load(A.head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          const int t = __hip_atomic_load(A.live_tail, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
+          if (h < t) {
+            int hh = h;
+            if (__hip_atomic_compare_exchange_strong(A.head, &hh, h + 1, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_AGENT)) {
+              idx = h;
+              k = __hip_atomic_load(&A.order[h % A.qcap], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+              break;
+            }
+            continue;
+          }
+          if (spin >= A.linger || __hip_atomic_load(A.live_stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM)) break;
+          __builtin_amdgcn_s_sleep(63);
+        }
+      }
+      // the descriptor, read once (system scope when the host writes it while the kernel runs)
+      int n = 0;
+      int64_t coff = 0, voff = 0;
+      if (idx >= 0 && (unsigned)k < (unsigned)A.count) {
+        if (live) {
+          n = __hip_atomic_load(&A.n[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+          coff = __hip_atomic_load(&A.coff[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+          voff = __hip_atomic_load(&A.voff[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        } else {
+          n = A.n[k];
+          coff = A.coff[k];
+          voff = A.voff[k];
+        }
+      }
+      s_idx = idx;
+      s_k = k;
+      s_n = n;
+      s_coff = coff;
+      s_voff = voff;
+    }
+    __syncthreads();
+    const int idx = s_idx, k = s_k, n = s_n;
+    const int64_t coff = s_coff, voff = s_voff;
+    __syncthreads();
+    if (idx < 0) break;  // every workgroup reaches this exit once the queue drains
+    // the completion tag: the launch's for a fixed queue, the entry's position
+    // (plus one, so never the initial zero) for a live queue
+    const int32_t tag = live ? idx + 1 : A.tag;
+    if ((unsigned)k >= (unsigned)A.count) continue;  // no such instance: nothing to report or flag
+    if (n < 1 || n > A.max_n || n > BLOCK * CPT) {
+      if (threadIdx.x == 0) {
+        if (A.stats) { ot_stats s = {}; s.status = OT_EINVAL; A.stats[k] = s; }
+        if (A.done) {
+          __threadfence_system();
+          __hip_atomic_store(&A.done[k], tag, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+        }
+      }
+      continue;
+    }
+    Problem P;
+    P.C = A.C + coff;
+    P.n = n;
+    P.ld = n;
+    P.CT = A.CT ? A.CT + coff : nullptr;
+    P.Cout = nullptr;
+    P.ldo = n;
+    P.dscale = 1;
+    P.init_u = nullptr; P.init_b = nullptr; P.init_rmax = nullptr;
+    P.max_paths = A.max_paths;
+    P.flags = 0;
+    P.plan = A.plan + voff;
+    P.cost = A.cost + k;
+    P.u = A.u ? A.u + voff : nullptr;
+    P.v = A.v ? A.v + voff : nullptr;
+    P.stats = A.stats ? A.stats + k : nullptr;
+    P.ws = ws;
+    Engine<BLOCK, CPT> E;
+    E.run(P, smem);
+    if (A.done) {
+      // outputs may live in host memory: make every thread's writes visible
+      // system-wide before the completion flag is released
+      __threadfence_system();
+      __syncthreads();
+      if (threadIdx.x == 0) __hip_atomic_store(&A.done[k], tag, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void k_fill_u64(uint64_t *p, uint64_t value, int64_t count);
+
+// ---------------------------------------------------------------------------
+// launch helpers
+// ---------------------------------------------------------------------------
+template <typename K>
+static hipError_t allow_lds(K kernel, size_t bytes) {
+  return hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+template <int B, int CPT>
+static hipError_t one(const Problem &P, const int32_t *gate, hipStream_t s) {
+  const size_t lds = lds_layout(P.n).total;
+  hipError_t e = allow_lds(k_assign_one<B, CPT>, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_assign_one<B, CPT>), dim3(1), dim3(B), lds, s, P, gate);
+  return hipGetLastError();
+}
+
+template <int B, int CPT>
+static hipError_t grid(const Problem &P, int wgs, hipStream_t s) {
+  const size_t lds = lds_layout(P.n).total;
+  hipError_t e = allow_lds(k_assign_grid<B, CPT>, lds);
+  if (e != hipSuccess) return e;
+  // every tag word must start below the first level
+  hipLaunchKernelGGL(k_fill_u64, dim3(16), dim3(256), 0, s, P.grid_ws, (uint64_t)0,
+                     (int64_t)grid_ws_u64(wgs, B * CPT));
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL((k_assign_grid<B, CPT>), dim3(wgs), dim3(B), lds, s, P);
+  return hipGetLastError();
+}
+
+template <int B, int CPT>
+static hipError_t batch(const BatchArgs &A, int grid, hipStream_t s) {
+  const size_t lds = lds_layout(A.max_n).total;
+  hipError_t e = allow_lds(k_assign_batch<B, CPT>, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_assign_batch<B, CPT>), dim3(grid), dim3(B), lds, s, A);
+  return hipGetLastError();
+}
+
+template <int B, int CPT>
+static int occ(int max_n) {
+  int blocks = 0;
+  const size_t lds = lds_layout(max_n).total;
+  if (allow_lds(k_assign_batch<B, CPT>, lds) != hipSuccess) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, (const void *)k_assign_batch<B, CPT>, B, lds) != hipSuccess)
+    return 0;
+  return blocks;
+}
+
+}  // namespace otkm

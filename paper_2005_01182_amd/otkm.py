@@ -15,7 +15,8 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libotkm.so")
+# OTKM_LIBRARY selects another build of the same library (for A/B measurements)
+LIB_PATH = os.environ.get("OTKM_LIBRARY") or os.path.join(_HERE, "libotkm.so")
 
 OT_OK, OT_EINVAL, OT_ERANGE, OT_EUNBALANCED, OT_ENEGMASS = 0, -1, -2, -3, -4
 OT_ETOOBIG, OT_ENOMEM, OT_EDEVICE, OT_ENODEV, OT_EINTERNAL = -5, -6, -7, -8, -9
@@ -23,7 +24,7 @@ OT_MAX_N = 4096
 
 EXPORTS = [
     "ot_strerror", "ot_init", "ot_assign", "ot_assign_ex", "ot_assign_rect", "ot_scale_for", "ot_transport",
-    "ot_assign_batch",
+    "ot_assign_batch", "ot_transport_bins", "ot_transport_bins_dev",
     "ot_assign_dev", "ot_assign_rect_dev", "ot_assign_batch_dev", "ot_transpose_batch_dev", "ot_transport_dev",
     "ot_schedule_get", "ot_schedule_set", "ot_schedule_tune", "ot_schedule_rule",
     "ot_split_get", "ot_split_set", "ot_split_tune", "ot_split_rule",
@@ -65,7 +66,7 @@ class ot_result(ctypes.Structure):
 
 class ot_serve_counters(ctypes.Structure):
     _fields_ = [(name, ctypes.c_int64) for name in
-                ("submitted", "admitted", "completed", "groups", "peak_inflight_bytes", "peak_inflight")]
+                ("submitted", "admitted", "completed", "groups", "peak_inflight_bytes", "peak_inflight", "joined")]
 
     def as_dict(self):
         return {name: int(getattr(self, name)) for name, _ in self._fields_}
@@ -105,6 +106,8 @@ def load():
         lib.ot_assign_rect.argtypes = [_VP, _I32, _I32, _VP, _VP, _VP, _VP, _VP, _VP]
         lib.ot_scale_for.argtypes = [_VP, _I32, ctypes.c_double, _VP, _VP]
         lib.ot_transport.argtypes = [_VP, _VP, _VP, _I32, _I32, _VP, _VP, _VP, _VP]
+        lib.ot_transport_bins.argtypes = [_VP, _VP, _VP, _I32, _I32, _VP, _VP, _VP, _VP, _VP]
+        lib.ot_transport_bins_dev.argtypes = [_VP, _VP, _VP, _I32, _I32, _I32, _VP, _VP, _VP, _VP, _VP, _VP]
         lib.ot_assign_batch.argtypes = [_I32, _VP, _VP, _VP, _VP, _VP, _VP, _VP]
         lib.ot_assign_dev.argtypes = [_VP, _I32, _I32, _VP, _VP, _VP, _VP, _VP, _VP, _VP]
         lib.ot_assign_rect_dev.argtypes = [_VP, _I32, _I32, _I32, _VP, _VP, _VP, _VP, _VP, _VP, _VP]
@@ -246,6 +249,27 @@ def ot_transport(C, r, c):
     rc = load().ot_transport(_p(C), _p(r), _p(c), n, m, _p(X), ctypes.byref(cost), _p(u), _p(v))
     _check(rc, "ot_transport")
     return X, int(cost.value), u, v
+
+
+def ot_transport_bins(C, r, c, with_stats: bool = False):
+    """Exact integer transport solved on the bins (no unit expansion; total mass
+    up to 2^31 - 1).  Returns (X, cost, u, v) or (X, cost, u, v, stats_dict)."""
+    C = np.ascontiguousarray(C, dtype=np.int32)
+    r = np.ascontiguousarray(r, dtype=np.int32)
+    c = np.ascontiguousarray(c, dtype=np.int32)
+    n, m = C.shape
+    if r.shape != (n,) or c.shape != (m,):
+        raise ValueError("mass vectors must match the cost matrix")
+    X = np.empty((n, m), np.int32)
+    u = np.empty(n, np.int64)
+    v = np.empty(m, np.int64)
+    cost = ctypes.c_int64(0)
+    st = ot_stats()
+    rc = load().ot_transport_bins(_p(C), _p(r), _p(c), n, m, _p(X), ctypes.byref(cost), _p(u), _p(v),
+                                  ctypes.byref(st))
+    _check(rc, "ot_transport_bins")
+    out = (X, int(cost.value), u, v)
+    return out + (st.as_dict(),) if with_stats else out
 
 
 def ot_assign_batch(Cs):
@@ -396,6 +420,15 @@ def ot_transport_dev(C, r, c, S, X, cost, u, v, stats=None, stream=None):
     rc = load().ot_transport_dev(_tp(C), _tp(r), _tp(c), n, m, int(S), _tp(X), _tp(cost), _tp(u), _tp(v),
                                  _tp(stats), _stream(stream))
     _check(rc, "ot_transport_dev")
+
+
+def ot_transport_bins_dev(C, r, c, X, cost, u, v, stats=None, stream=None, ld=None):
+    """Queue a bin-level transport solve on device tensors (asynchronous on `stream`)."""
+    n, m = int(C.shape[0]), int(C.shape[1])
+    ld = int(ld if ld is not None else C.stride(0))
+    rc = load().ot_transport_bins_dev(_tp(C), _tp(r), _tp(c), n, m, ld, _tp(X), _tp(cost), _tp(u), _tp(v),
+                                      _tp(stats), _stream(stream))
+    _check(rc, "ot_transport_bins_dev")
 
 
 def ot_grid_cost_dev(src, dst, C, stream=None):

@@ -88,7 +88,7 @@ def summarise(path, kernel=None, skip=0):
     return "\n".join(out)
 
 
-KERNEL_SOURCES = ("csrc/engine.hpp", "csrc/kernels.hip", "csrc/launch.hpp")
+KERNEL_SOURCES = ("csrc/engine.hpp", "csrc/solve_kernels.hpp", "csrc/kernels.hip", "csrc/launch.hpp")
 
 
 def kernel_source_sha():

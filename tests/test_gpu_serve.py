@@ -108,3 +108,31 @@ def test_streams_per_class_do_not_change_results(otkm_gpu):
     for a, b in zip(*out):
         assert a["status"] == 0 and b["status"] == 0 and a["cost"] == b["cost"]
         assert np.array_equal(a["plan"], b["plan"]) and np.array_equal(a["u"], b["u"])
+
+
+def test_request_joins_the_running_kernel(otkm_gpu):
+    """A request of the same size class submitted while that class's kernel is
+    solving an earlier one is taken by the running kernel (no new launch), and
+    both results are certified."""
+    import time
+    rng = np.random.default_rng(9)
+    first, second = points(rng, 4096), points(rng, 2100)
+    with otkm_gpu.Server() as srv:
+        a = srv.submit(*first)
+        # wait until the first request's kernel runs (a solve at n = 4096 takes
+        # a few hundred milliseconds on one workgroup)
+        for _ in range(2000):
+            ctr, _ = srv.stats()
+            if ctr["groups"] >= 1:
+                break
+            time.sleep(0.001)
+        time.sleep(0.005)
+        b = srv.submit(*second)
+        ra, rb = srv.poll(a, 4096), srv.poll(b, 2100)
+        ctr, _ = srv.stats()
+    say("counters", ctr)
+    assert ra["status"] == 0 and rb["status"] == 0
+    assert ctr["groups"] == 1 and ctr["joined"] >= 1
+    for (s, d), r in ((first, ra), (second, rb)):
+        C = wl.grid_points_cost(s, d)
+        assert oracle.certify_assign(C, r["plan"], r["u"], r["v"]) == 0
