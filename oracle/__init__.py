@@ -19,6 +19,10 @@ Functions (all exact, int64 results):
 * ``certify_transport(C, r, c, X, u, v)`` -> 0 if the certificate holds
 * ``transport_bins(C, r, c)`` -> (X, cost, u, v)  successive shortest paths on the
                              bins themselves (no unit expansion; masses up to 2^31 - 1)
+* ``assign_sparse(ptr, idx, cst, n, m)`` -> (plan, cost, u, v)  n <= m rows matched
+                             along the edges of a CSR cost graph; raises ``Infeasible``
+                             when no matching covers every row
+* ``certify_sparse(ptr, idx, cst, n, m, plan, u, v)`` -> 0 if the sparse LP certificate holds
 """
 from __future__ import annotations
 
@@ -64,9 +68,12 @@ def _load():
             lib.oracle_transport.argtypes = [_I32P, _I32P, _I32P, i32, i32, _I32P, _I64P, _I64P, i64p]
             lib.oracle_certify_transport.argtypes = [_I32P, _I32P, _I32P, i32, i32, _I32P, _I64P, _I64P]
             lib.oracle_transport_ssp.argtypes = [_I32P, _I32P, _I32P, i32, i32, _I32P, _I64P, _I64P, i64p]
+            lib.oracle_assign_sparse.argtypes = [_I64P, _I32P, _I32P, i32, i32, _I32P, _I64P, _I64P, i64p]
+            lib.oracle_certify_sparse.argtypes = [_I64P, _I32P, _I32P, i32, i32, _I32P, _I64P, _I64P]
             for f in (lib.oracle_assign, lib.oracle_brute_force, lib.oracle_certify_assign,
                       lib.oracle_assign_rect, lib.oracle_certify_rect,
-                      lib.oracle_transport, lib.oracle_certify_transport, lib.oracle_transport_ssp):
+                      lib.oracle_transport, lib.oracle_certify_transport, lib.oracle_transport_ssp,
+                      lib.oracle_assign_sparse, lib.oracle_certify_sparse):
                 f.restype = ctypes.c_int
             _lib = lib
     return _lib
@@ -218,3 +225,52 @@ def transport_bins(C, r, c):
     if rc:
         raise RuntimeError("oracle_transport_ssp failed: %d" % rc)
     return X, int(cost.value), u, v
+
+
+class Infeasible(Exception):
+    """No matching of the graph covers every row (Hall's condition fails)."""
+
+
+def _csr(ptr, idx, cst, n, m):
+    ptr = np.ascontiguousarray(ptr, dtype=np.int64)
+    idx = np.ascontiguousarray(idx, dtype=np.int32)
+    cst = np.ascontiguousarray(cst, dtype=np.int32)
+    if ptr.shape != (n + 1,) or idx.shape != cst.shape or idx.shape != (int(ptr[-1]),):
+        raise ValueError("CSR arrays do not match n and the edge count")
+    # zero-length arrays still need a valid pointer
+    if idx.size == 0:
+        idx, cst = np.zeros(1, np.int32), np.zeros(1, np.int32)
+    return ptr, idx, cst
+
+
+def assign_sparse(ptr, idx, cst, n: int, m: int):
+    """Minimum-cost matching of all n rows into m >= n columns along the edges of
+    a CSR graph (row i: columns idx[ptr[i]:ptr[i+1]], costs cst[...]).  Returns
+    (plan int32[n], cost int, u int64[n], v int64[m]) with u_i + v_j <= c_e on
+    every edge, equality on the plan, v <= 0 and v = 0 on unmatched columns.
+    Raises Infeasible when no such matching exists."""
+    n, m = int(n), int(m)
+    ptr, idx, cst = _csr(ptr, idx, cst, n, m)
+    plan = np.empty(n, np.int32)
+    u = np.empty(n, np.int64)
+    v = np.empty(m, np.int64)
+    cost = ctypes.c_int64(0)
+    rc = _load().oracle_assign_sparse(ptr, idx, cst, n, m, plan, u, v, ctypes.byref(cost))
+    if rc == -10:
+        raise Infeasible("no matching covers every row")
+    if rc:
+        raise RuntimeError("oracle_assign_sparse failed: %d" % rc)
+    return plan, int(cost.value), u, v
+
+
+def certify_sparse(ptr, idx, cst, n: int, m: int, plan, u, v) -> int:
+    """0 when (plan, u, v) certifies an optimal sparse assignment; else the failing
+    condition (1-5)."""
+    n, m = int(n), int(m)
+    ptr, idx, cst = _csr(ptr, idx, cst, n, m)
+    plan = np.ascontiguousarray(plan, dtype=np.int32)
+    u = np.ascontiguousarray(u, dtype=np.int64)
+    v = np.ascontiguousarray(v, dtype=np.int64)
+    if plan.shape != (n,) or u.shape != (n,) or v.shape != (m,):
+        return 1
+    return int(_load().oracle_certify_sparse(ptr, idx, cst, n, m, plan, u, v))

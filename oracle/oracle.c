@@ -555,3 +555,154 @@ int oracle_certify_rect(const int32_t *C, int32_t n, int32_t m, const int32_t *p
     for (int32_t j = 0; j < m; ++j) dual += v[j];
     return primal == dual ? 0 : 5;
 }
+
+/* ------------------------------------------------------------------------- */
+/* Sparse assignment on a bipartite graph given in CSR                         */
+/* ------------------------------------------------------------------------- */
+/*
+ * Rows 0..n-1 and columns 0..m-1 with n <= m; row i's edges are the columns
+ * idx[ptr[i] .. ptr[i+1]) with costs cst[...] (a column at most once per row).
+ * Minimise the total cost over matchings that cover every row using edges of
+ * the graph only: Eq. (1) with unit masses on a cost graph where missing
+ * entries are not allowed (the sparse, possibly rectangular form of the
+ * problem).  The LP's dual maximises sum u + sum v subject to u_i + v_j <= c_e
+ * on every edge e = (i, j) and v_j <= 0.
+ *
+ * Same shortest-augmenting-path method as sap_rows_le_cols, one new row per
+ * stage; a tree row relaxes only its own edges, so a column that no tree
+ * edge reaches keeps dist = BIG.  When every unsettled column has dist = BIG
+ * the tree cannot grow and holds a free column nowhere: its rows have fewer
+ * neighbours than rows (Hall's condition fails) and no matching covers all
+ * rows: ORC_EINFEASIBLE.  Duals start at zero and column duals only fall
+ * after their column is settled; the first step of a stage may lower the new
+ * root's u below zero (its edges can be cheaper than anything so far), and
+ * every later step has delta >= 0, so v_j <= 0 and columns never matched keep
+ * v_j = 0.
+ */
+#define ORC_EINFEASIBLE (-10)
+
+static int sparse_validate(const int64_t *ptr, const int32_t *idx, int32_t n, int32_t m)
+{
+    if (ptr[0] != 0) return ORC_EINVAL;
+    int32_t *mark = malloc((size_t)m * sizeof *mark);
+    if (!mark) return ORC_ENOMEM;
+    for (int32_t j = 0; j < m; ++j) mark[j] = -1;
+    int rc = 0;
+    for (int32_t i = 0; i < n && !rc; ++i) {
+        if (ptr[i + 1] < ptr[i]) { rc = ORC_EINVAL; break; }
+        for (int64_t e = ptr[i]; e < ptr[i + 1]; ++e) {
+            int32_t j = idx[e];
+            if (j < 0 || j >= m || mark[j] == i) { rc = ORC_EINVAL; break; }
+            mark[j] = i;
+        }
+    }
+    free(mark);
+    return rc;
+}
+
+int oracle_assign_sparse(const int64_t *ptr, const int32_t *idx, const int32_t *cst, int32_t n,
+                         int32_t m, int32_t *plan, int64_t *u, int64_t *v, int64_t *cost_out)
+{
+    if (!ptr || !plan || !u || !v || !cost_out || n <= 0 || m < n) return ORC_EINVAL;
+    if (ptr[n] > 0 && (!idx || !cst)) return ORC_EINVAL;
+    int rc = sparse_validate(ptr, idx, n, m);
+    if (rc) return rc;
+    int64_t *dist = malloc((size_t)m * sizeof *dist);
+    int32_t *via = malloc((size_t)m * sizeof *via);
+    int32_t *owner = malloc((size_t)m * sizeof *owner);
+    int32_t *trow = malloc((size_t)n * sizeof *trow);
+    unsigned char *done = malloc((size_t)m);
+    if (!dist || !via || !owner || !trow || !done) { rc = ORC_ENOMEM; goto out; }
+    for (int32_t i = 0; i < n; ++i) { plan[i] = -1; u[i] = 0; }
+    for (int32_t j = 0; j < m; ++j) { owner[j] = -1; v[j] = 0; }
+
+    for (int32_t r = 0; r < n && !rc; ++r) {
+        for (int32_t j = 0; j < m; ++j) { dist[j] = BIG; via[j] = -1; done[j] = 0; }
+        int32_t ntree = 0;
+        trow[ntree++] = r;
+        int32_t newest = r;
+        int32_t end = -1;
+        for (;;) {
+            for (int64_t e = ptr[newest]; e < ptr[newest + 1]; ++e) {
+                int32_t j = idx[e];
+                if (done[j]) continue;
+                int64_t s = (int64_t)cst[e] - u[newest] - v[j];
+                if (s < dist[j]) { dist[j] = s; via[j] = newest; }
+            }
+            int32_t best = -1;
+            for (int32_t j = 0; j < m; ++j)
+                if (!done[j] && dist[j] < BIG && (best < 0 || dist[j] < dist[best])) best = j;
+            if (best < 0) { rc = ORC_EINFEASIBLE; break; }
+            int64_t delta = dist[best];
+            for (int32_t t = 0; t < ntree; ++t) u[trow[t]] += delta;
+            for (int32_t j = 0; j < m; ++j) {
+                if (done[j]) v[j] -= delta;
+                else if (dist[j] < BIG) dist[j] -= delta;
+            }
+            done[best] = 1;
+            if (owner[best] < 0) { end = best; break; }
+            newest = owner[best];
+            trow[ntree++] = newest;
+        }
+        if (rc) break;
+        for (int32_t j = end;;) {
+            int32_t i = via[j];
+            int32_t before = plan[i];
+            owner[j] = i;
+            plan[i] = j;
+            if (i == r) break;
+            j = before;
+        }
+    }
+    if (!rc) {
+        int64_t total = 0;
+        for (int32_t i = 0; i < n; ++i)
+            for (int64_t e = ptr[i]; e < ptr[i + 1]; ++e)
+                if (idx[e] == plan[i]) total += cst[e];
+        *cost_out = total;
+    }
+out:
+    free(dist); free(via); free(owner); free(trow); free(done);
+    return rc;
+}
+
+/*
+ * Certificate of the sparse LP above.  Returns 0 when:
+ *   1  plan maps the rows to distinct columns, each along an edge of its row
+ *   2  u_i + v_j <= c_e on every edge
+ *   3  equality on every matched edge
+ *   4  v_j <= 0, and v_j == 0 on columns left unmatched
+ *   5  sum of matched costs == sum u + sum v
+ * 1-4 give optimality by weak duality; 5 catches overflow.
+ */
+int oracle_certify_sparse(const int64_t *ptr, const int32_t *idx, const int32_t *cst, int32_t n,
+                          int32_t m, const int32_t *plan, const int64_t *u, const int64_t *v)
+{
+    if (!ptr || !plan || !u || !v || n <= 0 || m < n) return ORC_EINVAL;
+    unsigned char *seen = calloc((size_t)m, 1);
+    if (!seen) return ORC_ENOMEM;
+    int64_t primal = 0, dual = 0;
+    int rc = 0;
+    for (int32_t i = 0; i < n && !rc; ++i) {
+        int32_t j = plan[i];
+        if (j < 0 || j >= m || seen[j]) { rc = 1; break; }
+        seen[j] = 1;
+        int found = 0;
+        for (int64_t e = ptr[i]; e < ptr[i + 1]; ++e) {
+            if (u[i] + v[idx[e]] > (int64_t)cst[e]) { rc = 2; break; }
+            if (idx[e] == j) {
+                found = 1;
+                if (u[i] + v[j] != (int64_t)cst[e]) { rc = 3; break; }
+                primal += cst[e];
+            }
+        }
+        if (!rc && !found) rc = 1;
+    }
+    for (int32_t j = 0; j < m && !rc; ++j)
+        if (v[j] > 0 || (!seen[j] && v[j] != 0)) rc = 4;
+    free(seen);
+    if (rc) return rc;
+    for (int32_t i = 0; i < n; ++i) dual += u[i];
+    for (int32_t j = 0; j < m; ++j) dual += v[j];
+    return primal == dual ? 0 : 5;
+}

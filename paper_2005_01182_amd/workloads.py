@@ -16,6 +16,10 @@ are not redistributed here:
   300-d vectors with near-duplicates, the NLP family in spirit (Section 3.2).
 * ``serving_trace`` / ``grid_points_cost`` -- Poisson request stream whose
   costs are rounded Euclidean distances between integer grid points.
+* ``knn_graph`` / ``knn_assignment`` -- sparse cost graphs in CSR: each source
+  point keeps its k nearest targets (plus, optionally, one edge of a random
+  perfect matching so that every row can be matched), the sparse form of the
+  geometric family.
 
 Every generator is a pure function of its seed (numpy PCG64; independent
 sub-streams come from ``SeedSequence(seed).spawn``).
@@ -44,6 +48,10 @@ __all__ = [
     "grid_points_cost",
     "ServingRequest",
     "serving_trace",
+    "knn_graph",
+    "knn_assignment",
+    "knn_batch",
+    "csr_to_dense",
 ]
 
 
@@ -274,3 +282,74 @@ def serving_trace(rate: float = 2000.0, duration: float = 60.0, lo: int = 32, hi
         dst = np.rint(grid * rng_p.uniform(0.0, 1.0, (n, 2))).astype(np.int32)
         yield ServingRequest(rid, t, n, src, dst)
         rid += 1
+
+
+# --------------------------------------------------------------------------- #
+# Sparse cost graphs (k nearest neighbours, CSR)
+# --------------------------------------------------------------------------- #
+def knn_graph(ps: np.ndarray, pt: np.ndarray, k: int, extra=None, chunk: int = 1024):
+    """CSR graph from source points ps (n, 2) to target points pt (m, 2), integer.
+
+    Row i keeps the k targets nearest to ps[i] (squared distance, ties to the
+    smaller index) and, when ``extra`` is given, also column extra[i]; the edge
+    cost is round(|p - q|) (as ``grid_points_cost``).  Columns are sorted within
+    each row.  Returns (ptr int64[n + 1], idx int32[nnz], cost int32[nnz]).
+    """
+    ps = np.asarray(ps, dtype=np.int64)
+    pt = np.asarray(pt, dtype=np.int64)
+    n, m = ps.shape[0], pt.shape[0]
+    k = min(int(k), m)
+    rows = []
+    for a in range(0, n, chunk):
+        b = min(n, a + chunk)
+        dx = ps[a:b, None, 0] - pt[None, :, 0]
+        dy = ps[a:b, None, 1] - pt[None, :, 1]
+        d2 = dx * dx + dy * dy
+        # exact k smallest with ties to the smaller column: sort by (d2, column)
+        key = d2 * m + np.arange(m)[None, :]
+        near = np.argpartition(key, k - 1, axis=1)[:, :k] if k < m else np.tile(np.arange(m), (b - a, 1))
+        rows.append(near)
+    near = np.concatenate(rows, axis=0) if rows else np.zeros((0, k), np.int64)
+    ptr = np.zeros(n + 1, np.int64)
+    idx_l, cst_l = [], []
+    for i in range(n):
+        cols = set(int(j) for j in near[i])
+        if extra is not None:
+            cols.add(int(extra[i]))
+        cols = np.array(sorted(cols), np.int64)
+        d = pt[cols] - ps[i]
+        idx_l.append(cols.astype(np.int32))
+        cst_l.append(isqrt_round((d * d).sum(1)).astype(np.int32))
+        ptr[i + 1] = ptr[i] + cols.size
+    idx = np.concatenate(idx_l) if idx_l else np.zeros(0, np.int32)
+    cst = np.concatenate(cst_l) if cst_l else np.zeros(0, np.int32)
+    return ptr, idx, cst
+
+
+def knn_assignment(n: int, m: int | None = None, k: int = 16, grid: int = 10000, matchable: bool = True,
+                   seed: int = 0):
+    """Sparse assignment instance: n source and m >= n target points ~ U{0..grid}^2,
+    each source joined to its k nearest targets; with ``matchable`` every row also
+    gets the edge to its partner in a random injective map, so some matching
+    covers all rows.  Returns (ptr, idx, cost, n, m)."""
+    m = n if m is None else int(m)
+    rng_p, rng_x = rng_for(seed, 2)
+    ps = rng_p.integers(0, grid, size=(n, 2), endpoint=True)
+    pt = rng_p.integers(0, grid, size=(m, 2), endpoint=True)
+    extra = rng_x.permutation(m)[:n] if matchable else None
+    ptr, idx, cst = knn_graph(ps, pt, k, extra)
+    return ptr, idx, cst, n, m
+
+
+def knn_batch(count: int = 4096, lo: int = 16, hi: int = 512, k: int = 16, seed: int = 0):
+    """``count`` matchable k-NN instances with n ~ U{lo..hi} (square)."""
+    sizes = embedding_sizes(count, lo, hi, seed)
+    return [knn_assignment(int(n), k=k, seed=seed * 1000003 + j) for j, n in enumerate(sizes)]
+
+
+def csr_to_dense(ptr, idx, cst, n: int, m: int, missing: int) -> np.ndarray:
+    """Dense n x m int32 matrix of the graph's costs with ``missing`` where no edge is."""
+    C = np.full((n, m), missing, np.int32)
+    rows = np.repeat(np.arange(n), np.diff(np.asarray(ptr, np.int64)))
+    C[rows, np.asarray(idx, np.int64)] = cst
+    return C
