@@ -11,6 +11,7 @@ Other modes (each prints one JSON line of its own; not the headline):
   --mode batch      4096 embedding assignments, n ~ U{16..512}, one graph replay per step
   --mode scaled     the headline instance under one scaling factor (--scale s): solved on floor(C / s)
   --mode serve      Poisson request stream through the continuous-batching server
+  --mode bins       the pixel histograms at mass 2^20 each, transport solved on the bins
 """
 from __future__ import annotations
 
@@ -448,6 +449,64 @@ def bench_transport(args):
     return out
 
 
+def bench_bins(args):
+    """Pixel-histogram transport solved on the bins (no unit expansion), at a total
+    mass per image that unit expansion could not hold (MNIST-like totals)."""
+    import torch
+
+    from paper_2005_01182_amd import otkm as ot
+    from paper_2005_01182_amd import workloads as wl
+    C, r, c = wl.pixel_histogram_pair(total=args.mass)
+    n, m = C.shape
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    dC, dr, dc = d(C), d(r), d(c)
+    X = torch.empty((n, m), dtype=torch.int32, device="cuda")
+    cost = torch.empty(1, dtype=torch.int64, device="cuda")
+    u = torch.empty(n, dtype=torch.int64, device="cuda")
+    v = torch.empty(m, dtype=torch.int64, device="cuda")
+    st = ot.stats_tensor(args.steps + args.warmup)
+    stream = torch.cuda.Stream()
+    log("bins transport, mass %d: warmup %d, steps %d" % (args.mass, args.warmup, args.steps))
+    for w in range(args.warmup):
+        ot.ot_transport_bins_dev(dC, dr, dc, X, cost, u, v, st[w], stream=stream)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0.record(stream)
+    for k in range(args.steps):
+        ev[k][0].record(stream)
+        ot.ot_transport_bins_dev(dC, dr, dc, X, cost, u, v, st[args.warmup + k], stream=stream)
+        ev[k][1].record(stream)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    per = [a.elapsed_time(b) for a, b in ev]
+    total = t0.elapsed_time(t1)
+    stats = st[args.warmup:].cpu().numpy()
+    if int(np.abs(stats[:, F["status"]]).max()) != 0:
+        raise SystemExit("bins transport status %s" % stats[:, F["status"]])
+    b = alg_bytes(stats, [m] * len(stats))
+    got = int(cost.item())
+    out = base_line(args, args.steps / (total / 1e3), "solves/s", total / args.steps,
+                    {"workload": "pixel-histogram transport on the bins: two 28x28 blob images (seeds 0, 1), "
+                                 "mass %d each, cost = squared grid distance, no unit expansion" % args.mass,
+                     "bins": n, "mass": args.mass, "optimal_cost": got})
+    out["metric"] = "solves/s, integer transport on bins"
+    out["roofline"] = roofline(float(np.mean(b)), float(np.mean(per)) / 1e3)
+    out["latency_ms"] = {"p50": pct(per, 50), "p99": pct(per, 99)}
+    out["solver_counters"] = {**counters(stats), "paths": int(stats[0, F["paths"]]),
+                              "alg_bytes_per_solve": int(b[0])}
+    if not args.skip_cpu:
+        import oracle
+        ref = oracle.transport_bins(C, r, c)
+        if ref[1] != got:
+            raise SystemExit("GPU transport cost %d differs from the oracle's %d" % (got, ref[1]))
+        rate, done = cpu_rate(lambda _: oracle.transport_bins(C, r, c), range(100), args.cpu_budget)
+        out["cpu_baseline"] = cpu_baseline(rate, "solves/s", 1,
+                                           "%d solve(s) of the same instance by the single-threaded C oracle "
+                                           "(successive shortest paths on the bins)" % done, oracle_cost_equal=True)
+    return out
+
+
 # ----------------------------------------------------------------------------- batch
 def bench_batch(args):
     import torch
@@ -480,7 +539,8 @@ def bench_batch(args):
         ot.ot_schedule_tune(4)
     t64, t256 = ot.ot_schedule_get()
     classes = []   # (block, max_n, order tensor) longest first within each class
-    for lo, hi, block in ((0, t64, 64), (t64, t256, 256), (t256, 1 << 30, 512)):
+    # one wavefront's class splits at n = 64, where the whole instance fits its registers
+    for lo, hi, block in ((0, min(64, t64), 64), (min(64, t64), t64, 64), (t64, t256, 256), (t256, 1 << 30, 512)):
         idx = np.nonzero((sizes > lo) & (sizes <= hi))[0]
         if len(idx) == 0:
             continue
@@ -654,7 +714,7 @@ def main():
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
     ap.add_argument("--mode", default="geometric", choices=["geometric", "small", "transport", "batch", "serve",
-                                                             "copy", "scaled", "rect"])
+                                                             "copy", "scaled", "rect", "bins"])
     ap.add_argument("--n", type=int, default=2048)
     ap.add_argument("--count", type=int, default=4096, help="batch mode: number of problems")
     ap.add_argument("--plain-steps", type=int, default=3)
@@ -673,11 +733,12 @@ def main():
     ap.add_argument("--scale", type=int, default=100, help="scaled mode: cost scaling factor s")
     ap.add_argument("--approx", type=float, default=0.0,
                     help="scaled mode: choose s for a (1 + approx)-approximation instead of --scale")
+    ap.add_argument("--mass", type=int, default=1 << 20, help="bins mode: total mass of each image")
     ap.add_argument("--rows", type=int, default=1024, help="rect mode: rows n")
     ap.add_argument("--cols", type=int, default=2048, help="rect mode: columns m")
     args = ap.parse_args()
     defaults = {"geometric": (20, 3), "small": (2000, 50), "transport": (50, 5), "batch": (5, 1), "serve": (1, 0),
-                "copy": (5, 2), "scaled": (20, 3), "rect": (10, 2)}
+                "copy": (5, 2), "scaled": (20, 3), "rect": (10, 2), "bins": (10, 2)}
     if args.steps is None:
         args.steps = defaults[args.mode][0]
     if args.warmup is None:
@@ -697,7 +758,7 @@ def main():
     else:
         out = {"geometric": bench_geometric, "small": bench_small, "transport": bench_transport,
                "batch": bench_batch, "copy": bench_copy, "scaled": bench_scaled,
-               "rect": bench_rect}[args.mode](args)
+               "rect": bench_rect, "bins": bench_bins}[args.mode](args)
     print(json.dumps(out), flush=True)
 
 

@@ -304,7 +304,11 @@ int ot_transport_dev(const int32_t *dC, const int32_t *dr, const int32_t *dc, in
  * it left before taking every published request.  Each request completes on
  * its own (the device releases a completion flag per request).  Results are
  * identical to a solve of the same request alone (the solver is
- * deterministic). */
+ * deterministic).  Every server stream (one build stream and one per queue)
+ * is created with a CU mask naming all CUs, which gives it a hardware queue
+ * of its own; such streams are blocking streams, so work the same process
+ * puts on the legacy default stream while the server runs waits for the
+ * running kernels. */
 typedef struct ot_server ot_server;
 
 /* Device cost builder used by the server, exposed on its own:
@@ -317,8 +321,7 @@ typedef struct ot_serve_cfg {
     int32_t max_inflight;      /* request slots (1..1024); 0 = 256; 1 = one request at a time */
     int32_t streams;           /* live queues per size class (n <= 512, 2048, 4096), 1..8; 0 = 1.
                                   Each queue has its own kernel stream; a request goes to the
-                                  class's queue with the fewest outstanding requests.  More than
-                                  one share the device's hardware queues with each other */
+                                  class's queue with the fewest outstanding requests */
     int32_t max_n;             /* largest n accepted (<= OT_MAX_N); 0 = OT_MAX_N */
     int32_t reserved[5];       /* must be zero */
 } ot_serve_cfg;

@@ -392,6 +392,25 @@ __global__ void k_grid_cost(const int32_t *ps, const int32_t *pt, int n, int32_t
   Cout[(size_t)i * n + j] = isqrt_round(dx * dx + dy * dy);
 }
 
+// Publish entries [first, first + count) of a serving queue: descriptors and
+// ring slots first, then (after a fence) the tail, so a workgroup that sees
+// the new tail sees the entries.  One workgroup.
+__global__ __launch_bounds__(256) void k_serve_publish(const int4 *staging, int first, int count, int qcap,
+                                                       int64_t vstride, int32_t *ring, int32_t *n, int64_t *coff,
+                                                       int64_t *voff, int32_t *tail) {
+  for (int q = threadIdx.x; q < count; q += blockDim.x) {
+    const int p = first + q;
+    const int4 e = staging[p % qcap];
+    n[e.x] = e.y;
+    coff[e.x] = (int64_t)(((uint64_t)(uint32_t)e.w << 32) | (uint32_t)e.z);
+    voff[e.x] = (int64_t)e.x * vstride;
+    ring[p % qcap] = e.x;
+  }
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) __hip_atomic_store(tail, first + count, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
@@ -508,6 +527,17 @@ hipError_t launch_rect_finish(int n, int m, bool trans, const int32_t *pq, const
 
 hipError_t launch_grid_cost(const int32_t *ps, const int32_t *pt, int n, int32_t *Cout, hipStream_t s) {
   hipLaunchKernelGGL(k_grid_cost, dim3((n + 255) / 256, n), dim3(256), 0, s, ps, pt, n, Cout);
+  return hipGetLastError();
+}
+
+}  // namespace otkm
+
+namespace otkm {
+
+hipError_t launch_serve_publish(const int4 *staging, int first, int count, int qcap, int64_t vstride, int32_t *ring,
+                                int32_t *n, int64_t *coff, int64_t *voff, int32_t *tail, hipStream_t s) {
+  hipLaunchKernelGGL(k_serve_publish, dim3(1), dim3(256), 0, s, staging, first, count, qcap, vstride, ring, n, coff,
+                     voff, tail);
   return hipGetLastError();
 }
 

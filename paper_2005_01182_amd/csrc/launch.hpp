@@ -26,11 +26,11 @@ struct BatchArgs {
   int32_t *done;          // [count] or null: done[k] = tag once instance k's outputs are visible to the host
   int32_t tag;
   // Live queue (serving): with live_tail set, order is a ring of qcap entries
-  // the host fills while the kernel runs (entry p at order[p % qcap], published
-  // once *live_tail > p, host memory), head is the first entry not yet taken
-  // (set before the launch), nq is unused, and done[k] = p + 1 for entry p.
+  // filled while the kernel runs (entry p at order[p % qcap], published once
+  // *live_tail > p; device memory written by a kernel on another stream),
+  // head is the first entry not yet taken (set before the launch), nq is
+  // unused, and done[k] = p + 1 for entry p.
   const int32_t *live_tail = nullptr;
-  const int32_t *live_stop = nullptr;  // host flag: leave when the queue is empty
   int32_t qcap = 0;
   int32_t linger = 0;                  // empty polls (a few microseconds each) before a workgroup leaves
 };
@@ -75,5 +75,11 @@ hipError_t launch_rect_finish(int n, int m, bool trans, const int32_t *pq, const
                               const int64_t *cq, const ot_stats *sq, int32_t *plan, int64_t *cost, int64_t *u,
                               int64_t *v, ot_stats *stats, hipStream_t s);
 hipError_t launch_grid_cost(const int32_t *ps, const int32_t *pt, int n, int32_t *Cout, hipStream_t s);
+// Serving: entries [first, first + count) of a live queue (each {slot, n, coff
+// low, coff high} in host memory at staging[p % qcap]) into the device
+// descriptors and ring, then the tail to first + count.
+hipError_t launch_serve_publish(const int4 *staging, int first, int count, int qcap, int64_t vstride,
+                                int32_t *ring, int32_t *n, int64_t *coff, int64_t *voff, int32_t *tail,
+                                hipStream_t s);
 
 }  // namespace otkm

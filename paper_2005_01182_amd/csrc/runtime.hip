@@ -223,6 +223,10 @@ static size_t solve_grid_bytes(int n, const Opts &o) {
   return o.wgs > 1 ? 8 * grid_ws_u64(o.wgs, o.block * cpt_for(n, o.block * o.wgs)) : 16;
 }
 
+// One wavefront holds the whole instance (wave_engine.hpp): it reads C itself,
+// so the grid-wide sweeps and the transpose are skipped and a solve is one launch.
+static bool wave_solve(int n, const Opts &o) { return o.wgs == 1 && o.block == 64 && n <= 64; }
+
 static hipError_t launch_solve(Problem &P, const Opts &o, uint64_t *gws, hipStream_t s) {
   if (o.wgs > 1) {
     P.grid_ws = gws;
@@ -299,14 +303,18 @@ int ot_assign_ex(const int32_t *C, int32_t n, const ot_options *opt, int32_t *pl
   auto *dpart = (uint64_t *)pool_get(82, init_part_bytes(n, n), &err);
   auto *db = (uint64_t *)pool_get(83, 16 * N, &err);
   if (err) return err;
-  // the streaming row sweep reads C first (from HBM when C is cold), the
-  // tiled transpose then finds it in the last-level cache
-  if ((e = launch_init_sweeps(dsolve, n, n, n, du0, drmax, dpart, db, s)) != hipSuccess) return map_hip(e);
-  if ((e = launch_transpose(dsolve, n, n, n, dCT, s)) != hipSuccess) return map_hip(e);
   Problem P;
-  P.C = dsolve; P.n = n; P.ld = n; P.CT = dCT; P.max_paths = o.max_paths; P.flags = o.flags;
+  P.C = dsolve; P.n = n; P.ld = n; P.CT = nullptr; P.max_paths = o.max_paths; P.flags = o.flags;
   P.Cout = dC; P.ldo = n; P.dscale = scale;
-  P.init_u = du0; P.init_b = db; P.init_rmax = drmax;
+  P.init_u = nullptr; P.init_b = nullptr; P.init_rmax = nullptr;
+  if (!wave_solve(n, o)) {
+    // the streaming row sweep reads C first (from HBM when C is cold), the
+    // tiled transpose then finds it in the last-level cache
+    if ((e = launch_init_sweeps(dsolve, n, n, n, du0, drmax, dpart, db, s)) != hipSuccess) return map_hip(e);
+    if ((e = launch_transpose(dsolve, n, n, n, dCT, s)) != hipSuccess) return map_hip(e);
+    P.CT = dCT;
+    P.init_u = du0; P.init_b = db; P.init_rmax = drmax;
+  }
   P.plan = dplan; P.cost = dcost; P.u = du; P.v = dv; P.stats = dstats; P.ws = dws;
   if ((e = launch_solve(P, o, dgws, s)) != hipSuccess) return map_hip(e);
   ot_stats hs;
@@ -394,14 +402,18 @@ int ot_assign_dev(const int32_t *dC, int32_t n, int32_t ld, const ot_options *op
   auto *dpart = (uint64_t *)stream_ws(s, 42, init_part_bytes(n, n), &err);
   auto *db = (uint64_t *)stream_ws(s, 43, 16 * (size_t)n, &err);
   if (err) return err;
-  // the streaming row sweep reads C first (from HBM when C is cold), the
-  // tiled transpose then finds it in the last-level cache
-  if ((e = launch_init_sweeps(dsolve, n, n, lds, du0, drmax, dpart, db, s)) != hipSuccess) return map_hip(e);
-  if ((e = launch_transpose(dsolve, n, n, lds, dCT, s)) != hipSuccess) return map_hip(e);
   Problem P;
-  P.C = dsolve; P.n = n; P.ld = lds; P.CT = dCT; P.max_paths = o.max_paths; P.flags = o.flags;
+  P.C = dsolve; P.n = n; P.ld = lds; P.CT = nullptr; P.max_paths = o.max_paths; P.flags = o.flags;
   P.Cout = dC; P.ldo = ld; P.dscale = scale;
-  P.init_u = du0; P.init_b = db; P.init_rmax = drmax;
+  P.init_u = nullptr; P.init_b = nullptr; P.init_rmax = nullptr;
+  if (!wave_solve(n, o)) {
+    // the streaming row sweep reads C first (from HBM when C is cold), the
+    // tiled transpose then finds it in the last-level cache
+    if ((e = launch_init_sweeps(dsolve, n, n, lds, du0, drmax, dpart, db, s)) != hipSuccess) return map_hip(e);
+    if ((e = launch_transpose(dsolve, n, n, lds, dCT, s)) != hipSuccess) return map_hip(e);
+    P.CT = dCT;
+    P.init_u = du0; P.init_b = db; P.init_rmax = drmax;
+  }
   P.plan = dplan; P.cost = dcost; P.u = du; P.v = dv; P.stats = dstats; P.ws = dws;
   return map_hip(launch_solve(P, o, dgws, s));
 }
@@ -579,10 +591,14 @@ int ot_assign_batch(int32_t count, const int32_t *const *C, const int32_t *n, in
     voff[k] = vtot;
     if (status[k] == OT_OK) { ctot += (int64_t)n[k] * n[k]; vtot += n[k]; }
   }
-  // size classes by workgroup width; each class runs longest-first
-  std::map<int, std::vector<int>> cls;
+  // size classes by workgroup width (one wavefront's classes split at n = 64,
+  // where the whole instance fits its registers); each class runs longest-first
+  std::map<std::pair<int, int>, std::vector<int>> cls;
   for (int k = 0; k < count; ++k)
-    if (status[k] == OT_OK) cls[schedule_block(n[k])].push_back(k);
+    if (status[k] == OT_OK) {
+      const int b = schedule_block(n[k]);
+      cls[{b, b == 64 && n[k] <= 64 ? 0 : 1}].push_back(k);
+    }
   if (cls.empty()) return OT_OK;
 
   std::lock_guard<std::mutex> lk(g_mu);
@@ -622,7 +638,7 @@ int ot_assign_batch(int32_t count, const int32_t *const *C, const int32_t *n, in
   if ((e = launch_fill_i32(head, 0, 8, s)) != hipSuccess) return map_hip(e);
   int ci = 0;
   for (auto &kv : cls) {
-    const int block = kv.first;
+    const int block = kv.first.first;
     const auto &v = kv.second;
     int max_n = 0;
     for (int k : v) max_n = std::max(max_n, n[k]);

@@ -3,13 +3,15 @@
 // Requests (n source and n target grid points) queue on the host.  A server
 // thread admits them in arrival order as request slots and device bytes free
 // up, builds each admitted request's cost matrix on the device from its
-// points (on one build stream), and publishes it into its size class's live
-// queue: a ring of request slots in host memory plus a tail counter the
-// device reads.  Each class runs one persistent batch kernel at a time; its
+// points and publishes it into its size class's live queue (a ring of request
+// slots and a tail counter in device memory, written by a small kernel on the
+// same build stream, so an entry becomes visible only after its matrix).  Each class runs one persistent batch kernel at a time; its
 // workgroups take entries from the queue while the host keeps appending, so a
 // request that arrives while its class's kernel runs joins that kernel as
 // soon as a workgroup is free, and workgroups that find the queue empty wait
-// a short, bounded while before they leave.  When the kernel has left with
+// a short, bounded while before they leave (the kernel holds several sets of
+// workgroups, so one that leaves is replaced while requests keep arriving,
+// and the kernel ends soon after they stop).  When the kernel has left with
 // entries still unclaimed (they arrived after its last workgroup looked), the
 // server launches it again from the first unclaimed entry.  The engine
 // writes each request's plan and duals straight into pinned host memory and
@@ -22,6 +24,7 @@
 #include <condition_variable>
 #include <cstring>
 #include <deque>
+#include <map>
 #include <memory>
 #include <mutex>
 #include <thread>
@@ -40,14 +43,20 @@ namespace {
 constexpr int kClasses = 3;
 constexpr int kMaxLanesPerClass = 8;
 constexpr int kDefaultLanesPerClass = 1;
-// size classes: (largest n, workgroup width).  Three kernel streams and one
-// build stream: the four hardware queues a process gets by default, so no
-// stream waits behind another's long kernel.
+// size classes: (largest n, workgroup width).  Each class's kernel runs on a
+// stream of its own and the builds on another, each on its own hardware queue
+// (dedicated_stream), so no stream waits behind another's long kernel.
 constexpr int kClassMaxN[kClasses] = {512, 2048, OT_MAX_N};
 constexpr int kClassBlock[kClasses] = {64, 256, 512};
 // Empty-queue polls before a workgroup leaves: each is a read of the tail in
 // host memory and a short sleep, a few microseconds together.
 constexpr int kLinger = 24;
+// A class's kernel is launched with this many times the workgroups that fit
+// on the device at once.  Workgroups that stay busy keep the first set
+// resident; one that finds the queue empty leaves, and a workgroup of the
+// next set starts in its place, so the kernel keeps its full width while
+// requests arrive and ends soon after they stop.
+constexpr int kGenerations = 4;
 
 int class_of(int n) {
   for (int c = 0; c < kClasses; ++c)
@@ -71,7 +80,7 @@ struct Req {
   std::vector<int64_t> u, v;
 };
 
-struct Build {  // requests of one lane whose cost matrices were queued on the build stream together
+struct Build {  // requests of one lane whose matrices and queue entries were queued on the build stream together
   hipEvent_t ev = nullptr;
   std::vector<Req *> reqs;
 };
@@ -82,11 +91,12 @@ struct Lane {  // one size class's queue and kernel stream
   hipEvent_t ev = nullptr;  // the running kernel's completion
   bool running = false;
   int64_t launches = 0;
-  int32_t tail = 0;     // entries published (host copy of *h_tail)
-  int32_t base = 0;     // first entry the next launch starts from
+  int32_t queued = 0;   // entries handed to the build stream
   int outstanding = 0;  // admitted requests of this lane not yet retired
-  int32_t *h_tail = nullptr;           // mapped: published entries, read by the device
-  int32_t *h_ring = nullptr;           // mapped: entry p -> request slot, at p % qcap
+  std::map<int32_t, int32_t> pend;     // published entries not yet retired: position -> request slot
+  int4 *h_stage = nullptr;             // mapped: entry p's {slot, n, coff} at p % qcap, read by the publish kernel
+  int32_t *d_ring = nullptr;           // entry p -> request slot, at p % qcap
+  int32_t *d_tail = nullptr;           // published entries
   int32_t *d_head = nullptr, *d_ws = nullptr;
   std::deque<Build> building;
 };
@@ -103,9 +113,11 @@ struct ot_server {
   int32_t *h_pts = nullptr;                   // pinned staging [slots][4 maxn]
   int32_t *h_plan = nullptr;                  // mapped [slots][maxn]
   int64_t *h_u = nullptr, *h_v = nullptr;     // mapped [slots][maxn]
-  // mapped per request slot: descriptor (read by the device) and results
-  int64_t *h_coff = nullptr, *h_voff = nullptr, *h_cost = nullptr;
-  int32_t *h_n = nullptr, *h_done = nullptr, *h_stop = nullptr;
+  // per request slot: the descriptor on the device, the results mapped
+  int64_t *d_coff = nullptr, *d_voff = nullptr;
+  int32_t *d_n = nullptr;
+  int64_t *h_cost = nullptr;
+  int32_t *h_done = nullptr;
   ot_stats *h_stats = nullptr;
   std::vector<int> free_slots;
   std::vector<hipEvent_t> free_events;
@@ -140,8 +152,8 @@ void free_server(ot_server *s) {
     for (auto &b : L.building) hipEventDestroy(b.ev);
     if (L.ev) hipEventDestroy(L.ev);
     if (L.s) hipStreamDestroy(L.s);
-    hipFree(L.d_head); hipFree(L.d_ws);
-    hipHostFree(L.h_tail); hipHostFree(L.h_ring);
+    hipFree(L.d_head); hipFree(L.d_ws); hipFree(L.d_ring); hipFree(L.d_tail);
+    hipHostFree(L.h_stage);
   }
   for (hipEvent_t e : s->free_events) hipEventDestroy(e);
   if (s->sb) hipStreamDestroy(s->sb);
@@ -151,8 +163,8 @@ void free_server(ot_server *s) {
   hipHostFree(s->h_plan);
   hipHostFree(s->h_u);
   hipHostFree(s->h_v);
-  hipHostFree(s->h_coff); hipHostFree(s->h_voff); hipHostFree(s->h_cost);
-  hipHostFree(s->h_n); hipHostFree(s->h_done); hipHostFree(s->h_stop); hipHostFree(s->h_stats);
+  hipFree(s->d_coff); hipFree(s->d_voff); hipFree(s->d_n);
+  hipHostFree(s->h_cost); hipHostFree(s->h_done); hipHostFree(s->h_stats);
   delete s;
 }
 
@@ -163,24 +175,31 @@ T *dptr(T *host) {  // device address of mapped host memory
   return (T *)d;
 }
 
-// (Re)start lane li's kernel from entry L.base.  Requires s->mu.
-int launch_lane(ot_server *s, int li) {
+// A stream on its own hardware queue.  Streams beyond the runtime's hardware
+// queue limit share queues, and work on a shared queue runs in submission
+// order across its streams: a class's long-running kernel would hold up the
+// builds and the other classes' kernels queued behind it.  A stream created
+// with a CU mask always gets a queue of its own; the mask here names every CU.
+hipError_t dedicated_stream(hipStream_t *st, int cus) {
+  std::vector<uint32_t> mask((size_t)(cus + 31) / 32, 0xffffffffu);
+  if (cus % 32) mask.back() = (1u << (cus % 32)) - 1;
+  return hipExtStreamCreateWithCUMask(st, (uint32_t)mask.size(), mask.data());
+}
+
+// (Re)start lane li's kernel from entry `base`.  Requires s->mu.
+int launch_lane(ot_server *s, int li, int32_t base) {
   Lane &L = s->lanes[li];
   hipError_t e;
-  if ((e = launch_fill_i32(L.d_head, L.base, 1, L.s)) != hipSuccess) return map_hip(e);
-  const int waiting = L.tail - L.base;
-  // room for the waiting entries and as many again for requests that arrive meanwhile
-  const int grid = std::max(1, std::min(L.grid_max, std::max(8, 2 * waiting)));
+  if ((e = launch_fill_i32(L.d_head, base, 1, L.s)) != hipSuccess) return map_hip(e);
+  const int grid = L.grid_max * kGenerations;
   BatchArgs A;
   A.C = (const int32_t *)s->arena_base;
-  A.coff = dptr(s->h_coff); A.n = dptr(s->h_n); A.voff = dptr(s->h_voff); A.order = dptr(L.h_ring);
+  A.coff = s->d_coff; A.n = s->d_n; A.voff = s->d_voff; A.order = L.d_ring;
   A.count = s->slots; A.nq = 0; A.max_n = L.max_n; A.max_paths = 0;
   A.plan = dptr(s->h_plan); A.cost = dptr(s->h_cost); A.u = dptr(s->h_u); A.v = dptr(s->h_v);
   A.stats = dptr(s->h_stats); A.ws = L.d_ws; A.head = L.d_head; A.done = dptr(s->h_done); A.tag = 0;
-  A.live_tail = dptr(L.h_tail); A.live_stop = dptr(s->h_stop); A.qcap = s->qcap; A.linger = kLinger;
-  if (!A.coff || !A.n || !A.voff || !A.order || !A.plan || !A.cost || !A.u || !A.v || !A.stats || !A.done ||
-      !A.live_tail || !A.live_stop)
-    return OT_EDEVICE;
+  A.live_tail = L.d_tail; A.qcap = s->qcap; A.linger = kLinger;
+  if (!A.plan || !A.cost || !A.u || !A.v || !A.stats || !A.done) return OT_EDEVICE;
   if ((e = launch_assign_batch(A, L.block, grid, L.s)) != hipSuccess) return map_hip(e);
   if ((e = hipEventRecord(L.ev, L.s)) != hipSuccess) return map_hip(e);
   L.running = true;
@@ -212,6 +231,7 @@ bool retire(ot_server *s) {
     r->t_done = s->now();
     r->done = true;
     --L.outstanding;
+    L.pend.erase(r->pos);
     s->arena->release(r->off, r->abytes);
     s->free_slots.push_back(r->slot);
     s->inflight_bytes -= r->bytes;
@@ -235,13 +255,6 @@ bool retire(ot_server *s) {
     }
     L.running = false;
     changed = true;
-    // the kernel took a prefix of the published entries and completed each
-    // one it took: the next launch starts after the last completed one
-    while (L.base < L.tail) {
-      const int32_t sl = L.h_ring[L.base % s->qcap];
-      if (__atomic_load_n(&s->h_done[sl], __ATOMIC_ACQUIRE) != L.base + 1) break;
-      ++L.base;
-    }
   }
   return changed;
 }
@@ -296,6 +309,19 @@ bool admit(ot_server *s) {
         return any;
       }
     }
+    // queue entries, published on the device after the matrices above
+    const int32_t first = L.queued;
+    for (Req *r : batch[li]) {
+      r->pos = L.queued++;
+      L.h_stage[r->pos % s->qcap] = make_int4(r->slot, r->n, (int)(uint32_t)(r->off / 4),
+                                             (int)(uint32_t)((uint64_t)(r->off / 4) >> 32));
+    }
+    std::atomic_thread_fence(std::memory_order_release);
+    if ((e = launch_serve_publish(dptr(L.h_stage), first, L.queued - first, s->qcap, (int64_t)M, L.d_ring, s->d_n,
+                                  s->d_coff, s->d_voff, L.d_tail, s->sb)) != hipSuccess) {
+      s->fatal = map_hip(e);
+      return any;
+    }
     Build b;
     if (!s->free_events.empty()) {
       b.ev = s->free_events.back();
@@ -311,42 +337,37 @@ bool admit(ot_server *s) {
   return any;
 }
 
-// Publish the requests whose cost matrices are built, and start the kernel of
-// every lane with unclaimed entries and no kernel running.  Requires s->mu.
+// Take note of the requests whose matrices and queue entries are on the
+// device (running from now on), and start the kernel of every lane with
+// unclaimed entries and no kernel running.  Requires s->mu.
 bool publish(ot_server *s) {
   bool any = false;
-  const size_t M = (size_t)s->maxn;
   for (int li = 0; li < s->nlanes(); ++li) {
     Lane &L = s->lanes[li];
-    bool published = false;
     while (!L.building.empty()) {
       Build &b = L.building.front();
       const hipError_t q = hipEventQuery(b.ev);
       if (q == hipErrorNotReady) break;
       if (q != hipSuccess) { s->fatal = map_hip(q); return any; }
       for (Req *r : b.reqs) {
-        const int sl = r->slot;
-        s->h_coff[sl] = r->off / 4;
-        s->h_voff[sl] = (int64_t)sl * (int64_t)M;
-        s->h_n[sl] = r->n;
-        r->pos = L.tail;
         r->launch = L.running ? L.launches : -1;
-        L.h_ring[L.tail % s->qcap] = sl;
-        ++L.tail;
         s->running.push_back(r);
+        L.pend[r->pos] = r->slot;
       }
       s->free_events.push_back(b.ev);
       L.building.pop_front();
-      published = true;
-    }
-    if (published) {
-      // the descriptors and ring entries above become visible before the tail
-      std::atomic_thread_fence(std::memory_order_release);
-      __atomic_store_n(L.h_tail, L.tail, __ATOMIC_RELEASE);
       any = true;
     }
-    if (!L.running && L.base < L.tail) {
-      const int rc = launch_lane(s, li);
+    if (L.running) continue;
+    // An ended kernel took a prefix of the entries and completed each one it
+    // took, so with no kernel running the flags are final: the next launch
+    // starts at the first published entry without its flag (entries not yet
+    // retired keep their slots, so their flags are theirs).
+    int32_t base = -1;
+    for (const auto &pe : L.pend)
+      if (__atomic_load_n(&s->h_done[pe.second], __ATOMIC_ACQUIRE) != pe.first + 1) { base = pe.first; break; }
+    if (base >= 0) {
+      const int rc = launch_lane(s, li, base);
       if (rc != OT_OK) { s->fatal = rc; return any; }
       any = true;
     }
@@ -368,7 +389,14 @@ void worker_main(ot_server *s) {
       for (int li = 0; li < s->nlanes(); ++li) idle = idle && !s->lanes[li].running && s->lanes[li].building.empty();
       if (idle) break;
     }
-    if (!progressed) s->cv_work.wait_for(lk, std::chrono::microseconds(20));
+    if (!progressed) {
+      s->cv_work.wait_for(lk, std::chrono::microseconds(20));
+    } else {
+      // let submit, poll and stats in between busy passes: the mutex is not fair
+      lk.unlock();
+      std::this_thread::yield();
+      lk.lock();
+    }
   }
   s->cv_done.notify_all();
 }
@@ -430,15 +458,14 @@ int ot_serve_open(ot_server **out, const ot_serve_cfg *cfg_in) {
   chk(hipHostMalloc(&s->h_plan, 4 * M * SL, mapped));
   chk(hipHostMalloc(&s->h_u, 8 * M * SL, mapped));
   chk(hipHostMalloc(&s->h_v, 8 * M * SL, mapped));
-  chk(hipHostMalloc(&s->h_coff, 8 * SL, mapped));
-  chk(hipHostMalloc(&s->h_voff, 8 * SL, mapped));
+  chk(hipMalloc(&s->d_coff, 8 * SL));
+  chk(hipMalloc(&s->d_voff, 8 * SL));
+  chk(hipMalloc(&s->d_n, 4 * SL));
   chk(hipHostMalloc(&s->h_cost, 8 * SL, mapped));
-  chk(hipHostMalloc(&s->h_n, 4 * SL, mapped));
   chk(hipHostMalloc(&s->h_done, 4 * SL, mapped));
-  chk(hipHostMalloc(&s->h_stop, 64, mapped));
   chk(hipHostMalloc(&s->h_stats, sizeof(ot_stats) * SL, mapped));
   s->lpc = cfg.streams;
-  chk(hipStreamCreateWithFlags(&s->sb, hipStreamNonBlocking));
+  chk(dedicated_stream(&s->sb, s->cus));
   for (int li = 0; li < s->nlanes() && e == hipSuccess; ++li) {
     Lane &L = s->lanes[li];
     L.cls = li / s->lpc;
@@ -447,12 +474,14 @@ int ot_serve_open(ot_server **out, const ot_serve_cfg *cfg_in) {
     const int occ = batch_occupancy(L.block, L.max_n);
     if (occ <= 0) { e = hipErrorInvalidValue; break; }
     L.grid_max = std::max(1, std::min<int>(s->slots, occ * s->cus));
-    chk(hipStreamCreateWithFlags(&L.s, hipStreamNonBlocking));
+    chk(dedicated_stream(&L.s, s->cus));
     chk(hipEventCreateWithFlags(&L.ev, hipEventDisableTiming));
     chk(hipMalloc(&L.d_head, 256));
-    chk(hipMalloc(&L.d_ws, 4 * ws_ints(L.max_n) * (size_t)L.grid_max));
-    chk(hipHostMalloc(&L.h_tail, 64, mapped));
-    chk(hipHostMalloc(&L.h_ring, 4 * (size_t)s->qcap, mapped));
+    chk(hipMalloc(&L.d_ws, 4 * ws_ints(L.max_n) * (size_t)L.grid_max * kGenerations));
+    chk(hipMalloc(&L.d_ring, 4 * (size_t)s->qcap));
+    chk(hipMalloc(&L.d_tail, 256));
+    chk(hipHostMalloc(&L.h_stage, sizeof(int4) * (size_t)s->qcap, mapped));
+    if (e == hipSuccess) chk(hipMemset(L.d_tail, 0, 256));
   }
   if (e != hipSuccess) {
     const int rc = map_hip(e);
@@ -460,8 +489,6 @@ int ot_serve_open(ot_server **out, const ot_serve_cfg *cfg_in) {
     return rc;
   }
   std::memset(s->h_done, 0, 4 * SL);
-  std::memset(s->h_stop, 0, 64);
-  for (int li = 0; li < s->nlanes(); ++li) std::memset(s->lanes[li].h_tail, 0, 64);
   s->arena.reset(new otkm::Arena(cfg.hbm_budget_bytes));
   for (int k = s->slots - 1; k >= 0; --k) s->free_slots.push_back(k);
   s->worker = std::thread(worker_main, s);
@@ -535,8 +562,6 @@ int ot_serve_close(ot_server *s) {
   }
   s->cv_work.notify_all();
   if (s->worker.joinable()) s->worker.join();
-  // kernels still waiting on an empty queue leave at once
-  __atomic_store_n(s->h_stop, 1, __ATOMIC_RELEASE);
   const int rc = s->fatal;
   free_server(s);
   return rc;

@@ -6,8 +6,12 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <atomic>
+
 #include "engine.hpp"
 #include "launch.hpp"
+#include "wave_engine.hpp"
 
 namespace otkm {
 
@@ -18,6 +22,13 @@ template <int BLOCK, int CPT>
 __global__ __launch_bounds__(BLOCK) void k_assign_one(Problem P, const int32_t *gate) {
   extern __shared__ __align__(16) char smem[];
   if (gate && *gate != 0) return;  // an earlier stage of this pipeline already failed
+  if constexpr (BLOCK == 64 && CPT == 1) {
+    if (P.nr == 0 || P.nr == P.n) {  // square, n <= 64: all state in one wavefront's registers
+      WaveEngine W;
+      W.run(P, smem);
+      return;
+    }
+  }
   Engine<BLOCK, CPT, (BLOCK <= 512), false, true> E;  // at 1024 threads the registers are too few for LONG
   E.run(P, smem);
 }
@@ -56,36 +67,35 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2))) void
         if (idx < A.nq) k = A.order ? A.order[idx] : idx;
         else idx = -1;
       } else {
-        // Live queue: the host publishes entries [0, *live_tail) while the
-        // kernel runs; an entry is taken by advancing the head past it.  An
-        // empty queue is polled `linger` times (a short sleep each) before the
-        // workgroup leaves, or not at all once the host raised the stop flag:
-        // every wait is bounded.
+        // Live queue: entries [0, *live_tail) are published (by a kernel on
+        // another stream) while this one runs; an entry is taken by advancing
+        // the head past it.  An empty queue is polled `linger` times (a short
+        // sleep each) before the workgroup leaves: every wait is bounded.
         for (int spin = 0;; ++spin) {
           const int h = __hip_atomic_load(A.head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          const int t = __hip_atomic_load(A.live_tail, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
+          const int t = __hip_atomic_load(A.live_tail, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
           if (h < t) {
             int hh = h;
             if (__hip_atomic_compare_exchange_strong(A.head, &hh, h + 1, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
                                                      __HIP_MEMORY_SCOPE_AGENT)) {
               idx = h;
-              k = __hip_atomic_load(&A.order[h % A.qcap], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+              k = __hip_atomic_load(&A.order[h % A.qcap], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
               break;
             }
             continue;
           }
-          if (spin >= A.linger || __hip_atomic_load(A.live_stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM)) break;
+          if (spin >= A.linger) break;
           __builtin_amdgcn_s_sleep(63);
         }
       }
-      // the descriptor, read once (system scope when the host writes it while the kernel runs)
+      // the descriptor, read once (device scope when it was written while the kernel runs)
       int n = 0;
       int64_t coff = 0, voff = 0;
       if (idx >= 0 && (unsigned)k < (unsigned)A.count) {
         if (live) {
-          n = __hip_atomic_load(&A.n[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-          coff = __hip_atomic_load(&A.coff[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-          voff = __hip_atomic_load(&A.voff[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+          n = __hip_atomic_load(&A.n[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          coff = __hip_atomic_load(&A.coff[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          voff = __hip_atomic_load(&A.voff[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         } else {
           n = A.n[k];
           coff = A.coff[k];
@@ -134,8 +144,13 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2))) void
     P.v = A.v ? A.v + voff : nullptr;
     P.stats = A.stats ? A.stats + k : nullptr;
     P.ws = ws;
-    Engine<BLOCK, CPT> E;
-    E.run(P, smem);
+    if constexpr (BLOCK == 64 && CPT == 1) {  // every instance has n <= 64: one wavefront's registers
+      WaveEngine W;
+      W.run(P, smem);
+    } else {
+      Engine<BLOCK, CPT> E;
+      E.run(P, smem);
+    }
     if (A.done) {
       // outputs may live in host memory: make every thread's writes visible
       // system-wide before the completion flag is released
@@ -152,15 +167,34 @@ __global__ void k_fill_u64(uint64_t *p, uint64_t value, int64_t count);
 // ---------------------------------------------------------------------------
 // launch helpers
 // ---------------------------------------------------------------------------
-template <typename K>
-static hipError_t allow_lds(K kernel, size_t bytes) {
-  return hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+// A kernel's dynamic LDS limit is raised only when a launch needs more than
+// it was last raised to, so repeated launches cost no extra runtime call.
+template <auto KERNEL>
+static hipError_t allow_lds(size_t bytes) {
+  static std::atomic<size_t> allowed{0};
+  if (bytes <= allowed.load(std::memory_order_acquire)) return hipSuccess;
+  const hipError_t e = hipFuncSetAttribute((const void *)KERNEL, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  if (e == hipSuccess) {
+    size_t cur = allowed.load(std::memory_order_relaxed);
+    while (cur < bytes && !allowed.compare_exchange_weak(cur, bytes, std::memory_order_release)) {
+    }
+  }
+  return e;
+}
+
+// LDS of a kernel of width B for instances of at most n columns: the
+// workgroup engine's layout, or the wave engine's copy of C when larger.
+template <int B>
+static size_t solve_lds(int n) {
+  size_t lds = lds_layout(n).total;
+  if (B == 64) lds = std::max(lds, wave_lds_bytes(std::min(n, kWaveMaxN)));
+  return lds;
 }
 
 template <int B, int CPT>
 static hipError_t one(const Problem &P, const int32_t *gate, hipStream_t s) {
-  const size_t lds = lds_layout(P.n).total;
-  hipError_t e = allow_lds(k_assign_one<B, CPT>, lds);
+  const size_t lds = solve_lds<B>(P.n);
+  hipError_t e = allow_lds<k_assign_one<B, CPT>>(lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_assign_one<B, CPT>), dim3(1), dim3(B), lds, s, P, gate);
   return hipGetLastError();
@@ -169,7 +203,7 @@ static hipError_t one(const Problem &P, const int32_t *gate, hipStream_t s) {
 template <int B, int CPT>
 static hipError_t grid(const Problem &P, int wgs, hipStream_t s) {
   const size_t lds = lds_layout(P.n).total;
-  hipError_t e = allow_lds(k_assign_grid<B, CPT>, lds);
+  hipError_t e = allow_lds<k_assign_grid<B, CPT>>(lds);
   if (e != hipSuccess) return e;
   // every tag word must start below the first level
   hipLaunchKernelGGL(k_fill_u64, dim3(16), dim3(256), 0, s, P.grid_ws, (uint64_t)0,
@@ -181,8 +215,8 @@ static hipError_t grid(const Problem &P, int wgs, hipStream_t s) {
 
 template <int B, int CPT>
 static hipError_t batch(const BatchArgs &A, int grid, hipStream_t s) {
-  const size_t lds = lds_layout(A.max_n).total;
-  hipError_t e = allow_lds(k_assign_batch<B, CPT>, lds);
+  const size_t lds = solve_lds<B>(A.max_n);
+  hipError_t e = allow_lds<k_assign_batch<B, CPT>>(lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_assign_batch<B, CPT>), dim3(grid), dim3(B), lds, s, A);
   return hipGetLastError();
@@ -191,8 +225,8 @@ static hipError_t batch(const BatchArgs &A, int grid, hipStream_t s) {
 template <int B, int CPT>
 static int occ(int max_n) {
   int blocks = 0;
-  const size_t lds = lds_layout(max_n).total;
-  if (allow_lds(k_assign_batch<B, CPT>, lds) != hipSuccess) return 0;
+  const size_t lds = solve_lds<B>(max_n);
+  if (allow_lds<k_assign_batch<B, CPT>>(lds) != hipSuccess) return 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, (const void *)k_assign_batch<B, CPT>, B, lds) != hipSuccess)
     return 0;
   return blocks;

@@ -1,0 +1,309 @@
+// wave_engine.hpp -- batched Kuhn-Munkres for instances of at most 64 rows,
+// on one wavefront with every piece of state in registers.
+//
+// The method and every choice it makes are the workgroup engine's (Engine in
+// engine.hpp): trees from every free row (or from the first max_paths rows),
+// exact per-column top-2 keys of (reduced cost + level, row) from distinct
+// trees, a level D that rises to the smallest key, columns settled at D, one
+// path per tree that reached a free column (its smallest such column), the
+// forest kept across augmentations with the duals of finished trees
+// materialised, stale keys recomputed when they could be the next minimum.
+// So the results are the same, bit for bit.  The organisation differs:
+//   * lane j holds column j's state and lane i row i's (dual, match, tree),
+//     so a row that joins a tree, a path flip or a finished tree is a few
+//     lane selects, ballots and cross-lane reads: no barrier and no LDS
+//     atomic anywhere in the level loop;
+//   * the frontier, the forest and the live trees are 64-bit lane masks;
+//   * the cost matrix sits in LDS (rows padded to n + 1 words, so a row and a
+//     column both read without bank conflicts): a sweep row is one LDS read
+//     per lane, and a stale column is recomputed by all 64 lanes at once (one
+//     row each) with a butterfly top-2 merge.
+#pragma once
+
+#include "engine.hpp"
+
+namespace otkm {
+
+constexpr int kWaveMaxN = 64;
+
+// LDS bytes of the wave engine for an n x n instance.
+__host__ __device__ inline size_t wave_lds_bytes(int n) { return (size_t)n * (size_t)(n + 1) * 4; }
+
+struct WaveEngine {
+  int n, lane;
+  bool cl;  // this lane holds a column and a row of the instance
+  // column state (lane j)
+  uint64_t k1, k2;
+  int t1, t2, ctree, par, mcol, dcol;
+  int32_t vj;
+  bool vis, stl;
+  bool bad;  // an invariant failed in this lane (reported as OT_EINTERNAL)
+  // row state (lane i)
+  int64_t h;   // u_i - D_i in a tree, u_i outside
+  int mrow, rtree, bend;
+  // lane masks
+  uint64_t alive, forest, front;
+
+  static __device__ __forceinline__ int bit_of(uint64_t m) { return __builtin_ctzll(m); }
+  __device__ __forceinline__ bool alive_tree(int t) const { return t >= 0 && ((alive >> t) & 1ull); }
+
+  // Fold rows `rows` (a uniform mask) into the column keys.
+  __device__ __forceinline__ void sweep(const int32_t *Cs, int S, uint64_t rows) {
+    while (rows) {
+      // four rows' LDS reads in flight at a time
+      int r[4];
+      int32_t c[4];
+      int cnt = 0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        r[q] = rows ? bit_of(rows) : -1;
+        if (rows) { rows &= rows - 1; ++cnt; }
+        c[q] = (r[q] >= 0 && cl) ? Cs[r[q] * S + lane] : 0;
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        if (q >= cnt) break;
+        const int64_t hr = (int64_t)readlane64((uint64_t)h, r[q]);
+        const int tr = __builtin_amdgcn_readlane(rtree, r[q]);
+        const int64_t val = (int64_t)c[q] - hr - vj;
+        if (cl) {
+          bad |= val < 0;  // a negative reduced cost would mean infeasible duals
+          const uint64_t key = pack(val < 0 ? 0 : val, r[q]);
+          const bool lt = key < k1;
+          top2_push(k1, t1, k2, t2, key, tr);
+          if (lt) stl = false;  // the best key now comes from a live tree
+        }
+      }
+    }
+  }
+
+  // Exact top-2 of column j over the forest rows, every lane taking one row;
+  // the result is uniform.
+  __device__ __forceinline__ void column_top2(const int32_t *Cs, int S, int j, uint64_t &a1, int &ta1, uint64_t &a2,
+                                              int &ta2) {
+    const int32_t vjj = __builtin_amdgcn_readlane(vj, j);
+    const bool in = cl && ((forest >> lane) & 1ull);
+    const int32_t c = in ? Cs[lane * S + j] : 0;
+    a1 = kInf; a2 = kInf; ta1 = -1; ta2 = -1;
+    if (in) {
+      const int64_t val = (int64_t)c - h - vjj;
+      bad |= val < 0;
+      a1 = pack(val < 0 ? 0 : val, lane);
+      ta1 = rtree;
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      const uint64_t b1 = __shfl_xor(a1, off, 64), b2 = __shfl_xor(a2, off, 64);
+      const int tb1 = __shfl_xor(ta1, off, 64), tb2 = __shfl_xor(ta2, off, 64);
+      top2_merge(a1, ta1, a2, ta2, b1, tb1, b2, tb2);
+    }
+  }
+
+  __device__ __forceinline__ void run(const Problem &P, char *smem) {
+    n = P.n;
+    lane = threadIdx.x & 63;
+    cl = lane < n;
+    const int S = n + 1;
+    int32_t *Cs = (int32_t *)smem;
+    // ---- C into LDS (row i at Cs[i * S])
+    for (int i0 = 0; i0 < n; i0 += 8) {
+      int32_t c[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) c[q] = (i0 + q < n && cl) ? P.C[(size_t)(i0 + q) * (size_t)P.ld + lane] : 0;
+#pragma unroll
+      for (int q = 0; q < 8; ++q)
+        if (i0 + q < n && cl) Cs[(i0 + q) * S + lane] = c[q];
+    }
+    __syncthreads();
+    // ---- u_i = min_j C_ij (lane i) and the cost range
+    int mn = 0x7fffffff, mx = (int)0x80000000;
+    if (cl)
+      for (int k = 0; k < n; ++k) {
+        const int32_t c = Cs[lane * S + k];
+        mn = min(mn, c);
+        mx = max(mx, c);
+      }
+    const int gmin = wave_min_i32(cl ? mn : 0x7fffffff), gmax = wave_max_i32(cl ? mx : (int)0x80000000);
+    if ((int64_t)gmax - (int64_t)gmin > 0x7fffffffll) {
+      if (P.stats && lane == 0) { ot_stats s = {}; s.status = OT_ERANGE; *P.stats = s; }
+      return;
+    }
+    h = cl ? (int64_t)mn : 0;
+    // ---- v_j = min_i (C_ij - u_i) and the two best rows of column j
+    uint64_t b1 = kInf, b2 = kInf;
+    for (int i = 0; i < n; ++i) {
+      const int64_t ui = (int64_t)readlane64((uint64_t)h, i);
+      const int32_t c = cl ? Cs[i * S + lane] : 0;
+      const uint64_t key = pack((int64_t)c - ui, i);
+      if (key < b1) { b2 = b1; b1 = key; }
+      else if (key < b2) b2 = key;
+    }
+    const int K = (P.max_paths <= 0 || P.max_paths > n) ? n : P.max_paths;
+    vj = cl ? (int32_t)kval(b1) : 0;
+    k1 = kInf; k2 = kInf; t1 = -1; t2 = -1;
+    if (cl && K == n) {
+      k1 = pack(kval(b1) - vj, krow(b1));
+      t1 = krow(b1);
+      if (b2 != kInf) { k2 = pack(kval(b2) - vj, krow(b2)); t2 = krow(b2); }
+    }
+    vis = false; stl = false; bad = false; dcol = 0; ctree = -1; par = -1; mcol = -1;
+    mrow = -1; bend = kNoEnd;
+    const uint64_t roots = K == 64 ? ~0ull : ((1ull << K) - 1);
+    rtree = (cl && lane < K) ? lane : -1;
+    alive = roots;
+    forest = roots;
+    front = K == n ? 0 : roots;  // with every row a root the keys above already hold the first sweep
+
+    int64_t st_levels = 0, st_dual = 0, st_aug = 0, st_paths = 0, st_rows = 2 * (int64_t)n, st_gath = 0;
+    int64_t st_resw = 0, st_refresh = 0, st_rcols = 0;
+    int err = 0;
+    int nfree = n, nalive = K, cursor = K;
+    int64_t D = 0;
+    const int64_t watchdog = (int64_t)(n + 2) * (int64_t)(n + 2) + 64;
+    const int gcap = gather_cap(n);
+
+    while (nfree > 0) {
+      // (1) fold the rows that joined last step into the keys
+      st_rows += __builtin_popcountll(front);
+      sweep(Cs, S, front);
+      front = 0;
+      // (2) smallest key over unreached columns (stale keys are lower bounds)
+      const bool open = cl && !vis && k1 != kInf;
+      uint64_t mv = wave_min_u64(open && !stl ? k1 : kInf) , ms = wave_min_u64(open && stl ? k1 : kInf);
+      if (ms != kInf && (mv == kInf || kval(ms) <= kval(mv))) {
+        const int64_t lim = mv == kInf ? INT64_MAX : kval(mv);
+        uint64_t R = __builtin_amdgcn_ballot_w64(open && stl && kval(k1) <= lim);
+        const int g = __builtin_popcountll(R);
+        ++st_refresh;
+        st_rcols += g;
+        if (g > gcap) {
+          // too many: one sweep of every forest row fixes all keys
+          if (cl) { k1 = kInf; k2 = kInf; t1 = -1; t2 = -1; }
+          stl = false;
+          ++st_resw;
+          st_rows += __builtin_popcountll(forest);
+          sweep(Cs, S, forest);
+        } else {
+          st_gath += (int64_t)g * __builtin_popcountll(forest);
+          while (R) {
+            const int j = bit_of(R);
+            R &= R - 1;
+            uint64_t a1, a2;
+            int ta1, ta2;
+            column_top2(Cs, S, j, a1, ta1, a2, ta2);
+            if (lane == j) { k1 = a1; t1 = ta1; k2 = a2; t2 = ta2; stl = false; }
+          }
+        }
+        const bool open2 = cl && !vis && k1 != kInf;
+        mv = wave_min_u64(open2 && !stl ? k1 : kInf);
+      }
+      if (mv == kInf) { err = OT_EINTERNAL; break; }
+      const int64_t level = kval(mv);
+      if (level > D) { D = level; ++st_dual; }
+      if (++st_levels > watchdog || D > 0x7ffffffell) { err = OT_EINTERNAL; break; }
+
+      // (3) settle every unreached column at the current level
+      const bool settle = cl && !vis && !stl && k1 != kInf && kval(k1) == D;
+      const uint64_t Sm = __builtin_amdgcn_ballot_w64(settle);
+      if (settle) { vis = true; dcol = (int32_t)D; ctree = t1; par = krow(k1); }
+      // matched rows of settled columns join their column's tree
+      const int src = (cl && mrow >= 0) ? mrow : lane;
+      const int ttree = __builtin_amdgcn_ds_bpermute(src * 4, t1);
+      const bool joins = cl && mrow >= 0 && ((Sm >> mrow) & 1ull);
+      if (joins) { rtree = ttree; h -= D; }
+      const uint64_t J = __builtin_amdgcn_ballot_w64(joins);
+      front |= J;
+      forest |= J;
+      // free settled columns end paths: per tree its smallest such column
+      uint64_t E = Sm & __builtin_amdgcn_ballot_w64(cl && mcol < 0), augm = 0;
+      while (E) {
+        const int j = bit_of(E);
+        E &= E - 1;
+        const int tr = __builtin_amdgcn_readlane(t1, j);
+        if (!((augm >> tr) & 1ull)) {
+          augm |= 1ull << tr;
+          if (lane == tr) bend = j;
+        }
+      }
+      if (augm) {
+        // (4) flip one path per such tree (trees are disjoint)
+        const int naug = __builtin_popcountll(augm);
+        for (uint64_t A = augm; A; A &= A - 1) {
+          const int tr = bit_of(A);
+          int j = __builtin_amdgcn_readlane(bend, tr);
+          for (int steps = 0;; ++steps) {
+            if (steps > n || (unsigned)j >= (unsigned)n) { err = OT_EINTERNAL; break; }
+            const int p = __builtin_amdgcn_readlane(par, j);
+            if ((unsigned)p >= (unsigned)n) { err = OT_EINTERNAL; break; }
+            const int before = __builtin_amdgcn_readlane(mrow, p);
+            if (lane == p) mrow = j;
+            if (lane == j) mcol = p;
+            if (p == tr) break;
+            j = before;
+          }
+          if (lane == tr) bend = kNoEnd;
+        }
+        if (err) break;
+        alive &= ~augm;
+        ++st_aug;
+        st_paths += naug;
+        nfree -= naug;
+        nalive -= naug;
+        // (5) rows and columns of finished trees leave the forest with their duals materialised
+        if (cl && rtree >= 0 && !alive_tree(rtree)) { h += D; rtree = -1; }
+        forest = __builtin_amdgcn_ballot_w64(cl && rtree >= 0);
+        front &= forest;  // rows that joined this step a tree that just finished
+        if (cl) {
+          if (vis && !alive_tree(ctree)) {
+            const int64_t d = D - dcol;
+            vj -= (int32_t)d;
+            const uint64_t sh = (uint64_t)d << kRowBits;
+            if (k1 != kInf) k1 += sh;
+            if (k2 != kInf) k2 += sh;
+            vis = false;
+            ctree = -1;
+          }
+          if (t1 >= 0 && !alive_tree(t1)) { k1 = k2; t1 = t2; t2 = -1; }
+          else if (t2 >= 0 && !alive_tree(t2)) t2 = -1;
+          if (nalive == 0) { k1 = kInf; k2 = kInf; t1 = -1; t2 = -1; }
+          stl = !(k1 == kInf || alive_tree(t1));
+        }
+        // (6) with a tree cap, start new trees from the next free rows
+        const int need = min(K - nalive, n - cursor);
+        if (need > 0) {
+          const uint64_t nr = (need == 64 ? ~0ull : ((1ull << need) - 1)) << cursor;
+          if ((nr >> lane) & 1ull) { rtree = lane; h -= D; }
+          alive |= nr;
+          forest |= nr;
+          front |= nr;
+          cursor += need;
+          nalive += need;
+        }
+      }
+    }
+    if (err == 0 && __builtin_amdgcn_ballot_w64(bad) != 0) err = OT_EINTERNAL;
+
+    if (err == 0) {
+      const int32_t *Cr = P.Cout ? P.Cout : P.C;
+      const size_t ldr = P.Cout ? (size_t)P.ldo : (size_t)P.ld;
+      int64_t part = 0;
+      if (cl) {
+        P.plan[lane] = mrow;
+        if (P.u) P.u[lane] = h * P.dscale;
+        if (P.v) P.v[lane] = (int64_t)vj * P.dscale;
+        part = (mrow >= 0 && mrow < n) ? (int64_t)Cr[(size_t)lane * ldr + mrow] : 0;
+      }
+      part = wave_sum_i64(part);
+      if (lane == 0) *P.cost = part;
+    }
+    if (P.stats && lane == 0) {
+      ot_stats s = {};
+      s.levels = st_levels; s.dual_adjusts = st_dual; s.aug_events = st_aug; s.paths = st_paths;
+      s.rows_swept = st_rows; s.gathers = st_gath; s.resweeps = st_resw; s.status = err;
+      s.refreshes = st_refresh; s.refresh_cols = st_rcols;
+      *P.stats = s;
+    }
+  }
+};
+
+}  // namespace otkm

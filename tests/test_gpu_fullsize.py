@@ -67,7 +67,7 @@ def test_embedding_batch_full_size_graph_replay(otkm_gpu, embedding4096):
     st = otkm_gpu.stats_tensor(count)
     t64, t256 = otkm_gpu.ot_schedule_get()
     classes = []
-    for lo, hi, block in ((0, t64, 64), (t64, t256, 256), (t256, 1 << 30, 512)):
+    for lo, hi, block in ((0, min(64, t64), 64), (min(64, t64), t64, 64), (t64, t256, 256), (t256, 1 << 30, 512)):
         idx = np.nonzero((sizes > lo) & (sizes <= hi))[0]
         if len(idx):
             idx = idx[np.argsort(-sizes[idx], kind="stable")].astype(np.int32)
