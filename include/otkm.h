@@ -232,6 +232,27 @@ int ot_assign_batch(int32_t count, const int32_t *const *C, const int32_t *n, in
 int ot_assign_dev(const int32_t *dC, int32_t n, int32_t ld, const ot_options *opt, int32_t *dplan,
                   int64_t *dcost, int64_t *du, int64_t *dv, ot_stats *dstats, void *stream);
 
+/* Allocation-free variant of ot_assign_dev, for callers that cannot allocate
+ * device memory (code under hipGraph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Same arguments and results as ot_assign_dev, but
+ * every call runs on one workgroup over the exact costs: opt->wgs must be 0 or
+ * 1 and opt->scale 0 or 1 (OT_EINVAL otherwise), and single stale columns are
+ * recomputed from C itself (no transposed copy).  Its scratch (the engine's
+ * lists and the reduction sweeps' outputs) is one static device array of
+ * OT_NOALLOC_SCRATCH_BYTES bytes per GPU, held until the process ends; the
+ * call calls no hipMalloc, hipFree or allocating library routine.  n must be
+ * <= OT_MAX_N (OT_ETOOBIG otherwise; every such n fits the array).  Calls
+ * that overlap on one GPU share the array and race: serialise them (one
+ * stream, or events).  The array keeps the last call's contents; every word
+ * a call reads it first writes.  The first call on a device also looks up the
+ * array's address there (hipGetSymbolAddress, no stream work); call ot_init()
+ * once beforehand where even the library's first set-up must stay out of a
+ * capture. */
+#define OT_NOALLOC_SCRATCH_BYTES 2244608
+int ot_assign_dev_noalloc(const int32_t *dC, int32_t n, int32_t ld, const ot_options *opt,
+                          int32_t *dplan, int64_t *dcost, int64_t *du, int64_t *dv, ot_stats *dstats,
+                          void *stream);
+
 /* Rectangular assignment on device memory (see ot_assign_rect).  dC [n*ld]
  * (ld >= m), dplan [n], dcost [1], du [n], dv [m] (du/dv may be NULL), dstats
  * [1] (may be NULL; status there).  On a data error (cost range, watchdog)

@@ -25,7 +25,7 @@ OT_MAX_N = 4096
 EXPORTS = [
     "ot_strerror", "ot_init", "ot_assign", "ot_assign_ex", "ot_assign_rect", "ot_scale_for", "ot_transport",
     "ot_assign_batch", "ot_transport_bins", "ot_transport_bins_dev",
-    "ot_assign_dev", "ot_assign_rect_dev", "ot_assign_batch_dev", "ot_transpose_batch_dev", "ot_transport_dev",
+    "ot_assign_dev", "ot_assign_dev_noalloc", "ot_assign_rect_dev", "ot_assign_batch_dev", "ot_transpose_batch_dev", "ot_transport_dev",
     "ot_schedule_get", "ot_schedule_set", "ot_schedule_tune", "ot_schedule_rule",
     "ot_split_get", "ot_split_set", "ot_split_tune", "ot_split_rule",
     "ot_grid_cost_dev", "ot_serve_open", "ot_serve_submit", "ot_serve_poll", "ot_serve_stats", "ot_serve_close",
@@ -110,6 +110,7 @@ def load():
         lib.ot_transport_bins_dev.argtypes = [_VP, _VP, _VP, _I32, _I32, _I32, _VP, _VP, _VP, _VP, _VP, _VP]
         lib.ot_assign_batch.argtypes = [_I32, _VP, _VP, _VP, _VP, _VP, _VP, _VP]
         lib.ot_assign_dev.argtypes = [_VP, _I32, _I32, _VP, _VP, _VP, _VP, _VP, _VP, _VP]
+        lib.ot_assign_dev_noalloc.argtypes = [_VP, _I32, _I32, _VP, _VP, _VP, _VP, _VP, _VP, _VP]
         lib.ot_assign_rect_dev.argtypes = [_VP, _I32, _I32, _I32, _VP, _VP, _VP, _VP, _VP, _VP, _VP]
         lib.ot_transpose_batch_dev.argtypes = [_I32, _I32, _VP, _VP, _VP, _VP, _VP]
         lib.ot_assign_batch_dev.argtypes = [_I32, _I32, _VP, _VP, _VP, _VP, _VP, _VP, _I32, _I32, _VP, _VP, _VP, _VP, _VP,
@@ -379,6 +380,18 @@ def ot_assign_dev(C, plan, cost, u=None, v=None, stats=None, max_paths=0, block=
     rc = load().ot_assign_dev(_tp(C), n, ld, ctypes.byref(opt), _tp(plan), _tp(cost), _tp(u), _tp(v),
                               _tp(stats), _stream(stream))
     _check(rc, "ot_assign_dev")
+
+
+def ot_assign_dev_noalloc(C, plan, cost, u=None, v=None, stats=None, max_paths=0, block=0, stream=None, ld=None,
+                          timers=False):
+    """ot_assign_dev without device allocation: one workgroup, scratch in a
+    static device array shared by every call on the GPU (serialise calls)."""
+    n = int(C.shape[0])
+    ld = int(ld if ld is not None else C.stride(0))
+    opt = _options(max_paths, block, timers, 1, 0)
+    rc = load().ot_assign_dev_noalloc(_tp(C), n, ld, ctypes.byref(opt), _tp(plan), _tp(cost), _tp(u), _tp(v),
+                                      _tp(stats), _stream(stream))
+    _check(rc, "ot_assign_dev_noalloc")
 
 
 def ot_assign_rect_dev(C, plan, cost, u=None, v=None, stats=None, max_paths=0, block=0, stream=None, ld=None,
