@@ -315,21 +315,20 @@ int ot_transport_dev(const int32_t *dC, const int32_t *dr, const int32_t *dc, in
  * (exact integer rounding, ties cannot occur) is built on the device, so only
  * the points cross PCIe.  A server thread admits queued requests in arrival
  * order while the device bytes of the admitted ones (4 n^2 + 64 n per
- * request) stay within hbm_budget_bytes and a slot is free, builds their cost
- * matrices, and publishes each into its size class's live queue (n <= 512,
- * 2048, 4096: one, four and eight wavefronts per request).  Each class runs one
- * persistent kernel whose workgroups take requests from that queue while the
- * server keeps appending to it: a request that arrives while its class's
- * kernel runs joins the running kernel as soon as a workgroup is free
- * (counted in ot_serve_counters.joined), and the kernel starts again only if
- * it left before taking every published request.  Each request completes on
- * its own (the device releases a completion flag per request).  Results are
- * identical to a solve of the same request alone (the solver is
- * deterministic).  Every server stream (one build stream and one per queue)
- * is created with a CU mask naming all CUs, which gives it a hardware queue
- * of its own; such streams are blocking streams, so work the same process
- * puts on the legacy default stream while the server runs waits for the
- * running kernels. */
+ * request) stay within hbm_budget_bytes and a slot is free, and publishes each
+ * into one queue in pinned host memory.  One persistent kernel serves every
+ * size (one workgroup of 512 threads per request and per CU): its workgroups
+ * take requests from the queue while the server keeps appending to it, build
+ * the request's matrix from its points, solve it and release the request's
+ * completion flag, so a request that arrives while the kernel runs joins it
+ * as soon as a workgroup is free (counted in ot_serve_counters.joined) and
+ * completes as soon as its own solve does.  The kernel ends after the server
+ * has been idle for a short while, and starts again with the next request.
+ * Results are identical to a solve of the same request alone (the solver is
+ * deterministic).  The kernel's stream is created with a CU mask naming all
+ * CUs, which gives it a hardware queue of its own; such a stream is a
+ * blocking stream, so work the same process puts on the legacy default
+ * stream while the server's kernel runs waits for it. */
 typedef struct ot_server ot_server;
 
 /* Device cost builder used by the server, exposed on its own:
@@ -340,9 +339,7 @@ int ot_grid_cost_dev(const int32_t *dsrc, const int32_t *ddst, int32_t n, int32_
 typedef struct ot_serve_cfg {
     int64_t hbm_budget_bytes;  /* device bytes admitted requests may hold; 0 = 8 GiB */
     int32_t max_inflight;      /* request slots (1..1024); 0 = 256; 1 = one request at a time */
-    int32_t streams;           /* live queues per size class (n <= 512, 2048, 4096), 1..8; 0 = 1.
-                                  Each queue has its own kernel stream; a request goes to the
-                                  class's queue with the fewest outstanding requests */
+    int32_t streams;           /* 0..8, accepted and unused (the server runs one queue) */
     int32_t max_n;             /* largest n accepted (<= OT_MAX_N); 0 = OT_MAX_N */
     int32_t reserved[5];       /* must be zero */
 } ot_serve_cfg;
@@ -358,9 +355,9 @@ typedef struct ot_result {
 
 typedef struct ot_serve_counters {
     int64_t submitted, admitted, completed;
-    int64_t groups;                /* kernel launches (a class's kernel starts again only after it left) */
+    int64_t groups;                /* kernel launches (the kernel starts again only after it ended) */
     int64_t peak_inflight_bytes, peak_inflight;
-    int64_t joined;                /* requests published while their class's kernel ran and completed by it */
+    int64_t joined;                /* requests published while the kernel ran and completed by it */
 } ot_serve_counters;
 
 /* Start a server on the current device.  Returns OT_OK and *out, or an error. */
@@ -374,7 +371,7 @@ int ot_serve_submit(ot_server *s, const int32_t *src, const int32_t *dst, int32_
 int ot_serve_poll(ot_server *s, uint64_t req_id, ot_result *out, int32_t timeout_us);
 /* Counters since open; now = the server clock. */
 int ot_serve_stats(ot_server *s, ot_serve_counters *out, double *now);
-/* Stop the server after in-flight groups drain; frees its resources. */
+/* Stop the server once every submitted request has completed; frees its resources. */
 int ot_serve_close(ot_server *s);
 
 /* ------------------------------------------------------------------------ */

@@ -11,6 +11,7 @@
 #include <hip/hip_runtime.h>
 
 #include "engine.hpp"
+#include "gridcost.hpp"
 #include "launch.hpp"
 
 namespace otkm {
@@ -375,41 +376,15 @@ __global__ void k_tr_duals_zero_cols(const int32_t *C, const int32_t *c, int n, 
 // ---------------------------------------------------------------------------
 // serving: C_ij = round(sqrt(|p_i - q_j|^2)) for integer points, exact
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ int32_t isqrt_round(int64_t d) {
-  // floor(sqrt(d)) from the double estimate, corrected to the exact integer
-  int64_t k = (int64_t)sqrt((double)d);
-  while (k * k > d) --k;
-  while ((k + 1) * (k + 1) <= d) ++k;
-  return (int32_t)(k + ((d - k * k) > k ? 1 : 0));
-}
-
 __global__ void k_grid_cost(const int32_t *ps, const int32_t *pt, int n, int32_t *Cout) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   const int i = blockIdx.y;
   if (j >= n || i >= n) return;
   const int64_t dx = (int64_t)ps[2 * i] - pt[2 * j];
   const int64_t dy = (int64_t)ps[2 * i + 1] - pt[2 * j + 1];
-  Cout[(size_t)i * n + j] = isqrt_round(dx * dx + dy * dy);
+  Cout[(size_t)i * n + j] = grid_isqrt_round(dx * dx + dy * dy);
 }
 
-// Publish entries [first, first + count) of a serving queue: descriptors and
-// ring slots first, then (after a fence) the tail, so a workgroup that sees
-// the new tail sees the entries.  One workgroup.
-__global__ __launch_bounds__(256) void k_serve_publish(const int4 *staging, int first, int count, int qcap,
-                                                       int64_t vstride, int32_t *ring, int32_t *n, int64_t *coff,
-                                                       int64_t *voff, int32_t *tail) {
-  for (int q = threadIdx.x; q < count; q += blockDim.x) {
-    const int p = first + q;
-    const int4 e = staging[p % qcap];
-    n[e.x] = e.y;
-    coff[e.x] = (int64_t)(((uint64_t)(uint32_t)e.w << 32) | (uint32_t)e.z);
-    voff[e.x] = (int64_t)e.x * vstride;
-    ring[p % qcap] = e.x;
-  }
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) __hip_atomic_store(tail, first + count, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-}
 
 // ---------------------------------------------------------------------------
 // launchers
@@ -527,17 +502,6 @@ hipError_t launch_rect_finish(int n, int m, bool trans, const int32_t *pq, const
 
 hipError_t launch_grid_cost(const int32_t *ps, const int32_t *pt, int n, int32_t *Cout, hipStream_t s) {
   hipLaunchKernelGGL(k_grid_cost, dim3((n + 255) / 256, n), dim3(256), 0, s, ps, pt, n, Cout);
-  return hipGetLastError();
-}
-
-}  // namespace otkm
-
-namespace otkm {
-
-hipError_t launch_serve_publish(const int4 *staging, int first, int count, int qcap, int64_t vstride, int32_t *ring,
-                                int32_t *n, int64_t *coff, int64_t *voff, int32_t *tail, hipStream_t s) {
-  hipLaunchKernelGGL(k_serve_publish, dim3(1), dim3(256), 0, s, staging, first, count, qcap, vstride, ring, n, coff,
-                     voff, tail);
   return hipGetLastError();
 }
 

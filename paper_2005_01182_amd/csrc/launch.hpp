@@ -25,14 +25,6 @@ struct BatchArgs {
   int32_t *head;          // queue head (reset to 0 before the launch)
   int32_t *done;          // [count] or null: done[k] = tag once instance k's outputs are visible to the host
   int32_t tag;
-  // Live queue (serving): with live_tail set, order is a ring of qcap entries
-  // filled while the kernel runs (entry p at order[p % qcap], published once
-  // *live_tail > p; device memory written by a kernel on another stream),
-  // head is the first entry not yet taken (set before the launch), nq is
-  // unused, and done[k] = p + 1 for entry p.
-  const int32_t *live_tail = nullptr;
-  int32_t qcap = 0;
-  int32_t linger = 0;                  // empty polls (a few microseconds each) before a workgroup leaves
 };
 
 struct TransportArgs {
@@ -75,11 +67,23 @@ hipError_t launch_rect_finish(int n, int m, bool trans, const int32_t *pq, const
                               const int64_t *cq, const ot_stats *sq, int32_t *plan, int64_t *cost, int64_t *u,
                               int64_t *v, ot_stats *stats, hipStream_t s);
 hipError_t launch_grid_cost(const int32_t *ps, const int32_t *pt, int n, int32_t *Cout, hipStream_t s);
-// Serving: entries [first, first + count) of a live queue (each {slot, n, coff
-// low, coff high} in host memory at staging[p % qcap]) into the device
-// descriptors and ring, then the tail to first + count.
-hipError_t launch_serve_publish(const int4 *staging, int first, int count, int qcap, int64_t vstride,
-                                int32_t *ring, int32_t *n, int64_t *coff, int64_t *voff, int32_t *tail,
-                                hipStream_t s);
+// Serving: one persistent kernel over a queue in host memory (serve_kernel.hip)
+struct ServeArgs {
+  const int32_t *h_tail, *h_quit;  // host (mapped): published entries; the epoch at or below which launches end
+  const int32_t *desc;             // host (mapped): entry p at [p % qcap][4] = {slot, n, coff low, coff high}
+  const int32_t *pts;              // host (mapped): [slots][4 max_n] points, src (2n) then dst (2n)
+  int32_t *head, *tail, *quit;     // device: entries taken; mirrors of the two host words
+  uint64_t *polled;                // device: s_memrealtime of the last read of the host words
+  int qcap, slots, max_n, epoch, linger;
+  int32_t *C;                      // device: cost matrices (element offset coff per entry)
+  int32_t *plan;                   // host (mapped): [slots][max_n]
+  int64_t *cost, *u, *v;           // host (mapped): [slots], [slots][max_n] x 2
+  ot_stats *stats;                 // host (mapped): [slots]
+  int32_t *done;                   // host (mapped): [slots], entry p's slot gets p + 1 when its results are out
+  int32_t *ws;                     // device: grid * ws_ints(max_n)
+};
+size_t serve_lds_bytes(int max_n);
+int serve_occupancy(int max_n);
+hipError_t launch_serve(const ServeArgs &A, int grid, hipStream_t s);
 
 }  // namespace otkm

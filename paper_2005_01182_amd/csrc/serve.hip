@@ -1,30 +1,27 @@
 // serve.hip -- continuous-batching request server (C-ABI in otkm.h).
 //
 // Requests (n source and n target grid points) queue on the host.  A server
-// thread admits them in arrival order as request slots and device bytes free
-// up, builds each admitted request's cost matrix on the device from its
-// points and publishes it into its size class's live queue (a ring of request
-// slots and a tail counter in device memory, written by a small kernel on the
-// same build stream, so an entry becomes visible only after its matrix).  Each class runs one persistent batch kernel at a time; its
-// workgroups take entries from the queue while the host keeps appending, so a
-// request that arrives while its class's kernel runs joins that kernel as
-// soon as a workgroup is free, and workgroups that find the queue empty wait
-// a short, bounded while before they leave (the kernel holds several sets of
-// workgroups, so one that leaves is replaced while requests keep arriving,
-// and the kernel ends soon after they stop).  When the kernel has left with
-// entries still unclaimed (they arrived after its last workgroup looked), the
-// server launches it again from the first unclaimed entry.  The engine
-// writes each request's plan and duals straight into pinned host memory and
-// then releases a per-request completion flag, so a request completes as
-// soon as its own solve does.
+// thread admits them in arrival order while a request slot is free and the
+// device bytes of the admitted ones stay within the budget: it reserves the
+// request's cost-matrix region in the device arena, copies its points into
+// the slot's pinned, device-mapped host buffer, writes the queue entry and
+// raises the queue's tail.  One persistent kernel (serve_kernel.hip) serves
+// every size: its workgroups take entries while the host keeps appending,
+// build each request's matrix on the device from its points, solve it and
+// write plan, duals and cost straight into mapped host memory before
+// releasing the request's completion flag, so a request completes as soon as
+// its own solve does and joins the running kernel as soon as a workgroup is
+// free.  The kernel ends on its own when it stays idle (or when the host,
+// with nothing outstanding, raises the quit word); the server thread starts
+// it again when entries are waiting and no launch is running.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <atomic>
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
 #include <deque>
-#include <map>
 #include <memory>
 #include <mutex>
 #include <thread>
@@ -40,38 +37,24 @@ using namespace otkm;
 
 namespace {
 
-constexpr int kClasses = 3;
-constexpr int kMaxLanesPerClass = 8;
-constexpr int kDefaultLanesPerClass = 1;
-// size classes: (largest n, workgroup width).  Each class's kernel runs on a
-// stream of its own and the builds on another, each on its own hardware queue
-// (dedicated_stream), so no stream waits behind another's long kernel.
-constexpr int kClassMaxN[kClasses] = {512, 2048, OT_MAX_N};
-constexpr int kClassBlock[kClasses] = {64, 256, 512};
-// Empty-queue polls before a workgroup leaves: each is a read of the tail in
-// host memory and a short sleep, a few microseconds together.
-constexpr int kLinger = 24;
-// A class's kernel is launched with this many times the workgroups that fit
-// on the device at once.  Workgroups that stay busy keep the first set
-// resident; one that finds the queue empty leaves, and a workgroup of the
-// next set starts in its place, so the kernel keeps its full width while
-// requests arrive and ends soon after they stop.
+// Empty-queue polls (about 2 us each) before an idle workgroup leaves: long
+// enough that the kernel keeps its width through the gaps of a request
+// stream, short enough that a lost host ends it soon.
+constexpr int kLinger = 25000;
+// The launch holds this many times the workgroups that fit at once: one that
+// leaves while others still solve is replaced from the next set, so the
+// kernel keeps its width after a quiet spell.
 constexpr int kGenerations = 4;
-
-int class_of(int n) {
-  for (int c = 0; c < kClasses; ++c)
-    if (n <= kClassMaxN[c]) return c;
-  return kClasses - 1;
-}
+// With nothing outstanding for this long, the host asks the kernel to end.
+constexpr double kIdleQuitSeconds = 0.002;
 
 int64_t request_bytes(int n) { return 4ll * n * n + 64ll * n; }
 
 struct Req {
   uint64_t id = 0;
-  int32_t n = 0, cls = 0, slot = -1, status = 0;
-  int lane = -1;
-  int32_t pos = -1;       // position in the lane's queue (the completion tag is pos + 1)
-  int64_t launch = -1;    // the lane's launch that was running when the request was published, or -1
+  int32_t n = 0, slot = -1, status = 0;
+  int32_t pos = -1;       // queue position (the completion tag is pos + 1)
+  int64_t launch = -1;    // the launch that was running when the request was published, or -1
   int64_t off = -1, abytes = 0, bytes = 0, cost = 0;  // arena offset and size of C; admitted bytes
   double t_submit = 0, t_admit = 0, t_done = 0;
   bool done = false;
@@ -80,58 +63,42 @@ struct Req {
   std::vector<int64_t> u, v;
 };
 
-struct Build {  // requests of one lane whose matrices and queue entries were queued on the build stream together
-  hipEvent_t ev = nullptr;
-  std::vector<Req *> reqs;
-};
-
-struct Lane {  // one size class's queue and kernel stream
-  int cls = 0, max_n = 1, block = 64, grid_max = 1;
-  hipStream_t s = nullptr;
-  hipEvent_t ev = nullptr;  // the running kernel's completion
-  bool running = false;
-  int64_t launches = 0;
-  int32_t queued = 0;   // entries handed to the build stream
-  int outstanding = 0;  // admitted requests of this lane not yet retired
-  std::map<int32_t, int32_t> pend;     // published entries not yet retired: position -> request slot
-  int4 *h_stage = nullptr;             // mapped: entry p's {slot, n, coff} at p % qcap, read by the publish kernel
-  int32_t *d_ring = nullptr;           // entry p -> request slot, at p % qcap
-  int32_t *d_tail = nullptr;           // published entries
-  int32_t *d_head = nullptr, *d_ws = nullptr;
-  std::deque<Build> building;
-};
-
 }  // namespace
 
 struct ot_server {
   ot_serve_cfg cfg{};
-  int maxn = OT_MAX_N, slots = 256, cus = 1, dev = 0, qcap = 512;
+  int maxn = OT_MAX_N, slots = 256, cus = 1, dev = 0, qcap = 512, grid = 1;
   char *arena_base = nullptr;
   std::unique_ptr<otkm::Arena> arena;
-  hipStream_t sb = nullptr;                   // builds every admitted request's cost matrix
-  int32_t *d_pts = nullptr;                   // [slots][4 maxn]
-  int32_t *h_pts = nullptr;                   // pinned staging [slots][4 maxn]
-  int32_t *h_plan = nullptr;                  // mapped [slots][maxn]
-  int64_t *h_u = nullptr, *h_v = nullptr;     // mapped [slots][maxn]
-  // per request slot: the descriptor on the device, the results mapped
-  int64_t *d_coff = nullptr, *d_voff = nullptr;
-  int32_t *d_n = nullptr;
-  int64_t *h_cost = nullptr;
-  int32_t *h_done = nullptr;
-  ot_stats *h_stats = nullptr;
+  hipStream_t ks = nullptr;  // the serving kernel's stream
+  hipEvent_t kev = nullptr;  // the running launch's completion
+  bool running = false;
+  int64_t launches = 0;
+  int32_t epoch = 0;         // of the latest launch
+  int32_t quit_sent = 0;     // the latest epoch asked to end
+  int32_t published = 0;     // queue positions handed out
+  // mapped host memory (the kernel reads and writes it over PCIe)
+  int32_t *h_tail = nullptr, *h_quit = nullptr;  // [1], [1]
+  int32_t *h_desc = nullptr;                     // [qcap][4]
+  int32_t *h_pts = nullptr;                      // [slots][4 maxn]
+  int32_t *h_plan = nullptr;                     // [slots][maxn]
+  int64_t *h_u = nullptr, *h_v = nullptr;        // [slots][maxn]
+  int64_t *h_cost = nullptr;                     // [slots]
+  int32_t *h_done = nullptr;                     // [slots]
+  ot_stats *h_stats = nullptr;                   // [slots]
+  // device memory
+  int32_t *d_ctl = nullptr;  // head, tail mirror, quit mirror, pad, then the poll time (u64)
+  int32_t *d_ws = nullptr;   // grid * ws_ints(maxn)
   std::vector<int> free_slots;
-  std::vector<hipEvent_t> free_events;
-  Lane lanes[kClasses * kMaxLanesPerClass];  // lane c * lpc + l: class c, stream l
-  int lpc = kDefaultLanesPerClass;
-  int nlanes() const { return kClasses * lpc; }
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
   std::deque<Req *> pending;
   std::unordered_map<uint64_t, std::unique_ptr<Req>> reqs;
-  std::vector<Req *> running;  // published requests not yet complete
+  std::vector<Req *> running_reqs;  // published requests not yet complete
   uint64_t next_id = 1;
   int64_t inflight_bytes = 0;
   int inflight = 0;
+  double last_busy = 0;
   bool stop = false;
   int fatal = 0;
   ot_serve_counters ctr{};
@@ -146,25 +113,15 @@ struct ot_server {
 namespace {
 
 void free_server(ot_server *s) {
-  for (auto &L : s->lanes) {
-    if (L.s) hipStreamSynchronize(L.s);
-    if (s->sb) hipStreamSynchronize(s->sb);
-    for (auto &b : L.building) hipEventDestroy(b.ev);
-    if (L.ev) hipEventDestroy(L.ev);
-    if (L.s) hipStreamDestroy(L.s);
-    hipFree(L.d_head); hipFree(L.d_ws); hipFree(L.d_ring); hipFree(L.d_tail);
-    hipHostFree(L.h_stage);
-  }
-  for (hipEvent_t e : s->free_events) hipEventDestroy(e);
-  if (s->sb) hipStreamDestroy(s->sb);
+  if (s->ks) hipStreamSynchronize(s->ks);
+  if (s->kev) hipEventDestroy(s->kev);
+  if (s->ks) hipStreamDestroy(s->ks);
   hipFree(s->arena_base);
-  hipFree(s->d_pts);
-  hipHostFree(s->h_pts);
-  hipHostFree(s->h_plan);
-  hipHostFree(s->h_u);
-  hipHostFree(s->h_v);
-  hipFree(s->d_coff); hipFree(s->d_voff); hipFree(s->d_n);
-  hipHostFree(s->h_cost); hipHostFree(s->h_done); hipHostFree(s->h_stats);
+  hipFree(s->d_ctl);
+  hipFree(s->d_ws);
+  for (void *p : {(void *)s->h_tail, (void *)s->h_quit, (void *)s->h_desc, (void *)s->h_pts, (void *)s->h_plan,
+                  (void *)s->h_u, (void *)s->h_v, (void *)s->h_cost, (void *)s->h_done, (void *)s->h_stats})
+    if (p) hipHostFree(p);
   delete s;
 }
 
@@ -175,49 +132,64 @@ T *dptr(T *host) {  // device address of mapped host memory
   return (T *)d;
 }
 
-// A stream on its own hardware queue.  Streams beyond the runtime's hardware
-// queue limit share queues, and work on a shared queue runs in submission
-// order across its streams: a class's long-running kernel would hold up the
-// builds and the other classes' kernels queued behind it.  A stream created
-// with a CU mask always gets a queue of its own; the mask here names every CU.
+// A stream on its own hardware queue: a stream created with a CU mask always
+// gets one (streams beyond the runtime's queue limit otherwise share queues,
+// and work on a shared queue runs in submission order across its streams,
+// so a long-running kernel would hold up whatever was queued behind it).
+// The mask names every CU.
 hipError_t dedicated_stream(hipStream_t *st, int cus) {
   std::vector<uint32_t> mask((size_t)(cus + 31) / 32, 0xffffffffu);
   if (cus % 32) mask.back() = (1u << (cus % 32)) - 1;
   return hipExtStreamCreateWithCUMask(st, (uint32_t)mask.size(), mask.data());
 }
 
-// (Re)start lane li's kernel from entry `base`.  Requires s->mu.
-int launch_lane(ot_server *s, int li, int32_t base) {
-  Lane &L = s->lanes[li];
+// Start the kernel.  The device head persists across launches (every entry a
+// launch took, it finished), so a launch continues at the first entry not yet
+// taken.  Requires s->mu.
+int launch(ot_server *s) {
+  ServeArgs A;
+  A.h_tail = dptr(s->h_tail);
+  A.h_quit = dptr(s->h_quit);
+  A.desc = dptr(s->h_desc);
+  A.pts = dptr(s->h_pts);
+  A.head = s->d_ctl;
+  A.tail = s->d_ctl + 1;
+  A.quit = s->d_ctl + 2;
+  A.polled = (uint64_t *)(s->d_ctl + 4);
+  A.qcap = s->qcap;
+  A.slots = s->slots;
+  A.max_n = s->maxn;
+  A.epoch = s->epoch + 1;
+  A.linger = kLinger;
+  A.C = (int32_t *)s->arena_base;
+  A.plan = dptr(s->h_plan);
+  A.cost = dptr(s->h_cost);
+  A.u = dptr(s->h_u);
+  A.v = dptr(s->h_v);
+  A.stats = dptr(s->h_stats);
+  A.done = dptr(s->h_done);
+  A.ws = s->d_ws;
+  if (!A.h_tail || !A.h_quit || !A.desc || !A.pts || !A.plan || !A.cost || !A.u || !A.v || !A.stats || !A.done)
+    return OT_EDEVICE;
   hipError_t e;
-  if ((e = launch_fill_i32(L.d_head, base, 1, L.s)) != hipSuccess) return map_hip(e);
-  const int grid = L.grid_max * kGenerations;
-  BatchArgs A;
-  A.C = (const int32_t *)s->arena_base;
-  A.coff = s->d_coff; A.n = s->d_n; A.voff = s->d_voff; A.order = L.d_ring;
-  A.count = s->slots; A.nq = 0; A.max_n = L.max_n; A.max_paths = 0;
-  A.plan = dptr(s->h_plan); A.cost = dptr(s->h_cost); A.u = dptr(s->h_u); A.v = dptr(s->h_v);
-  A.stats = dptr(s->h_stats); A.ws = L.d_ws; A.head = L.d_head; A.done = dptr(s->h_done); A.tag = 0;
-  A.live_tail = L.d_tail; A.qcap = s->qcap; A.linger = kLinger;
-  if (!A.plan || !A.cost || !A.u || !A.v || !A.stats || !A.done) return OT_EDEVICE;
-  if ((e = launch_assign_batch(A, L.block, grid, L.s)) != hipSuccess) return map_hip(e);
-  if ((e = hipEventRecord(L.ev, L.s)) != hipSuccess) return map_hip(e);
-  L.running = true;
-  ++L.launches;
+  if ((e = launch_serve(A, s->grid, s->ks)) != hipSuccess) return map_hip(e);
+  if ((e = hipEventRecord(s->kev, s->ks)) != hipSuccess) return map_hip(e);
+  s->epoch = A.epoch;
+  s->running = true;
+  ++s->launches;
   ++s->ctr.groups;
   return OT_OK;
 }
 
-// Retire finished requests and finished kernels.  Returns true when anything
+// Retire finished requests and a finished launch.  Returns true when anything
 // changed.  Requires s->mu.
 bool retire(ot_server *s) {
   bool changed = false;
   const size_t M = (size_t)s->maxn;
-  for (size_t i = 0; i < s->running.size();) {
-    Req *r = s->running[i];
+  for (size_t i = 0; i < s->running_reqs.size();) {
+    Req *r = s->running_reqs[i];
     const int32_t flag = __atomic_load_n(&s->h_done[r->slot], __ATOMIC_ACQUIRE);
     if (flag != r->pos + 1) { ++i; continue; }
-    Lane &L = s->lanes[r->lane];
     const ot_stats st = s->h_stats[r->slot];
     r->status = (int32_t)st.status;
     r->cost = s->h_cost[r->slot];
@@ -226,45 +198,40 @@ bool retire(ot_server *s) {
       r->u.assign(s->h_u + (size_t)r->slot * M, s->h_u + (size_t)r->slot * M + r->n);
       r->v.assign(s->h_v + (size_t)r->slot * M, s->h_v + (size_t)r->slot * M + r->n);
     }
-    // published while the lane's kernel ran, and completed by that same kernel
-    if (r->launch >= 0 && r->launch == L.launches && L.running) ++s->ctr.joined;
+    // published while the kernel ran, and completed by that same launch
+    if (r->launch >= 0 && r->launch == s->launches && s->running) ++s->ctr.joined;
     r->t_done = s->now();
     r->done = true;
-    --L.outstanding;
-    L.pend.erase(r->pos);
     s->arena->release(r->off, r->abytes);
     s->free_slots.push_back(r->slot);
     s->inflight_bytes -= r->bytes;
     --s->inflight;
     ++s->ctr.completed;
-    s->running[i] = s->running.back();
-    s->running.pop_back();
+    s->running_reqs[i] = s->running_reqs.back();
+    s->running_reqs.pop_back();
+    s->last_busy = s->now();
     changed = true;
   }
-  for (int li = 0; li < s->nlanes(); ++li) {
-    Lane &L = s->lanes[li];
-    if (!L.running) continue;
-    const hipError_t q = hipEventQuery(L.ev);
-    if (q == hipErrorNotReady) continue;
-    if (q != hipSuccess) {
+  if (s->running) {
+    const hipError_t q = hipEventQuery(s->kev);
+    if (q == hipSuccess) {
+      s->running = false;
+      changed = true;
+    } else if (q != hipErrorNotReady) {
       // the kernel failed: its flags will never arrive, so every waiter is
       // woken with the error instead of waiting forever
       if (s->fatal == 0) s->fatal = map_hip(q);
       changed = true;
-      continue;
     }
-    L.running = false;
-    changed = true;
   }
   return changed;
 }
 
 // Admit queued requests (arrival order, within the budget and the slots) and
-// queue their cost matrices on the build stream.  Requires s->mu.
+// publish them.  Requires s->mu.
 bool admit(ot_server *s) {
   bool any = false;
   const size_t M = (size_t)s->maxn;
-  std::vector<Req *> batch[kClasses * kMaxLanesPerClass];
   int scanned = 0;
   for (auto it = s->pending.begin(); it != s->pending.end() && scanned < 4096; ++scanned) {
     Req *r = *it;
@@ -273,106 +240,58 @@ bool admit(ot_server *s) {
     const int64_t abytes = 4ll * r->n * r->n;
     const int64_t off = s->arena->alloc(abytes);
     if (off < 0) { ++it; continue; }
-    // the class's lane with the fewest outstanding requests
-    int li = r->cls * s->lpc;
-    for (int l = 1; l < s->lpc; ++l) {
-      const int c = r->cls * s->lpc + l;
-      if (s->lanes[c].outstanding < s->lanes[li].outstanding) li = c;
-    }
     r->off = off;
     r->abytes = abytes;
     r->slot = s->free_slots.back();
     s->free_slots.pop_back();
-    r->lane = li;
     r->t_admit = s->now();
     s->inflight_bytes += r->bytes;
     ++s->inflight;
-    ++s->lanes[li].outstanding;
     s->ctr.peak_inflight_bytes = std::max(s->ctr.peak_inflight_bytes, s->inflight_bytes);
     s->ctr.peak_inflight = std::max<int64_t>(s->ctr.peak_inflight, s->inflight);
     ++s->ctr.admitted;
-    batch[li].push_back(r);
+    std::memcpy(s->h_pts + (size_t)r->slot * 4 * M, r->pts.data(), sizeof(int32_t) * 4 * (size_t)r->n);
+    r->pos = s->published++;
+    int32_t *e = s->h_desc + 4 * (size_t)(r->pos % s->qcap);
+    const uint64_t coff = (uint64_t)(off / 4);
+    e[0] = r->slot;
+    e[1] = r->n;
+    e[2] = (int32_t)(uint32_t)coff;
+    e[3] = (int32_t)(uint32_t)(coff >> 32);
+    r->launch = s->running ? s->launches : -1;
+    s->running_reqs.push_back(r);
     it = s->pending.erase(it);
     any = true;
   }
-  for (int li = 0; li < s->nlanes(); ++li) {
-    if (batch[li].empty()) continue;
-    Lane &L = s->lanes[li];
-    hipError_t e;
-    for (Req *r : batch[li]) {
-      int32_t *hp = s->h_pts + (size_t)r->slot * 4 * M;
-      std::memcpy(hp, r->pts.data(), sizeof(int32_t) * 4 * (size_t)r->n);
-      int32_t *dp = s->d_pts + (size_t)r->slot * 4 * M;
-      if ((e = hipMemcpyAsync(dp, hp, sizeof(int32_t) * 4 * (size_t)r->n, hipMemcpyHostToDevice, s->sb)) != hipSuccess ||
-          (e = launch_grid_cost(dp, dp + 2 * r->n, r->n, (int32_t *)(s->arena_base + r->off), s->sb)) != hipSuccess) {
-        s->fatal = map_hip(e);
-        return any;
-      }
-    }
-    // queue entries, published on the device after the matrices above
-    const int32_t first = L.queued;
-    for (Req *r : batch[li]) {
-      r->pos = L.queued++;
-      L.h_stage[r->pos % s->qcap] = make_int4(r->slot, r->n, (int)(uint32_t)(r->off / 4),
-                                             (int)(uint32_t)((uint64_t)(r->off / 4) >> 32));
-    }
-    std::atomic_thread_fence(std::memory_order_release);
-    if ((e = launch_serve_publish(dptr(L.h_stage), first, L.queued - first, s->qcap, (int64_t)M, L.d_ring, s->d_n,
-                                  s->d_coff, s->d_voff, L.d_tail, s->sb)) != hipSuccess) {
-      s->fatal = map_hip(e);
-      return any;
-    }
-    Build b;
-    if (!s->free_events.empty()) {
-      b.ev = s->free_events.back();
-      s->free_events.pop_back();
-    } else if ((e = hipEventCreateWithFlags(&b.ev, hipEventDisableTiming)) != hipSuccess) {
-      s->fatal = map_hip(e);
-      return any;
-    }
-    if ((e = hipEventRecord(b.ev, s->sb)) != hipSuccess) { s->fatal = map_hip(e); return any; }
-    b.reqs = std::move(batch[li]);
-    L.building.push_back(std::move(b));
+  if (any) {
+    // entries and points are written before the tail that covers them
+    __atomic_store_n(s->h_tail, s->published, __ATOMIC_RELEASE);
+    s->last_busy = s->now();
   }
   return any;
 }
 
-// Take note of the requests whose matrices and queue entries are on the
-// device (running from now on), and start the kernel of every lane with
-// unclaimed entries and no kernel running.  Requires s->mu.
-bool publish(ot_server *s) {
-  bool any = false;
-  for (int li = 0; li < s->nlanes(); ++li) {
-    Lane &L = s->lanes[li];
-    while (!L.building.empty()) {
-      Build &b = L.building.front();
-      const hipError_t q = hipEventQuery(b.ev);
-      if (q == hipErrorNotReady) break;
-      if (q != hipSuccess) { s->fatal = map_hip(q); return any; }
-      for (Req *r : b.reqs) {
-        r->launch = L.running ? L.launches : -1;
-        s->running.push_back(r);
-        L.pend[r->pos] = r->slot;
-      }
-      s->free_events.push_back(b.ev);
-      L.building.pop_front();
-      any = true;
-    }
-    if (L.running) continue;
-    // An ended kernel took a prefix of the entries and completed each one it
-    // took, so with no kernel running the flags are final: the next launch
-    // starts at the first published entry without its flag (entries not yet
-    // retired keep their slots, so their flags are theirs).
-    int32_t base = -1;
-    for (const auto &pe : L.pend)
-      if (__atomic_load_n(&s->h_done[pe.second], __ATOMIC_ACQUIRE) != pe.first + 1) { base = pe.first; break; }
-    if (base >= 0) {
-      const int rc = launch_lane(s, li, base);
-      if (rc != OT_OK) { s->fatal = rc; return any; }
-      any = true;
-    }
+// Start the kernel when entries wait and no launch runs; ask a running launch
+// to end when nothing has been outstanding for a while.  Requires s->mu.
+bool schedule(ot_server *s) {
+  if (!s->running) {
+    if (s->running_reqs.empty()) return false;
+    // no launch runs, so every flag is final: any entry without its flag waits
+    bool waiting = false;
+    for (const Req *r : s->running_reqs)
+      if (__atomic_load_n(&s->h_done[r->slot], __ATOMIC_ACQUIRE) != r->pos + 1) { waiting = true; break; }
+    if (!waiting) return false;
+    const int rc = launch(s);
+    if (rc != OT_OK) s->fatal = rc;
+    return true;
   }
-  return any;
+  if (s->quit_sent < s->epoch && s->running_reqs.empty() && s->pending.empty() &&
+      s->now() - s->last_busy > kIdleQuitSeconds) {
+    __atomic_store_n(s->h_quit, s->epoch, __ATOMIC_RELEASE);
+    s->quit_sent = s->epoch;
+    return true;
+  }
+  return false;
 }
 
 void worker_main(ot_server *s) {
@@ -383,11 +302,13 @@ void worker_main(ot_server *s) {
     bool progressed = retire(s);
     if (progressed) s->cv_done.notify_all();
     progressed = admit(s) || progressed;
-    progressed = publish(s) || progressed;
-    if (s->stop && s->pending.empty() && s->running.empty()) {
-      bool idle = true;
-      for (int li = 0; li < s->nlanes(); ++li) idle = idle && !s->lanes[li].running && s->lanes[li].building.empty();
-      if (idle) break;
+    progressed = schedule(s) || progressed;
+    if (s->stop && s->pending.empty() && s->running_reqs.empty()) {
+      if (!s->running) break;
+      if (s->quit_sent < s->epoch) {
+        __atomic_store_n(s->h_quit, s->epoch, __ATOMIC_RELEASE);
+        s->quit_sent = s->epoch;
+      }
     }
     if (!progressed) {
       s->cv_work.wait_for(lk, std::chrono::microseconds(20));
@@ -424,11 +345,10 @@ int ot_serve_open(ot_server **out, const ot_serve_cfg *cfg_in) {
   for (int k = 0; k < 5; ++k)
     if (cfg.reserved[k] != 0) return OT_EINVAL;
   if (cfg.hbm_budget_bytes < 0 || cfg.max_inflight < 0 || cfg.max_inflight > 1024 || cfg.streams < 0 ||
-      cfg.streams > kMaxLanesPerClass || cfg.max_n < 0 || cfg.max_n > OT_MAX_N)
+      cfg.streams > 8 || cfg.max_n < 0 || cfg.max_n > OT_MAX_N)
     return OT_EINVAL;
   if (cfg.hbm_budget_bytes == 0) cfg.hbm_budget_bytes = 8ll << 30;
   if (cfg.max_inflight == 0) cfg.max_inflight = 256;
-  if (cfg.streams == 0) cfg.streams = kDefaultLanesPerClass;
   if (cfg.max_n == 0) cfg.max_n = OT_MAX_N;
   if (request_bytes(cfg.max_n) > cfg.hbm_budget_bytes) return OT_ETOOBIG;
   {
@@ -443,51 +363,41 @@ int ot_serve_open(ot_server **out, const ot_serve_cfg *cfg_in) {
   s->cfg = cfg;
   s->maxn = cfg.max_n;
   s->slots = cfg.max_inflight;
-  // more ring entries than slots: an entry's ring position is reused only after
-  // every earlier entry has been taken (at most `slots` wait at a time)
+  // more queue entries than slots: entry p's descriptor is rewritten (as
+  // entry p + qcap) only after entry p completed
   s->qcap = 2 * s->slots;
   s->cus = device_cus();
   s->t0 = std::chrono::steady_clock::now();
   const size_t M = (size_t)s->maxn, SL = (size_t)s->slots;
-  hipError_t e = hipSuccess;
+  const int occ = serve_occupancy(s->maxn);
+  s->grid = std::max(1, std::min(s->slots, occ * s->cus)) * kGenerations;
+  hipError_t e = occ > 0 ? hipSuccess : hipErrorInvalidValue;
   auto chk = [&](hipError_t x) { if (e == hipSuccess) e = x; };
   const unsigned mapped = hipHostMallocMapped | hipHostMallocCoherent;
   chk(hipMalloc(&s->arena_base, (size_t)cfg.hbm_budget_bytes));
-  chk(hipMalloc(&s->d_pts, 4 * 4 * M * SL));
-  chk(hipHostMalloc(&s->h_pts, 4 * 4 * M * SL, hipHostMallocDefault));
+  chk(hipMalloc(&s->d_ctl, 256));
+  chk(hipMalloc(&s->d_ws, 4 * ws_ints(s->maxn) * (size_t)s->grid));
+  chk(hipHostMalloc(&s->h_tail, 64, mapped));
+  chk(hipHostMalloc(&s->h_quit, 64, mapped));
+  chk(hipHostMalloc(&s->h_desc, 16 * (size_t)s->qcap, mapped));
+  chk(hipHostMalloc(&s->h_pts, 4 * 4 * M * SL, mapped));
   chk(hipHostMalloc(&s->h_plan, 4 * M * SL, mapped));
   chk(hipHostMalloc(&s->h_u, 8 * M * SL, mapped));
   chk(hipHostMalloc(&s->h_v, 8 * M * SL, mapped));
-  chk(hipMalloc(&s->d_coff, 8 * SL));
-  chk(hipMalloc(&s->d_voff, 8 * SL));
-  chk(hipMalloc(&s->d_n, 4 * SL));
   chk(hipHostMalloc(&s->h_cost, 8 * SL, mapped));
   chk(hipHostMalloc(&s->h_done, 4 * SL, mapped));
   chk(hipHostMalloc(&s->h_stats, sizeof(ot_stats) * SL, mapped));
-  s->lpc = cfg.streams;
-  chk(dedicated_stream(&s->sb, s->cus));
-  for (int li = 0; li < s->nlanes() && e == hipSuccess; ++li) {
-    Lane &L = s->lanes[li];
-    L.cls = li / s->lpc;
-    L.max_n = std::min(kClassMaxN[L.cls], s->maxn);
-    L.block = kClassBlock[L.cls];
-    const int occ = batch_occupancy(L.block, L.max_n);
-    if (occ <= 0) { e = hipErrorInvalidValue; break; }
-    L.grid_max = std::max(1, std::min<int>(s->slots, occ * s->cus));
-    chk(dedicated_stream(&L.s, s->cus));
-    chk(hipEventCreateWithFlags(&L.ev, hipEventDisableTiming));
-    chk(hipMalloc(&L.d_head, 256));
-    chk(hipMalloc(&L.d_ws, 4 * ws_ints(L.max_n) * (size_t)L.grid_max * kGenerations));
-    chk(hipMalloc(&L.d_ring, 4 * (size_t)s->qcap));
-    chk(hipMalloc(&L.d_tail, 256));
-    chk(hipHostMalloc(&L.h_stage, sizeof(int4) * (size_t)s->qcap, mapped));
-    if (e == hipSuccess) chk(hipMemset(L.d_tail, 0, 256));
-  }
+  chk(dedicated_stream(&s->ks, s->cus));
+  chk(hipEventCreateWithFlags(&s->kev, hipEventDisableTiming));
+  if (e == hipSuccess) chk(hipMemsetAsync(s->d_ctl, 0, 256, s->ks));
+  if (e == hipSuccess) chk(hipStreamSynchronize(s->ks));
   if (e != hipSuccess) {
     const int rc = map_hip(e);
     free_server(s);
     return rc;
   }
+  *s->h_tail = 0;
+  *s->h_quit = 0;
   std::memset(s->h_done, 0, 4 * SL);
   s->arena.reset(new otkm::Arena(cfg.hbm_budget_bytes));
   for (int k = s->slots - 1; k >= 0; --k) s->free_slots.push_back(k);
@@ -501,7 +411,6 @@ int ot_serve_submit(ot_server *s, const int32_t *src, const int32_t *dst, int32_
   if (n > s->maxn) return OT_ETOOBIG;
   std::unique_ptr<Req> r(new Req());
   r->n = n;
-  r->cls = class_of(n);
   r->bytes = request_bytes(n);
   r->pts.resize(4 * (size_t)n);
   std::memcpy(r->pts.data(), src, 8 * (size_t)n);

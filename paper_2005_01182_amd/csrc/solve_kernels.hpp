@@ -55,93 +55,42 @@ __global__ __launch_bounds__(BLOCK) void k_assign_grid(Problem P) {
 template <int BLOCK, int CPT>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2))) void k_assign_batch(BatchArgs A) {
   extern __shared__ __align__(16) char smem[];
-  __shared__ int s_idx, s_k, s_n;
-  __shared__ int64_t s_coff, s_voff;
+  __shared__ int s_idx;
   int32_t *ws = A.ws + (size_t)blockIdx.x * ws_ints(A.max_n);
-  const bool live = A.live_tail != nullptr;
   for (;;) {
-    if (threadIdx.x == 0) {
-      int idx = -1, k = -1;
-      if (!live) {
-        idx = atomicAdd(A.head, 1);
-        if (idx < A.nq) k = A.order ? A.order[idx] : idx;
-        else idx = -1;
-      } else {
-        // Live queue: entries [0, *live_tail) are published (by a kernel on
-        // another stream) while this one runs; an entry is taken by advancing
-        // the head past it.  An empty queue is polled `linger` times (a short
-        // sleep each) before the workgroup leaves: every wait is bounded.
-        for (int spin = 0;; ++spin) {
-          const int h = __hip_atomic_load(A.head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          const int t = __hip_atomic_load(A.live_tail, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-          if (h < t) {
-            int hh = h;
-            if (__hip_atomic_compare_exchange_strong(A.head, &hh, h + 1, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
-                                                     __HIP_MEMORY_SCOPE_AGENT)) {
-              idx = h;
-              k = __hip_atomic_load(&A.order[h % A.qcap], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-              break;
-            }
-            continue;
-          }
-          if (spin >= A.linger) break;
-          __builtin_amdgcn_s_sleep(63);
-        }
-      }
-      // the descriptor, read once (device scope when it was written while the kernel runs)
-      int n = 0;
-      int64_t coff = 0, voff = 0;
-      if (idx >= 0 && (unsigned)k < (unsigned)A.count) {
-        if (live) {
-          n = __hip_atomic_load(&A.n[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          coff = __hip_atomic_load(&A.coff[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          voff = __hip_atomic_load(&A.voff[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        } else {
-          n = A.n[k];
-          coff = A.coff[k];
-          voff = A.voff[k];
-        }
-      }
-      s_idx = idx;
-      s_k = k;
-      s_n = n;
-      s_coff = coff;
-      s_voff = voff;
-    }
+    if (threadIdx.x == 0) s_idx = atomicAdd(A.head, 1);
     __syncthreads();
-    const int idx = s_idx, k = s_k, n = s_n;
-    const int64_t coff = s_coff, voff = s_voff;
+    const int idx = s_idx;
     __syncthreads();
-    if (idx < 0) break;  // every workgroup reaches this exit once the queue drains
-    // the completion tag: the launch's for a fixed queue, the entry's position
-    // (plus one, so never the initial zero) for a live queue
-    const int32_t tag = live ? idx + 1 : A.tag;
+    if (idx >= A.nq) break;  // every workgroup reaches this exit once the queue drains
+    const int k = A.order ? A.order[idx] : idx;
     if ((unsigned)k >= (unsigned)A.count) continue;  // no such instance: nothing to report or flag
+    const int n = A.n[k];
     if (n < 1 || n > A.max_n || n > BLOCK * CPT) {
       if (threadIdx.x == 0) {
         if (A.stats) { ot_stats s = {}; s.status = OT_EINVAL; A.stats[k] = s; }
         if (A.done) {
           __threadfence_system();
-          __hip_atomic_store(&A.done[k], tag, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+          __hip_atomic_store(&A.done[k], A.tag, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
         }
       }
       continue;
     }
     Problem P;
-    P.C = A.C + coff;
+    P.C = A.C + A.coff[k];
     P.n = n;
     P.ld = n;
-    P.CT = A.CT ? A.CT + coff : nullptr;
+    P.CT = A.CT ? A.CT + A.coff[k] : nullptr;
     P.Cout = nullptr;
     P.ldo = n;
     P.dscale = 1;
     P.init_u = nullptr; P.init_b = nullptr; P.init_rmax = nullptr;
     P.max_paths = A.max_paths;
     P.flags = 0;
-    P.plan = A.plan + voff;
+    P.plan = A.plan + A.voff[k];
     P.cost = A.cost + k;
-    P.u = A.u ? A.u + voff : nullptr;
-    P.v = A.v ? A.v + voff : nullptr;
+    P.u = A.u ? A.u + A.voff[k] : nullptr;
+    P.v = A.v ? A.v + A.voff[k] : nullptr;
     P.stats = A.stats ? A.stats + k : nullptr;
     P.ws = ws;
     if constexpr (BLOCK == 64 && CPT == 1) {  // every instance has n <= 64: one wavefront's registers
@@ -156,7 +105,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2))) void
       // system-wide before the completion flag is released
       __threadfence_system();
       __syncthreads();
-      if (threadIdx.x == 0) __hip_atomic_store(&A.done[k], tag, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+      if (threadIdx.x == 0) __hip_atomic_store(&A.done[k], A.tag, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
     }
     __syncthreads();
   }
