@@ -507,6 +507,135 @@ def bench_bins(args):
     return out
 
 
+# ----------------------------------------------------------------------------- sparse
+def sparse_alg_bytes(stats, nnz):
+    """Algorithmic bytes of one sparse solve: every edge entry (column and cost,
+    8 bytes) read by the initial pass and the closing cost pass (2 nnz) plus the
+    sweeps' edge reads counted on the device."""
+    return 8.0 * (stats[:, F["gathers"]].astype(np.float64) + 2.0 * nnz)
+
+
+def bench_sparse(args):
+    """Sparse assignment on a k-nearest-neighbour cost graph in CSR: one instance
+    (n = --n), or with --sparse-count > 1 a batch of instances of n ~ U{16..512}
+    in one launch."""
+    import torch
+
+    from paper_2005_01182_amd import otkm as ot
+    from paper_2005_01182_amd import workloads as wl
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    k = args.knn
+    if args.sparse_count <= 1:
+        n = args.n if args.n is not None else 4096
+        g = wl.knn_assignment(n, k=k, seed=1)
+        ptr, idx, cst, n, m = g
+        nnz = int(ptr[-1])
+        dp, di, dc = d(ptr), d(idx), d(cst)
+        plan = torch.empty(n, dtype=torch.int32, device="cuda")
+        total = torch.empty(1, dtype=torch.int64, device="cuda")
+        u = torch.empty(n, dtype=torch.int64, device="cuda")
+        v = torch.empty(m, dtype=torch.int64, device="cuda")
+        st = ot.stats_tensor(args.steps + args.warmup)
+        stream = torch.cuda.Stream()
+        log("sparse k-NN %d x %d, k = %d, nnz %d: warmup %d, steps %d" % (n, m, k, nnz, args.warmup, args.steps))
+        for w in range(args.warmup):
+            ot.ot_assign_sparse_dev(dp, di, dc, n, m, plan, total, u, v, st[w], stream=stream)
+        torch.cuda.synchronize()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+        t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0.record(stream)
+        for q in range(args.steps):
+            ev[q][0].record(stream)
+            ot.ot_assign_sparse_dev(dp, di, dc, n, m, plan, total, u, v, st[args.warmup + q], stream=stream)
+            ev[q][1].record(stream)
+        t1.record(stream)
+        torch.cuda.synchronize()
+        per = [a.elapsed_time(b) for a, b in ev]
+        tot_ms = t0.elapsed_time(t1)
+        stats = st[args.warmup:].cpu().numpy()
+        if int(np.abs(stats[:, F["status"]]).max()) != 0:
+            raise SystemExit("sparse status %s" % stats[:, F["status"]])
+        got = int(total.item())
+        b = sparse_alg_bytes(stats, nnz)
+        out = base_line(args, args.steps / (tot_ms / 1e3), "solves/s", tot_ms / args.steps,
+                        {"workload": "sparse assignment: %d source and %d target points U{0..1e4}^2 (seed 1), each "
+                                     "source joined to its %d nearest targets plus one edge of a random injective map, "
+                                     "cost = round(|p - q|), CSR" % (n, m, k),
+                         "n": n, "m": m, "k": k, "nnz": nnz, "optimal_cost": got})
+        out["metric"] = "solves/s, sparse k-NN assignment"
+        out["roofline"] = roofline(float(np.mean(b)), float(np.mean(per)) / 1e3)
+        out["latency_ms"] = {"p50": pct(per, 50), "p99": pct(per, 99)}
+        out["solver_counters"] = {"levels": int(stats[0, F["levels"]]), "rounds": int(stats[0, F["aug_events"]]),
+                                  "level_rises": int(stats[0, F["dual_adjusts"]]),
+                                  "rows_swept": int(stats[0, F["rows_swept"]]),
+                                  "edges_swept": int(stats[0, F["gathers"]]), "alg_bytes_per_solve": int(b[0])}
+        if not args.skip_cpu:
+            import oracle
+            ref = oracle.assign_sparse(*g)
+            if ref[1] != got:
+                raise SystemExit("GPU sparse cost %d differs from the oracle's %d" % (got, ref[1]))
+            if oracle.certify_sparse(*g, plan.cpu().numpy(), u.cpu().numpy(), v.cpu().numpy()) != 0:
+                raise SystemExit("GPU sparse result fails the certificate")
+            rate, done = cpu_rate(lambda _: oracle.assign_sparse(*g), range(100), args.cpu_budget)
+            out["cpu_baseline"] = cpu_baseline(rate, "solves/s", 1,
+                                               "%d solve(s) of the same instance by the single-threaded C oracle "
+                                               "(shortest augmenting paths on the graph)" % done,
+                                               oracle_cost_equal=True)
+        return out
+    count = args.sparse_count
+    log("generating %d sparse k-NN instances" % count)
+    graphs = wl.knn_batch(count, k=k, seed=0)
+    max_m = max(g[4] for g in graphs)
+    items, outs = [], []
+    for ptr, idx, cst, n, m in graphs:
+        plan = torch.empty(n, dtype=torch.int32, device="cuda")
+        total = torch.empty(1, dtype=torch.int64, device="cuda")
+        u = torch.empty(n, dtype=torch.int64, device="cuda")
+        v = torch.empty(m, dtype=torch.int64, device="cuda")
+        st = ot.stats_tensor(1)
+        items.append((d(ptr), d(idx), d(cst), n, m, plan, total, u, v, st))
+        outs.append((total, st))
+    descs = ot.sparse_descs(items)
+    stream = torch.cuda.Stream()
+    for w in range(args.warmup):
+        ot.ot_assign_sparse_batch_dev(descs, count, max_m, stream=stream)
+    torch.cuda.synchronize()
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0.record(stream)
+    for q in range(args.steps):
+        ot.ot_assign_sparse_batch_dev(descs, count, max_m, stream=stream)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / args.steps
+    stats = torch.cat([o[1] for o in outs]).cpu().numpy()
+    if int(np.abs(stats[:, F["status"]]).max()) != 0:
+        raise SystemExit("sparse batch status %s" % np.unique(stats[:, F["status"]]))
+    nnz = np.array([int(g[0][-1]) for g in graphs], np.float64)
+    b = float(sparse_alg_bytes(stats, nnz).sum())
+    out = base_line(args, count / (ms / 1e3), "solves/s", ms,
+                    {"workload": "%d sparse k-NN assignments (k = %d), n ~ U{16..512} square, points U{0..1e4}^2, "
+                                 "cost = round(|p - q|), one launch" % (count, k),
+                     "count": count, "k": k, "max_m": int(max_m), "nnz_total": int(nnz.sum())})
+    out["metric"] = "solves/s, batch of sparse k-NN assignments"
+    out["roofline"] = roofline(b, ms / 1e3)
+    if not args.skip_cpu:
+        import oracle
+        costs = [int(o[0].item()) for o in outs]
+        t_c = time.perf_counter()
+        done = 0
+        for g, c in zip(graphs, costs):
+            if oracle.assign_sparse(*g)[1] != c:
+                raise SystemExit("GPU sparse batch cost differs from the oracle on instance %d" % done)
+            done += 1
+            if time.perf_counter() - t_c > args.cpu_budget:
+                break
+        rate = done / (time.perf_counter() - t_c)
+        out["cpu_baseline"] = cpu_baseline(rate, "solves/s", 1,
+                                           "the first %d instances of the batch by the single-threaded C oracle "
+                                           "(costs equal to the GPU's)" % done, oracle_cost_equal=done)
+    return out
+
+
 # ----------------------------------------------------------------------------- batch
 def bench_batch(args):
     import torch
@@ -714,8 +843,8 @@ def main():
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
     ap.add_argument("--mode", default="geometric", choices=["geometric", "small", "transport", "batch", "serve",
-                                                             "copy", "scaled", "rect", "bins"])
-    ap.add_argument("--n", type=int, default=2048)
+                                                             "copy", "scaled", "rect", "bins", "sparse"])
+    ap.add_argument("--n", type=int, default=None, help="geometric / scaled: n (2048); sparse: n (4096)")
     ap.add_argument("--count", type=int, default=4096, help="batch mode: number of problems")
     ap.add_argument("--plain-steps", type=int, default=3)
     ap.add_argument("--plain-count", type=int, default=256, help="batch mode: instances in the per-launch comparison")
@@ -736,9 +865,13 @@ def main():
     ap.add_argument("--mass", type=int, default=1 << 20, help="bins mode: total mass of each image")
     ap.add_argument("--rows", type=int, default=1024, help="rect mode: rows n")
     ap.add_argument("--cols", type=int, default=2048, help="rect mode: columns m")
+    ap.add_argument("--knn", type=int, default=16, help="sparse mode: nearest targets kept per source")
+    ap.add_argument("--sparse-count", type=int, default=1, help="sparse mode: instances (1 = one instance of size --n)")
     args = ap.parse_args()
     defaults = {"geometric": (20, 3), "small": (2000, 50), "transport": (50, 5), "batch": (5, 1), "serve": (1, 0),
-                "copy": (5, 2), "scaled": (20, 3), "rect": (10, 2), "bins": (10, 2)}
+                "copy": (5, 2), "scaled": (20, 3), "rect": (10, 2), "bins": (10, 2), "sparse": (10, 2)}
+    if args.n is None and args.mode != "sparse":
+        args.n = 2048
     if args.steps is None:
         args.steps = defaults[args.mode][0]
     if args.warmup is None:
@@ -758,7 +891,7 @@ def main():
     else:
         out = {"geometric": bench_geometric, "small": bench_small, "transport": bench_transport,
                "batch": bench_batch, "copy": bench_copy, "scaled": bench_scaled,
-               "rect": bench_rect, "bins": bench_bins}[args.mode](args)
+               "rect": bench_rect, "bins": bench_bins, "sparse": bench_sparse}[args.mode](args)
     print(json.dumps(out), flush=True)
 
 

@@ -64,7 +64,8 @@ typedef enum ot_status {
     OT_ENOMEM = -6,       /* host or device allocation failed */
     OT_EDEVICE = -7,      /* a HIP runtime call failed */
     OT_ENODEV = -8,       /* no usable gfx950 device */
-    OT_EINTERNAL = -9     /* solver watchdog or invariant check tripped */
+    OT_EINTERNAL = -9,    /* solver watchdog or invariant check tripped */
+    OT_EINFEASIBLE = -10  /* sparse graph: no matching covers every row (Hall's condition fails) */
 } ot_status;
 
 /* Per-solve counters (written when a stats pointer is given).  A "level" is
@@ -306,6 +307,52 @@ int ot_transport_bins_dev(const int32_t *dC, const int32_t *dr, const int32_t *d
 int ot_transport_dev(const int32_t *dC, const int32_t *dr, const int32_t *dc, int32_t n, int32_t m,
                      int32_t S, int32_t *dX, int64_t *dcost, int64_t *du, int64_t *dv,
                      ot_stats *dstats, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Sparse assignment: a cost graph in CSR, missing entries forbidden          */
+/* ------------------------------------------------------------------------ */
+/* Eq. (1) with unit masses on a bipartite cost graph (the sparse form of the
+ * problem; Section 2.3.1's method on the graph's edges only): rows 0..n-1,
+ * columns 0..m-1 with 1 <= n <= m <= OT_MAX_N; row i's edges go to columns
+ * idx[ptr[i] .. ptr[i+1]) at int32 costs cost[...] (ptr[0] = 0, ptr
+ * non-decreasing, nnz = ptr[n]).  Finds a minimum-cost matching that covers
+ * every row using edges only; columns may stay free.  Outputs: plan[n] (the
+ * column of each row), *total (int64), u[n] and v[m] (may be NULL): optimal
+ * duals of the LP, u_i + v_j <= c_e on every edge, equality on the plan,
+ * v_j <= 0 and v_j = 0 on the columns left free.  When no matching covers
+ * every row, returns OT_EINFEASIBLE.  ot_assign_sparse takes host buffers,
+ * checks the graph (offsets, column range, no column twice in a row:
+ * OT_EINVAL) and returns once the results are copied back; outputs are
+ * untouched on error.  stats may be NULL. */
+int ot_assign_sparse(const int64_t *ptr, const int32_t *idx, const int32_t *cost, int32_t n, int32_t m,
+                     int32_t *plan, int64_t *total, int64_t *u, int64_t *v, ot_stats *stats);
+
+/* The same on device buffers, asynchronous on stream (NULL: the library's
+ * stream).  The device checks the column range (OT_EINVAL in dstats->status)
+ * and reports OT_EINFEASIBLE there; ptr must be a valid offset array.  A
+ * column given twice in a row counts at its cheapest copy.  du, dv, dstats
+ * may be NULL. */
+int ot_assign_sparse_dev(const int64_t *dptr, const int32_t *didx, const int32_t *dcost, int32_t n, int32_t m,
+                         int32_t *dplan, int64_t *dtotal, int64_t *du, int64_t *dv, ot_stats *dstats,
+                         void *stream);
+
+/* One sparse instance of a batch: every pointer is a device pointer. */
+typedef struct ot_sparse_desc {
+    const int64_t *ptr;
+    const int32_t *idx;
+    const int32_t *cost;
+    int32_t n, m;
+    int32_t *plan;
+    int64_t *total;
+    int64_t *u, *v;        /* may be NULL */
+    ot_stats *stats;       /* may be NULL (then errors go unreported) */
+} ot_sparse_desc;
+
+/* Many sparse instances in one persistent launch (one workgroup per instance
+ * at a time), asynchronous on stream.  ddesc [count] lives in device memory;
+ * max_m bounds every instance's m (it sizes the on-chip state; an instance
+ * above it reports OT_EINVAL).  Per-instance status in its stats. */
+int ot_assign_sparse_batch_dev(int32_t count, const ot_sparse_desc *ddesc, int32_t max_m, void *stream);
 
 /* ------------------------------------------------------------------------ */
 /* Serving: continuous batching of assignment requests                       */

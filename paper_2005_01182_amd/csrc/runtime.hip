@@ -256,6 +256,7 @@ const char *ot_strerror(int status) {
     case OT_EDEVICE: return "HIP runtime error";
     case OT_ENODEV: return "no usable gfx950 device";
     case OT_EINTERNAL: return "internal solver error (watchdog or invariant)";
+    case OT_EINFEASIBLE: return "no matching of the graph covers every row";
     default: return "unknown status";
   }
 }

@@ -20,6 +20,7 @@ LIB_PATH = os.environ.get("OTKM_LIBRARY") or os.path.join(_HERE, "libotkm.so")
 
 OT_OK, OT_EINVAL, OT_ERANGE, OT_EUNBALANCED, OT_ENEGMASS = 0, -1, -2, -3, -4
 OT_ETOOBIG, OT_ENOMEM, OT_EDEVICE, OT_ENODEV, OT_EINTERNAL = -5, -6, -7, -8, -9
+OT_EINFEASIBLE = -10
 OT_MAX_N = 4096
 
 EXPORTS = [
@@ -29,6 +30,7 @@ EXPORTS = [
     "ot_schedule_get", "ot_schedule_set", "ot_schedule_tune", "ot_schedule_rule",
     "ot_split_get", "ot_split_set", "ot_split_tune", "ot_split_rule",
     "ot_grid_cost_dev", "ot_serve_open", "ot_serve_submit", "ot_serve_poll", "ot_serve_stats", "ot_serve_close",
+    "ot_assign_sparse", "ot_assign_sparse_dev", "ot_assign_sparse_batch_dev",
 ]
 
 
@@ -62,6 +64,12 @@ class ot_result(ctypes.Structure):
     _fields_ = [("plan", ctypes.c_void_p), ("u", ctypes.c_void_p), ("v", ctypes.c_void_p),
                 ("cost", ctypes.c_int64), ("status", ctypes.c_int32), ("n", ctypes.c_int32),
                 ("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double), ("t_done", ctypes.c_double)]
+
+
+class ot_sparse_desc(ctypes.Structure):
+    _fields_ = [("ptr", ctypes.c_void_p), ("idx", ctypes.c_void_p), ("cost", ctypes.c_void_p),
+                ("n", ctypes.c_int32), ("m", ctypes.c_int32), ("plan", ctypes.c_void_p), ("total", ctypes.c_void_p),
+                ("u", ctypes.c_void_p), ("v", ctypes.c_void_p), ("stats", ctypes.c_void_p)]
 
 
 class ot_serve_counters(ctypes.Structure):
@@ -108,6 +116,9 @@ def load():
         lib.ot_transport.argtypes = [_VP, _VP, _VP, _I32, _I32, _VP, _VP, _VP, _VP]
         lib.ot_transport_bins.argtypes = [_VP, _VP, _VP, _I32, _I32, _VP, _VP, _VP, _VP, _VP]
         lib.ot_transport_bins_dev.argtypes = [_VP, _VP, _VP, _I32, _I32, _I32, _VP, _VP, _VP, _VP, _VP, _VP]
+        lib.ot_assign_sparse.argtypes = [_VP, _VP, _VP, _I32, _I32, _VP, _VP, _VP, _VP, _VP]
+        lib.ot_assign_sparse_dev.argtypes = [_VP, _VP, _VP, _I32, _I32, _VP, _VP, _VP, _VP, _VP, _VP]
+        lib.ot_assign_sparse_batch_dev.argtypes = [_I32, _VP, _I32, _VP]
         lib.ot_assign_batch.argtypes = [_I32, _VP, _VP, _VP, _VP, _VP, _VP, _VP]
         lib.ot_assign_dev.argtypes = [_VP, _I32, _I32, _VP, _VP, _VP, _VP, _VP, _VP, _VP]
         lib.ot_assign_dev_noalloc.argtypes = [_VP, _I32, _I32, _VP, _VP, _VP, _VP, _VP, _VP, _VP]
@@ -250,6 +261,29 @@ def ot_transport(C, r, c):
     rc = load().ot_transport(_p(C), _p(r), _p(c), n, m, _p(X), ctypes.byref(cost), _p(u), _p(v))
     _check(rc, "ot_transport")
     return X, int(cost.value), u, v
+
+
+def ot_assign_sparse(ptr, idx, cost, n: int, m: int, with_stats: bool = False):
+    """Minimum-cost matching of every row of a CSR cost graph (n <= m, edges only).
+
+    Returns (plan, total, u, v) or (..., stats_dict); raises OtError with
+    OT_EINFEASIBLE when no matching covers every row."""
+    n, m = int(n), int(m)
+    ptr = np.ascontiguousarray(ptr, dtype=np.int64)
+    idx = np.ascontiguousarray(idx, dtype=np.int32)
+    cost = np.ascontiguousarray(cost, dtype=np.int32)
+    if ptr.shape != (n + 1,) or idx.shape != cost.shape or idx.shape != (int(ptr[-1]),):
+        raise ValueError("CSR arrays do not match n and the edge count")
+    plan = np.empty(n, np.int32)
+    u = np.empty(n, np.int64)
+    v = np.empty(m, np.int64)
+    total = ctypes.c_int64(0)
+    st = ot_stats()
+    rc = load().ot_assign_sparse(_p(ptr), _p(idx) if idx.size else None, _p(cost) if cost.size else None, n, m,
+                                 _p(plan), ctypes.byref(total), _p(u), _p(v), ctypes.byref(st))
+    _check(rc, "ot_assign_sparse")
+    out = (plan, int(total.value), u, v)
+    return out + (st.as_dict(),) if with_stats else out
 
 
 def ot_transport_bins(C, r, c, with_stats: bool = False):
@@ -433,6 +467,32 @@ def ot_transport_dev(C, r, c, S, X, cost, u, v, stats=None, stream=None):
     rc = load().ot_transport_dev(_tp(C), _tp(r), _tp(c), n, m, int(S), _tp(X), _tp(cost), _tp(u), _tp(v),
                                  _tp(stats), _stream(stream))
     _check(rc, "ot_transport_dev")
+
+
+def ot_assign_sparse_dev(ptr, idx, cost, n, m, plan, total, u=None, v=None, stats=None, stream=None):
+    """Queue a sparse assignment on device tensors (asynchronous on `stream`)."""
+    rc = load().ot_assign_sparse_dev(_tp(ptr), _tp(idx), _tp(cost), int(n), int(m), _tp(plan), _tp(total), _tp(u),
+                                     _tp(v), _tp(stats), _stream(stream))
+    _check(rc, "ot_assign_sparse_dev")
+
+
+def sparse_descs(items, device="cuda"):
+    """Device array of ot_sparse_desc from (ptr, idx, cost, n, m, plan, total, u, v, stats) tensor tuples."""
+    import torch
+    arr = (ot_sparse_desc * len(items))()
+    for k, (ptr, idx, cost, n, m, plan, total, u, v, stats) in enumerate(items):
+        arr[k] = ot_sparse_desc(ptr.data_ptr(), idx.data_ptr(), cost.data_ptr(), int(n), int(m), plan.data_ptr(),
+                                total.data_ptr(), u.data_ptr() if u is not None else None,
+                                v.data_ptr() if v is not None else None,
+                                stats.data_ptr() if stats is not None else None)
+    raw = np.frombuffer(bytes(arr), dtype=np.uint8).copy()
+    return torch.from_numpy(raw).to(device)
+
+
+def ot_assign_sparse_batch_dev(descs, count, max_m, stream=None):
+    """Queue a batch of sparse assignments (descs from sparse_descs)."""
+    rc = load().ot_assign_sparse_batch_dev(int(count), _tp(descs), int(max_m), _stream(stream))
+    _check(rc, "ot_assign_sparse_batch_dev")
 
 
 def ot_transport_bins_dev(C, r, c, X, cost, u, v, stats=None, stream=None, ld=None):
