@@ -295,9 +295,9 @@ struct Engine {
   // one merge.  Returns rows used.
   // Rows per chunk, measured on MI355X (geometric n = 512..4096): U * CPT = 8
   // loads per lane (two rows at 4 columns per lane) beat 16 and 4 on the short
-  // frontiers that dominate; long frontiers take chunks of UB = 2U rows.
-  static constexpr int U = CPT >= 8 ? 2 : 8 / CPT;
-  static constexpr int UB = 2 * U * CPT > 32 ? 32 / CPT : 2 * U;  // UB * CPT <= 32 pass bits
+  // frontiers that dominate; on long frontiers the next chunk's loads are
+  // issued before the current chunk is folded.
+  static constexpr int U = CPT >= 8 ? 2 : 8 / CPT;  // U * CPT <= 32 pass bits
   static constexpr int GU = 8;  // forest rows in flight per lane when recomputing a stale column
   // One chunk of UU rows list[f .. f+UU) (slots past cnt are skipped).  REC:
   // list holds frontier records (row, tree and the low word of h, written when
@@ -411,38 +411,55 @@ struct Engine {
     return sweep_chunk_narrow<S, REC>(list, f, cnt);
   }
 
+  // One chunk's rows, trees, row duals and cost entries (the loads of the
+  // entries may still be in flight).
+  template <int UU>
+  struct Chunk {
+    int r[UU], t[UU];
+    int64_t h[UU];
+    uint32_t h32[UU];
+    int32_t c[UU][CPT];
+  };
+
+  // Read chunk list[f .. f+UU) (slots past cnt are skipped) and issue its
+  // cost loads; nothing here waits for them.
   template <bool NARROW, int UU, bool REC>
-  __device__ __forceinline__ int sweep_chunk(const int32_t *list, int f, int cnt) {
+  __device__ __forceinline__ void chunk_load(const int32_t *list, int f, int cnt, Chunk<UU> &X) {
+#pragma unroll
+    for (int q = 0; q < UU; ++q) {
+      if (REC) {
+        const int2 e = ((const int2 *)list)[f + q < cnt ? f + q : cnt - 1];
+        X.r[q] = e.x & 0xffff;
+        if ((unsigned)X.r[q] >= (unsigned)rows()) { fail(OT_EINTERNAL); X.r[q] = 0; }
+        X.t[q] = (f + q < cnt && e.x >= 0) ? (e.x >> 16) : -1;  // sign bit: the row's tree has gone
+        X.h32[q] = (uint32_t)e.y;
+        X.h[q] = NARROW ? 0 : hrow[X.r[q]];
+      } else {
+        X.r[q] = f + q < cnt ? list[f + q] : 0;
+        if ((unsigned)X.r[q] >= (unsigned)rows()) { fail(OT_EINTERNAL); X.r[q] = 0; }
+        X.t[q] = f + q < cnt ? rtree[X.r[q]] : -1;
+        X.h[q] = hrow[X.r[q]];
+        X.h32[q] = (uint32_t)X.h[q];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < UU; ++q) {
+      const int32_t *row = C + (size_t)X.r[q] * (size_t)ld;
+#pragma unroll
+      for (int k = 0; k < CPT; ++k) X.c[q][k] = row[lcol(k)];
+    }
+  }
+
+  // Fold a loaded chunk into every owned column's top-2 keys; returns the rows used.
+  template <bool NARROW, int UU>
+  __device__ __forceinline__ int chunk_fold(const Chunk<UU> &X) {
     int used = 0;
     {
       constexpr int U = UU;
-      int r[U], t[U];
-      int64_t h[U];
-      uint32_t h32[U];
-      int32_t c[U][CPT];
-#pragma unroll
-      for (int q = 0; q < U; ++q) {
-        if (REC) {
-          const int2 e = ((const int2 *)list)[f + q < cnt ? f + q : cnt - 1];
-          r[q] = e.x & 0xffff;
-          if ((unsigned)r[q] >= (unsigned)rows()) { fail(OT_EINTERNAL); r[q] = 0; }
-          t[q] = (f + q < cnt && e.x >= 0) ? (e.x >> 16) : -1;  // sign bit: the row's tree has gone
-          h32[q] = (uint32_t)e.y;
-          h[q] = NARROW ? 0 : hrow[r[q]];
-        } else {
-          r[q] = f + q < cnt ? list[f + q] : 0;
-          if ((unsigned)r[q] >= (unsigned)rows()) { fail(OT_EINTERNAL); r[q] = 0; }
-          t[q] = f + q < cnt ? rtree[r[q]] : -1;
-          h[q] = hrow[r[q]];
-          h32[q] = (uint32_t)h[q];
-        }
-      }
-#pragma unroll
-      for (int q = 0; q < U; ++q) {
-        const int32_t *row = C + (size_t)r[q] * (size_t)ld;
-#pragma unroll
-        for (int k = 0; k < CPT; ++k) c[q][k] = row[lcol(k)];
-      }
+      const int *r = X.r, *t = X.t;
+      const int64_t *h = X.h;
+      const uint32_t *h32 = X.h32;
+      const int32_t(*c)[CPT] = X.c;
 #pragma unroll
       for (int q = 0; q < U; ++q) used += t[q] >= 0;
       if (NARROW) {
@@ -536,9 +553,17 @@ struct Engine {
     return used;
   }
 
-  // Rows go in chunks of U, or (one-instance kernel) of UB while at least UB
-  // rows remain: a short frontier pays one small chunk, a long one fewer,
-  // fuller chunks.
+
+  template <bool NARROW, int UU, bool REC>
+  __device__ __forceinline__ int sweep_chunk(const int32_t *list, int f, int cnt) {
+    Chunk<UU> X;
+    chunk_load<NARROW, UU, REC>(list, f, cnt, X);
+    return chunk_fold<NARROW, UU>(X);
+  }
+
+  // Rows go in chunks of U.  In the one-instance kernel the chunks are
+  // pipelined: a short frontier pays one small chunk, a long one about one
+  // memory latency in all.
   template <bool NARROW, bool REC>
   __device__ __forceinline__ int sweep_t(const int32_t *list, int cnt) {
     int used = 0;
@@ -551,8 +576,22 @@ struct Engine {
       if (f < cnt) used += sweep_narrow_tail<UN, REC>(list, f, cnt);
       return used;
     }
-    if (LONG)
-      for (; f + UB <= cnt; f += UB) used += sweep_chunk<NARROW, UB, REC>(list, f, cnt);
+    if (LONG) {
+      // the next chunk's cost loads are in flight while this chunk is folded,
+      // so a long frontier pays about one memory latency, not one per chunk
+      if (f < cnt) {
+        Chunk<U> a;
+        chunk_load<NARROW, U, REC>(list, f, cnt, a);
+        for (f += U; f < cnt; f += U) {
+          Chunk<U> b;
+          chunk_load<NARROW, U, REC>(list, f, cnt, b);
+          used += chunk_fold<NARROW, U>(a);
+          a = b;
+        }
+        used += chunk_fold<NARROW, U>(a);
+      }
+      return used;
+    }
     for (; f < cnt; f += U) used += sweep_chunk<NARROW, U, REC>(list, f, cnt);
     return used;
   }
