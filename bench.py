@@ -727,21 +727,22 @@ def bench_batch(args):
     out["batch_latency_ms"] = {"p50": pct(per, 50), "p99": pct(per, 99)}
     # plain comparison: one launch per instance, sequential on one stream, over a prefix of the batch
     k_plain = min(args.plain_count, count)
-    pp = torch.empty(int(sizes[:k_plain].max()), dtype=torch.int32, device="cuda")
-    pc = torch.empty(1, dtype=torch.int64, device="cuda")
-    views = [dC[int(coff[k]):int(coff[k] + ns[k] * ns[k])].view(int(ns[k]), int(ns[k])) for k in range(k_plain)]
-    for k in range(min(8, k_plain)):
-        ot.ot_assign_dev(views[k], pp, pc, stream=stream)
-    torch.cuda.synchronize()
-    pev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(k_plain)]
-    for k in range(k_plain):
-        pev[k][0].record(stream)
-        ot.ot_assign_dev(views[k], pp, pc, stream=stream)
-        pev[k][1].record(stream)
-    torch.cuda.synchronize()
-    pl = [a.elapsed_time(b) for a, b in pev]
-    out["plain_per_instance"] = {"instances": k_plain, "solves_per_s": round(k_plain / (sum(pl) / 1e3), 3),
-                                 "latency_ms_p50": pct(pl, 50), "latency_ms_p99": pct(pl, 99)}
+    if k_plain > 0:
+        pp = torch.empty(int(sizes[:k_plain].max()), dtype=torch.int32, device="cuda")
+        pc = torch.empty(1, dtype=torch.int64, device="cuda")
+        views = [dC[int(coff[k]):int(coff[k] + ns[k] * ns[k])].view(int(ns[k]), int(ns[k])) for k in range(k_plain)]
+        for k in range(min(8, k_plain)):
+            ot.ot_assign_dev(views[k], pp, pc, stream=stream)
+        torch.cuda.synchronize()
+        pev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(k_plain)]
+        for k in range(k_plain):
+            pev[k][0].record(stream)
+            ot.ot_assign_dev(views[k], pp, pc, stream=stream)
+            pev[k][1].record(stream)
+        torch.cuda.synchronize()
+        pl = [a.elapsed_time(b) for a, b in pev]
+        out["plain_per_instance"] = {"instances": k_plain, "solves_per_s": round(k_plain / (sum(pl) / 1e3), 3),
+                                     "latency_ms_p50": pct(pl, 50), "latency_ms_p99": pct(pl, 99)}
     out["solver_counters"] = {"levels_total": int(stats[:, F["levels"]].sum()),
                               "rows_swept_total": int(stats[:, F["rows_swept"]].sum()),
                               "gathers_total": int(stats[:, F["gathers"]].sum()),

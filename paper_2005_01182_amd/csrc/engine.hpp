@@ -185,14 +185,15 @@ __device__ __forceinline__ int64_t wave_sum_i64(int64_t x) {
 
 // Insert candidate c (from a row of tree t >= 0) into a column's top-2:
 // a1 = best key overall (tree ta1), a2 = best key among trees != ta1.
-__device__ __forceinline__ void top2_push(uint64_t &a1, int &ta1, uint64_t &a2, int &ta2, uint64_t c, int t) {
+template <class K>
+__device__ __forceinline__ void top2_push(K &a1, int &ta1, K &a2, int &ta2, K c, int t) {
   // same tree as the best: only the best can improve; another tree: c may
   // become the best (the old best moves to second) or the second.  a1 <= a2,
   // so c < a1 implies c < a2 and the second changes exactly when c is from
   // another tree and below a2.  Flat selects only (no divergent branches).
   const bool same = t == ta1, lt1 = c < a1, lt2 = c < a2;
   const bool ch2 = !same && lt2;
-  const uint64_t x = lt1 ? a1 : c;
+  const K x = lt1 ? a1 : c;
   const int tx = lt1 ? ta1 : t;
   a2 = ch2 ? x : a2;
   ta2 = ch2 ? tx : ta2;
@@ -201,14 +202,14 @@ __device__ __forceinline__ void top2_push(uint64_t &a1, int &ta1, uint64_t &a2, 
 }
 
 // Merge two exact top-2 summaries (symmetric, so both butterfly partners agree).
-__device__ __forceinline__ void top2_merge(uint64_t &a1, int &ta1, uint64_t &a2, int &ta2, uint64_t b1, int tb1,
-                                           uint64_t b2, int tb2) {
+template <class K>
+__device__ __forceinline__ void top2_merge(K &a1, int &ta1, K &a2, int &ta2, K b1, int tb1, K b2, int tb2) {
   if (b1 < a1) {
-    uint64_t x1 = a1, x2 = a2; int y1 = ta1, y2 = ta2;
+    K x1 = a1, x2 = a2; int y1 = ta1, y2 = ta2;
     a1 = b1; ta1 = tb1; a2 = b2; ta2 = tb2;
     b1 = x1; tb1 = y1; b2 = x2; tb2 = y2;
   }
-  uint64_t c = (tb1 != ta1) ? b1 : b2;
+  K c = (tb1 != ta1) ? b1 : b2;
   int tc = (tb1 != ta1) ? tb1 : tb2;
   if (c < a2) { a2 = c; ta2 = tc; }
 }
@@ -219,14 +220,40 @@ __device__ __forceinline__ int64_t now_ticks() { return (int64_t)wall_clock64();
 // the one-instance kernel, where occupancy does not matter).
 // RECT: the rows may be fewer than the columns (Problem::nr); the batched
 // kernel is square and keeps n in their place.
+// Column keys are value << bits | row.  Wide keys (64-bit, 24 row bits) hold
+// every value the method reaches with int32 costs.  Compact keys (32-bit, 12
+// row bits, n <= 4096) hold values below 2^20, which is enough when the cost
+// range R is below 2^18: a key value is at most 3R (a reduced cost in
+// [0, 2R] plus a level in [0, R]), as long as every free row is a root (with
+// a tree cap the level adds up over stages).  Compact keys halve the
+// instructions of every key comparison and selection.
+template <bool COMPACT>
+struct KeyOf {
+  using T = uint64_t;
+  static constexpr int kBits = kRowBits;
+};
+template <>
+struct KeyOf<true> {
+  using T = uint32_t;
+  static constexpr int kBits = 12;
+};
+constexpr int64_t kCompactRange = 1 << 18;  // cost ranges below this use compact keys
+constexpr int kCompactMaxN = 1 << 12;
+
 // GRID: one instance over gridDim.x workgroups.  Rows, matches and the forest
 // are replicated in every workgroup's LDS and updated identically; the columns
 // (keys in registers) are split.  Per level the workgroups exchange their
 // minimum keys and the columns they settled through global memory, with a
 // grid barrier after each.
-template <int BLOCK, int CPT, bool LONG = false, bool GRID = false, bool RECT = false>
+template <int BLOCK, int CPT, bool LONG = false, bool GRID = false, bool RECT = false, bool COMPACT = false>
 struct Engine {
   static constexpr int NW = BLOCK / 64;
+  using Key = typename KeyOf<COMPACT>::T;
+  static constexpr int KB = KeyOf<COMPACT>::kBits;
+  static constexpr Key KINF = (Key)~(Key)0;
+  static __device__ __forceinline__ Key kpack(int64_t val, int row) { return ((Key)val << KB) | (Key)(uint32_t)row; }
+  static __device__ __forceinline__ int64_t kv(Key k) { return (int64_t)(k >> KB); }
+  static __device__ __forceinline__ int kr(Key k) { return (int)(k & (((Key)1 << KB) - 1)); }
 
   // problem
   const int32_t *__restrict__ C;
@@ -254,7 +281,7 @@ struct Engine {
   __amdgpu_buffer_rsrc_t crsrc;
   int voff[CPT];
   // per-column registers
-  uint64_t k1[CPT], k2[CPT];
+  Key k1[CPT], k2[CPT];
   int t1[CPT], t2[CPT], ctree[CPT];
   // v_j lies in [-R, R] and the level at which a column is reached in [0, R]
   // (R = max C - min C < 2^31), so both fit 32 bits.
@@ -282,7 +309,7 @@ struct Engine {
 
   // exact iff the best key's tree is still alive (or there is no candidate at all)
   __device__ __forceinline__ void recompute_stale(int k) {
-    const bool ok = k1[k] == kInf || (t1[k] >= 0 && alive[t1[k]]);
+    const bool ok = k1[k] == KINF || (t1[k] >= 0 && alive[t1[k]]);
     if (ok) stl &= ~(1u << k); else stl |= 1u << k;
   }
 
@@ -470,15 +497,15 @@ struct Engine {
         uint32_t clr = 0;
 #pragma unroll
         for (int k = 0; k < CPT; ++k) {
-          uint64_t key[U];
-          uint64_t b1 = kInf, b2 = kInf;
+          Key key[U];
+          Key b1 = KINF, b2 = KINF;
           int tb1 = -1, tb2 = -1;
 #pragma unroll
           for (int q = 0; q < U; ++q) {
             // exact: every key value is below 2^32 here, so 32-bit wrap-around cannot occur
             const uint32_t v = (uint32_t)c[q][k] - (h32[q] + (uint32_t)vj[k]);
             const bool ok = (t[q] >= 0) & (col(k) < n);
-            key[q] = ok ? (((uint64_t)v << kRowBits) | (uint32_t)r[q]) : kInf;
+            key[q] = ok ? (((Key)v << KB) | (Key)(uint32_t)r[q]) : KINF;
             const bool lt = key[q] < b1;
             b1 = lt ? key[q] : b1;
             tb1 = lt ? t[q] : tb1;
@@ -493,12 +520,12 @@ struct Engine {
           // wins, and the second is the better of the loser's best (when it
           // is from another tree) or its second, and the winner's second
           const bool sw = b1 < k1[k];
-          const uint64_t x1 = sw ? b1 : k1[k], x2 = sw ? b2 : k2[k];
+          const Key x1 = sw ? b1 : k1[k], x2 = sw ? b2 : k2[k];
           const int tx1 = sw ? tb1 : t1[k], tx2 = sw ? tb2 : t2[k];
-          const uint64_t y1 = sw ? k1[k] : b1, y2 = sw ? k2[k] : b2;
+          const Key y1 = sw ? k1[k] : b1, y2 = sw ? k2[k] : b2;
           const int ty1 = sw ? t1[k] : tb1, ty2 = sw ? t2[k] : tb2;
           const bool d = ty1 != tx1;
-          const uint64_t cc = d ? y1 : y2;
+          const Key cc = d ? y1 : y2;
           const int tc = d ? ty1 : ty2;
           const bool lt = cc < x2;
           k1[k] = x1; t1[k] = tx1;
@@ -516,7 +543,7 @@ struct Engine {
 #pragma unroll
         for (int k = 0; k < CPT; ++k) {
           const int64_t v = (int64_t)c[q][k] - h[q] - vj[k];
-          const bool p = v <= kval(k2[k]);
+          const bool p = v <= kv(k2[k]);
           pass |= (p & (t[q] >= 0) & (col(k) < n)) ? (1u << (q * CPT + k)) : 0u;
         }
       }
@@ -534,7 +561,7 @@ struct Engine {
             if (p) {
               int64_t val = (int64_t)c[q][k] - h[q] - vj[k];
               if (val < 0) { fail(OT_EINTERNAL); val = 0; }
-              const uint64_t key = pack(val, r[q]);
+              const Key key = kpack(val, r[q]);
               const int tq = t[q];
               if (key < k1[k]) {
                 // new best; the old best stays second unless it is from the same tree
@@ -597,11 +624,13 @@ struct Engine {
   }
 
   __device__ __forceinline__ int sweep(const int32_t *list, int cnt) {
-    return narrow ? sweep_t<true, false>(list, cnt) : sweep_t<false, false>(list, cnt);
+    if constexpr (COMPACT) return sweep_t<true, false>(list, cnt);
+    else return narrow ? sweep_t<true, false>(list, cnt) : sweep_t<false, false>(list, cnt);
   }
   __device__ __forceinline__ int sweep_frontier(int cnt) {
     const int32_t *list = (const int32_t *)fr;
-    return narrow ? sweep_t<true, true>(list, cnt) : sweep_t<false, true>(list, cnt);
+    if constexpr (COMPACT) return sweep_t<true, true>(list, cnt);
+    else return narrow ? sweep_t<true, true>(list, cnt) : sweep_t<false, true>(list, cnt);
   }
   __device__ __forceinline__ static int2 frontier_rec(int row, int tree, int64_t h) {
     return make_int2(row | (tree << 16), (int)(uint32_t)h);
@@ -614,12 +643,12 @@ struct Engine {
   // slots receive value << kRowBits.  With NARROW every value is below 2^32 - 1
   // and the wavefront reduction runs on 32-bit words.
   __device__ __forceinline__ void reduce_min(int s, int es) {
-    if (narrow) {
+    if (COMPACT || narrow) {
       uint32_t a = 0xffffffffu, b = 0xffffffffu;
 #pragma unroll
       for (int k = 0; k < CPT; ++k) {
         const bool open = (col(k) < n) & !((vis >> k) & 1u);
-        const uint32_t v = open ? (uint32_t)kval(k1[k]) : 0xffffffffu;  // kInf maps to 0xffffffff
+        const uint32_t v = (open && k1[k] != KINF) ? (uint32_t)kv(k1[k]) : 0xffffffffu;
         const bool st = stale(k);
         a = st ? a : min(a, v);
         b = st ? min(b, v) : b;
@@ -630,7 +659,7 @@ struct Engine {
         if (a != 0xffffffffu) atomicMin((unsigned long long *)&red[2 * s], (unsigned long long)a << kRowBits);
         if (b != 0xffffffffu) atomicMin((unsigned long long *)&red[2 * s + 1], (unsigned long long)b << kRowBits);
       }
-    } else {
+    } else if constexpr (!COMPACT) {
       uint64_t a = kInf, b = kInf;
 #pragma unroll
       for (int k = 0; k < CPT; ++k) {
@@ -753,7 +782,7 @@ struct Engine {
     for (int k = 0; k < CPT; ++k) {
       slot[k] = -1;
       if (col(k) >= n || ((vis >> k) & 1u) || !stale(k)) continue;
-      if (kval(k1[k]) > lim) continue;
+      if (kv(k1[k]) > lim) continue;
       int s = atomicAdd(&ctl[GCNT], 1);
       slot[k] = s;
       req |= 1u << k;
@@ -767,7 +796,7 @@ struct Engine {
     if (g > gcap) {
       // too many: one coalesced re-sweep of every forest row fixes all keys
 #pragma unroll
-      for (int k = 0; k < CPT; ++k) { k1[k] = kInf; k2[k] = kInf; t1[k] = -1; t2[k] = -1; }
+      for (int k = 0; k < CPT; ++k) { k1[k] = KINF; k2[k] = KINF; t1[k] = -1; t2[k] = -1; }
       stl = 0;
       swept = sweep(fst, nf);
       resweep = true;
@@ -789,7 +818,7 @@ struct Engine {
         // else one entry per cost row
         const int32_t *colp = CT ? CT + (size_t)j * (size_t)ldt : C + j;
         const size_t cstride = CT ? 1 : (size_t)ld;
-        uint64_t a1 = kInf, a2 = kInf;
+        Key a1 = KINF, a2 = KINF;
         int ta1 = -1, ta2 = -1;
         const int stride = 64 * wpc;
         for (int f0 = slice * 64 + lane; f0 < nf; f0 += GU * stride) {
@@ -811,12 +840,12 @@ struct Engine {
             if (t[q] < 0) continue;
             int64_t val = (int64_t)c[q] - h[q] - v;
             if (val < 0) { fail(OT_EINTERNAL); val = 0; }
-            top2_push(a1, ta1, a2, ta2, pack(val, i[q]), t[q]);
+            top2_push(a1, ta1, a2, ta2, kpack(val, i[q]), t[q]);
           }
         }
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) {
-          uint64_t b1 = __shfl_xor(a1, off, 64), b2 = __shfl_xor(a2, off, 64);
+          Key b1 = __shfl_xor(a1, off, 64), b2 = __shfl_xor(a2, off, 64);
           int tb1 = __shfl_xor(ta1, off, 64), tb2 = __shfl_xor(ta2, off, 64);
           top2_merge(a1, ta1, a2, ta2, b1, tb1, b2, tb2);
         }
@@ -828,9 +857,9 @@ struct Engine {
       __syncthreads();
       if (wpc > 1 && tid < per_round && base + tid < g) {
         const int w0 = tid * wpc;
-        uint64_t a1 = pk1[w0], a2 = pk2[w0];
+        Key a1 = (Key)pk1[w0], a2 = (Key)pk2[w0];
         int ta1 = pt[2 * w0], ta2 = pt[2 * w0 + 1];
-        for (int w = w0 + 1; w < w0 + wpc; ++w) top2_merge(a1, ta1, a2, ta2, pk1[w], pt[2 * w], pk2[w], pt[2 * w + 1]);
+        for (int w = w0 + 1; w < w0 + wpc; ++w) top2_merge(a1, ta1, a2, ta2, (Key)pk1[w], pt[2 * w], (Key)pk2[w], pt[2 * w + 1]);
         const int s = base + tid;
         gk1[s] = a1; gt1[s] = ta1; gk2[s] = a2; gt2[s] = ta2;
       }
@@ -840,7 +869,7 @@ struct Engine {
     for (int k = 0; k < CPT; ++k) {
       if (!((req >> k) & 1u)) continue;
       const int s = slot[k];
-      k1[k] = gk1[s]; t1[k] = gt1[s]; k2[k] = gk2[s]; t2[k] = gt2[s];
+      k1[k] = (Key)gk1[s]; t1[k] = gt1[s]; k2[k] = (Key)gk2[s]; t2[k] = gt2[s];
       stl &= ~(1u << k);
     }
     return (int64_t)g * (int64_t)nf;
@@ -943,6 +972,11 @@ struct Engine {
     gmin = 0x7fffffff; gmax = (int)0x80000000;
     for (int w = 0; w < NW; ++w) { gmin = min(gmin, ired[w]); gmax = max(gmax, ired[NW + w]); }
     narrow = (int64_t)gmax - (int64_t)gmin < (1ll << 30);
+    if (COMPACT && ((int64_t)gmax - (int64_t)gmin >= kCompactRange || n > kCompactMaxN)) {
+      // the caller chose compact keys for a range they cannot hold
+      if (P.stats && tid == 0) { ot_stats s = {}; s.status = OT_EINTERNAL; *P.stats = s; }
+      return;
+    }
     if ((int64_t)gmax - (int64_t)gmin > 0x7fffffffll) {
       if (P.stats && tid == 0) { ot_stats s = {}; s.status = OT_ERANGE; *P.stats = s; }
       return;
@@ -954,7 +988,7 @@ struct Engine {
     stl = 0;
 #pragma unroll
     for (int k = 0; k < CPT; ++k) {
-      k1[k] = kInf; k2[k] = kInf; t1[k] = -1; t2[k] = -1; vj[k] = 0; dcol[k] = 0; ctree[k] = -1;
+      k1[k] = KINF; k2[k] = KINF; t1[k] = -1; t2[k] = -1; vj[k] = 0; dcol[k] = 0; ctree[k] = -1;
     }
     {
       uint64_t b1[CPT], b2[CPT];
@@ -1002,9 +1036,9 @@ struct Engine {
         if (col(k) >= n) continue;
         vj[k] = colred ? (int32_t)kval(b1[k]) : 0;
         if (K == nr) {
-          k1[k] = pack(kval(b1[k]) - vj[k], krow(b1[k]));
+          k1[k] = kpack(kval(b1[k]) - vj[k], krow(b1[k]));
           t1[k] = krow(b1[k]);
-          if (b2[k] != kInf) { k2[k] = pack(kval(b2[k]) - vj[k], krow(b2[k])); t2[k] = krow(b2[k]); }
+          if (b2[k] != kInf) { k2[k] = kpack(kval(b2[k]) - vj[k], krow(b2[k])); t2[k] = krow(b2[k]); }
         }
       }
     }
@@ -1071,7 +1105,9 @@ struct Engine {
       if (level > D) { D = level; ++st_dual; }
       // the watchdog; and with a tree cap the level adds up over stages and
       // could in principle leave the 32-bit range of the per-column levels
-      if (++st_levels > watchdog || D > 0x7ffffffell) { fail(OT_EINTERNAL); break; }
+      // (compact keys hold levels below 2^20; the cost range bounds the level
+      // by R < 2^18 unless a tree cap lets it add up over stages)
+      if (++st_levels > watchdog || D > (COMPACT ? (1ll << 20) - 1 : 0x7ffffffell)) { fail(OT_EINTERNAL); break; }
       const int64_t t1_ = timers ? now_ticks() : 0;
       tm_select += t1_ - t0;
 
@@ -1089,11 +1125,11 @@ struct Engine {
 #pragma unroll
         for (int k = 0; k < CPT; ++k) {
           const int j = col(k);
-          if (j >= n || ((vis >> k) & 1u) || k1[k] == kInf || stale(k) || kval(k1[k]) != D) continue;
+          if (j >= n || ((vis >> k) & 1u) || k1[k] == KINF || stale(k) || kv(k1[k]) != D) continue;
           vis |= 1u << k;
           dcol[k] = (int32_t)D;
           ctree[k] = t1[k];
-          const uint64_t e = etag | ((uint64_t)j << 24) | ((uint64_t)krow(k1[k]) << 12) | (uint64_t)(uint32_t)t1[k];
+          const uint64_t e = etag | ((uint64_t)j << 24) | ((uint64_t)kr(k1[k]) << 12) | (uint64_t)(uint32_t)t1[k];
           __hip_atomic_store(&lst[1 + atomicAdd(&ctl[LCNT], 1)], e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
         __syncthreads();
@@ -1174,8 +1210,8 @@ struct Engine {
 #pragma unroll
       for (int k = 0; k < CPT; ++k) {
         const int j = col(k);
-        if (j >= n || ((vis >> k) & 1u) || k1[k] == kInf || stale(k) || kval(k1[k]) != D) continue;
-        const int p = krow(k1[k]);
+        if (j >= n || ((vis >> k) & 1u) || k1[k] == KINF || stale(k) || kv(k1[k]) != D) continue;
+        const int p = kr(k1[k]);
         const int tr = t1[k];
         vis |= 1u << k;
         dcol[k] = (int32_t)D;
@@ -1240,9 +1276,9 @@ struct Engine {
           if (((vis >> k) & 1u) && !alive[ctree[k]]) {
             const int64_t d = D - dcol[k];
             vj[k] -= (int32_t)d;
-            const uint64_t sh = (uint64_t)d << kRowBits;
-            if (k1[k] != kInf) k1[k] += sh;
-            if (k2[k] != kInf) k2[k] += sh;
+            const Key sh = (Key)d << KB;
+            if (k1[k] != KINF) k1[k] += sh;
+            if (k2[k] != KINF) k2[k] += sh;
             vis &= ~(1u << k);
             ctree[k] = -1;
           }
@@ -1253,7 +1289,7 @@ struct Engine {
           } else if (t2[k] >= 0 && !alive[t2[k]]) {
             t2[k] = -1;
           }
-          if (nalive == 0) { k1[k] = kInf; k2[k] = kInf; t1[k] = -1; t2[k] = -1; }
+          if (nalive == 0) { k1[k] = KINF; k2[k] = KINF; t1[k] = -1; t2[k] = -1; }
           recompute_stale(k);
         }
         if (tid == 0) ctl[FCNT] = 0;

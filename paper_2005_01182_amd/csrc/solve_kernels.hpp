@@ -18,6 +18,34 @@ namespace otkm {
 // ---------------------------------------------------------------------------
 // single instance
 // ---------------------------------------------------------------------------
+// Whether compact (32-bit) keys hold this instance: the cost range from the
+// grid-wide initial sweeps is below kCompactRange, n <= kCompactMaxN, and
+// every free row is a root.  Uniform over the workgroup; uses the start of
+// the LDS before the engine lays it out.
+template <int BLOCK>
+__device__ __forceinline__ bool compact_keys_fit(const Problem &P, char *smem) {
+  constexpr int NW = BLOCK / 64;
+  const int nr = (P.nr > 0 && P.nr < P.n) ? P.nr : P.n;
+  if (!P.init_u || !P.init_rmax || P.n > kCompactMaxN || (P.max_paths > 0 && P.max_paths < nr)) return false;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  int64_t mn = INT64_MAX;
+  int mx = (int)0x80000000;
+  for (int i = tid; i < nr; i += BLOCK) {
+    mn = min(mn, P.init_u[i]);
+    mx = max(mx, P.init_rmax[i]);
+  }
+  int lo = wave_min_i32((int)max(mn, (int64_t)INT32_MIN)), hi = wave_max_i32(mx);
+  int *red = (int *)smem;
+  if (lane == 0) { red[2 * wid] = lo; red[2 * wid + 1] = hi; }
+  __syncthreads();
+  lo = 0x7fffffff;
+  hi = (int)0x80000000;
+#pragma unroll
+  for (int w = 0; w < NW; ++w) { lo = min(lo, red[2 * w]); hi = max(hi, red[2 * w + 1]); }
+  __syncthreads();  // the engine reuses this LDS
+  return (int64_t)hi - (int64_t)lo < kCompactRange;
+}
+
 template <int BLOCK, int CPT>
 __global__ __launch_bounds__(BLOCK) void k_assign_one(Problem P, const int32_t *gate) {
   extern __shared__ __align__(16) char smem[];
@@ -29,7 +57,13 @@ __global__ __launch_bounds__(BLOCK) void k_assign_one(Problem P, const int32_t *
       return;
     }
   }
-  Engine<BLOCK, CPT, (BLOCK <= 512), false, true> E;  // at 1024 threads the registers are too few for LONG
+  constexpr bool kLong = BLOCK <= 512;  // at 1024 threads the registers are too few for LONG
+  if (compact_keys_fit<BLOCK>(P, smem)) {
+    Engine<BLOCK, CPT, kLong, false, true, true> E;
+    E.run(P, smem);
+    return;
+  }
+  Engine<BLOCK, CPT, kLong, false, true> E;
   E.run(P, smem);
 }
 
@@ -41,6 +75,12 @@ __global__ __launch_bounds__(BLOCK) void k_assign_one(Problem P, const int32_t *
 template <int BLOCK, int CPT>
 __global__ __launch_bounds__(BLOCK) void k_assign_grid(Problem P) {
   extern __shared__ __align__(16) char smem[];
+  // every workgroup reads the same sweep results, so all of them pick the same keys
+  if (compact_keys_fit<BLOCK>(P, smem)) {
+    Engine<BLOCK, CPT, true, true, true, true> E;
+    E.run(P, smem);
+    return;
+  }
   Engine<BLOCK, CPT, true, true, true> E;
   E.run(P, smem);
 }
