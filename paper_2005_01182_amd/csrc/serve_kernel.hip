@@ -41,15 +41,21 @@ size_t serve_lds_bytes(int max_n) {
 }
 
 template <int CPT>
-__device__ __forceinline__ void serve_solve(const Problem &P, char *smem) {
-  Engine<kServeBlock, CPT> E;
-  E.run(P, smem);
+__device__ __forceinline__ void serve_solve(const Problem &P, char *smem, bool compact) {
+  if (compact) {
+    Engine<kServeBlock, CPT, false, false, false, true> E;
+    E.run(P, smem);
+  } else {
+    Engine<kServeBlock, CPT> E;
+    E.run(P, smem);
+  }
 }
 
 __global__ __launch_bounds__(kServeBlock) void k_serve(ServeArgs A) {
   extern __shared__ __align__(16) char smem[];
   __shared__ int s_idx, s_slot, s_n;
   __shared__ int64_t s_coff;
+  __shared__ int s_lo[kServeBlock / 64], s_hi[kServeBlock / 64];
   int32_t *ws = A.ws + (size_t)blockIdx.x * ws_ints(A.max_n);
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   for (;;) {
@@ -125,17 +131,28 @@ __global__ __launch_bounds__(kServeBlock) void k_serve(ServeArgs A) {
     __syncthreads();
     // ---- C_ij = round(|src_i - dst_j|), one wavefront per row, lanes along it
     int32_t *C = A.C + coff;
+    int lo = 0x7fffffff, hi = 0;
     for (int i = wid; i < n; i += kServeBlock / 64) {
       const int64_t sx = pts[2 * i], sy = pts[2 * i + 1];
       int32_t *row = C + (size_t)i * (size_t)n;
       for (int j = lane; j < n; j += 64) {
         const int64_t dx = sx - pts[2 * n + 2 * j], dy = sy - pts[2 * n + 2 * j + 1];
-        row[j] = grid_isqrt_round(dx * dx + dy * dy);
+        const int32_t c = grid_isqrt_round(dx * dx + dy * dy);
+        row[j] = c;
+        lo = min(lo, c);
+        hi = max(hi, c);
       }
     }
+    lo = wave_min_i32(lo);
+    hi = wave_max_i32(hi);
+    if (lane == 0) { s_lo[wid] = lo; s_hi[wid] = hi; }
     // the engine reads C back (and reuses the LDS): every store done and visible
     __threadfence();
     __syncthreads();
+#pragma unroll
+    for (int w = 0; w < kServeBlock / 64; ++w) { lo = min(lo, s_lo[w]); hi = max(hi, s_hi[w]); }
+    // compact keys when the cost range allows them (same results, fewer instructions)
+    const bool compact = (int64_t)hi - (int64_t)lo < kCompactRange && n <= kCompactMaxN;
     Problem P;
     P.C = C;
     P.n = n;
@@ -153,10 +170,10 @@ __global__ __launch_bounds__(kServeBlock) void k_serve(ServeArgs A) {
     P.v = A.v + slot * M;
     P.stats = A.stats + slot;
     P.ws = ws;
-    if (n <= kServeBlock) serve_solve<1>(P, smem);
-    else if (n <= 2 * kServeBlock) serve_solve<2>(P, smem);
-    else if (n <= 4 * kServeBlock) serve_solve<4>(P, smem);
-    else serve_solve<8>(P, smem);
+    if (n <= kServeBlock) serve_solve<1>(P, smem, compact);
+    else if (n <= 2 * kServeBlock) serve_solve<2>(P, smem, compact);
+    else if (n <= 4 * kServeBlock) serve_solve<4>(P, smem, compact);
+    else serve_solve<8>(P, smem, compact);
     // outputs live in host memory: every thread's writes visible system-wide
     // before the completion flag is released
     __threadfence_system();
