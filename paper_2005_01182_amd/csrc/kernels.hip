@@ -17,6 +17,40 @@
 namespace otkm {
 
 // ---------------------------------------------------------------------------
+// batch: which instances compact keys hold
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_batch_flags(BatchArgs A) {
+  const int idx = blockIdx.x;
+  if (idx >= A.nq) return;
+  const int k = A.order ? A.order[idx] : idx;
+  if ((unsigned)k >= (unsigned)A.count) return;
+  const int n = A.n[k];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  __shared__ int s_lo[4], s_hi[4];
+  int lo = 0x7fffffff, hi = (int)0x80000000;
+  const bool sized = n >= 1 && n <= kCompactMaxN && n <= A.max_n && A.max_paths <= 0;
+  if (sized) {
+    const int32_t *C = A.C + A.coff[k];
+    const int64_t total = (int64_t)n * n;
+    int64_t q = threadIdx.x;
+    for (; q + 768 < total; q += 1024) {
+      const int a = C[q], b = C[q + 256], c = C[q + 512], d = C[q + 768];
+      lo = min(lo, min(min(a, b), min(c, d)));
+      hi = max(hi, max(max(a, b), max(c, d)));
+    }
+    for (; q < total; q += 256) { lo = min(lo, C[q]); hi = max(hi, C[q]); }
+  }
+  lo = wave_min_i32(lo);
+  hi = wave_max_i32(hi);
+  if (lane == 0) { s_lo[wid] = lo; s_hi[wid] = hi; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < 4; ++w) { lo = min(lo, s_lo[w]); hi = max(hi, s_hi[w]); }
+    A.kflags[k] = (sized && (int64_t)hi - (int64_t)lo < kCompactRange) ? 1 : 0;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // grid-wide initial sweeps of one instance (the two full passes over C that the
 // KM reduction needs: row minima, then per column the two smallest C_ij - u_i)
 // ---------------------------------------------------------------------------

@@ -25,6 +25,12 @@ struct BatchArgs {
   int32_t *head;          // queue head (reset to 0 before the launch)
   int32_t *done;          // [count] or null: done[k] = tag once instance k's outputs are visible to the host
   int32_t tag;
+  // Optional: per instance whether compact keys hold it ([count] bytes, set by
+  // the launch) and a second queue head; with both, the launch runs the
+  // compact-key kernel over those instances and the 64-bit-key kernel over the
+  // rest, one after the other on the stream.
+  uint8_t *kflags = nullptr;
+  int32_t *head2 = nullptr;
 };
 
 struct TransportArgs {

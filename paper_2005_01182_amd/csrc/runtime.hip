@@ -567,6 +567,7 @@ int ot_assign_batch_dev(int32_t count, int32_t max_n, const int32_t *dC, const i
   int err = OT_OK;
   auto *head = (int32_t *)stream_ws(s, 1, 256, &err);
   auto *dws = (int32_t *)stream_ws(s, 2, 4 * ws_ints(max_n) * (size_t)grid, &err);
+  auto *kflags = (uint8_t *)stream_ws(s, 5, (size_t)count, &err);
   if (err) return err;
   hipError_t e = launch_fill_i32(head, 0, 1, s);
   if (e != hipSuccess) return map_hip(e);
@@ -574,6 +575,7 @@ int ot_assign_batch_dev(int32_t count, int32_t max_n, const int32_t *dC, const i
   A.C = dC; A.CT = dCT; A.coff = coff; A.n = n; A.voff = voff; A.order = order;
   A.count = count; A.nq = nq; A.max_n = max_n; A.max_paths = 0;
   A.plan = dplan; A.cost = dcost; A.u = du; A.v = dv; A.stats = dstats; A.ws = dws; A.head = head; A.done = nullptr; A.tag = 0;
+  A.kflags = kflags; A.head2 = head + 32;  // another 128-byte line of the same buffer
   return map_hip(launch_assign_batch(A, block, grid, s));
 }
 
@@ -618,6 +620,8 @@ int ot_assign_batch(int32_t count, const int32_t *const *C, const int32_t *n, in
   auto *dn = (int32_t *)pool_get(18, 4 * (size_t)count, &err);
   auto *dorder = (int32_t *)pool_get(19, 4 * (size_t)count, &err);
   auto *head = (int32_t *)pool_get(20, 4 * 8, &err);
+  auto *head2 = (int32_t *)pool_get(21, 4 * 8, &err);
+  auto *kflags = (uint8_t *)pool_get(22, (size_t)count, &err);
   if (err) return err;
   hipError_t e;
   for (int k = 0; k < count; ++k)
@@ -652,6 +656,7 @@ int ot_assign_batch(int32_t count, const int32_t *const *C, const int32_t *n, in
     A.C = dC; A.coff = dcoff; A.n = dn; A.voff = dvoff; A.order = dorder + spans[ci].first;
     A.count = count; A.nq = spans[ci].second; A.max_n = max_n; A.max_paths = 0;
     A.plan = dplan; A.cost = dcost; A.u = du; A.v = dv; A.stats = dstats; A.ws = dws; A.head = head + ci; A.done = nullptr; A.tag = 0;
+    A.kflags = kflags; A.head2 = head2 + ci;
     if ((e = launch_assign_batch(A, block, grid, s)) != hipSuccess) return map_hip(e);
     ++ci;
   }

@@ -92,19 +92,26 @@ __global__ __launch_bounds__(BLOCK) void k_assign_grid(Problem P) {
 // spill at 8 columns per lane) and twice as many instances share each CU, which
 // measured 126k -> 181k solves/s on the embedding batch; three or four per SIMD
 // spill heavily and lose.
-template <int BLOCK, int CPT>
+// COMPACT: the compact-key engine over the instances whose flag is set (the
+// 64-bit-key kernel takes the others); without flags the 64-bit-key kernel
+// takes every instance.
+template <int BLOCK, int CPT, bool COMPACT = false>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2))) void k_assign_batch(BatchArgs A) {
   extern __shared__ __align__(16) char smem[];
   __shared__ int s_idx;
   int32_t *ws = A.ws + (size_t)blockIdx.x * ws_ints(A.max_n);
+  constexpr bool kSplit = !(BLOCK == 64 && CPT == 1);  // the one-wavefront class does not split
+  const bool split = kSplit && A.kflags && A.head2;
+  int32_t *head = (COMPACT || !split) ? A.head : A.head2;
   for (;;) {
-    if (threadIdx.x == 0) s_idx = atomicAdd(A.head, 1);
+    if (threadIdx.x == 0) s_idx = atomicAdd(head, 1);
     __syncthreads();
     const int idx = s_idx;
     __syncthreads();
     if (idx >= A.nq) break;  // every workgroup reaches this exit once the queue drains
     const int k = A.order ? A.order[idx] : idx;
     if ((unsigned)k >= (unsigned)A.count) continue;  // no such instance: nothing to report or flag
+    if (split && (A.kflags[k] != 0) != COMPACT) continue;  // the other kernel's instance
     const int n = A.n[k];
     if (n < 1 || n > A.max_n || n > BLOCK * CPT) {
       if (threadIdx.x == 0) {
@@ -137,7 +144,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2))) void
       WaveEngine W;
       W.run(P, smem);
     } else {
-      Engine<BLOCK, CPT> E;
+      Engine<BLOCK, CPT, false, false, false, COMPACT> E;
       E.run(P, smem);
     }
     if (A.done) {
@@ -152,6 +159,11 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2))) void
 }
 
 __global__ void k_fill_u64(uint64_t *p, uint64_t value, int64_t count);
+
+// Per queue entry (one workgroup each): whether compact keys hold the
+// instance (cost range below kCompactRange, n <= kCompactMaxN, every free row
+// a root).  One pass over its matrix.
+__global__ void k_batch_flags(BatchArgs A);
 
 // ---------------------------------------------------------------------------
 // launch helpers
@@ -205,8 +217,19 @@ static hipError_t grid(const Problem &P, int wgs, hipStream_t s) {
 template <int B, int CPT>
 static hipError_t batch(const BatchArgs &A, int grid, hipStream_t s) {
   const size_t lds = solve_lds<B>(A.max_n);
-  hipError_t e = allow_lds<k_assign_batch<B, CPT>>(lds);
-  if (e != hipSuccess) return e;
+  hipError_t e;
+  if constexpr (!(B == 64 && CPT == 1)) {
+    if (A.kflags && A.head2) {
+      // flags, then the compact-key kernel, then the 64-bit-key kernel on the rest
+      hipLaunchKernelGGL(k_batch_flags, dim3(A.nq), dim3(256), 0, s, A);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+      if ((e = launch_fill_i32(A.head2, 0, 1, s)) != hipSuccess) return e;
+      if ((e = allow_lds<k_assign_batch<B, CPT, true>>(lds)) != hipSuccess) return e;
+      hipLaunchKernelGGL((k_assign_batch<B, CPT, true>), dim3(grid), dim3(B), lds, s, A);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+  }
+  if ((e = allow_lds<k_assign_batch<B, CPT>>(lds)) != hipSuccess) return e;
   hipLaunchKernelGGL((k_assign_batch<B, CPT>), dim3(grid), dim3(B), lds, s, A);
   return hipGetLastError();
 }
