@@ -802,7 +802,9 @@ def bench_serve(args):
     with otkm.Server(hbm_budget_bytes=budget, max_inflight=512) as srv2:
         served_prefix = serve.summarize(serve.replay(srv2, reqs[:k_plain]))
     print("serve: one at a time %s; continuous batching %s" % (plain, served_prefix), file=sys.stderr, flush=True)
-    saturated = served["solves_per_s"] < 0.9 * offered
+    # saturated: the server falls behind the offered rate, or requests wait for
+    # admission (every slot or byte of the budget taken) for more than 0.1 s
+    saturated = served["solves_per_s"] < 0.95 * offered or served["queue_ms_p99"] > 100.0
     out = {"metric": "solves/s + achieved HBM GB/s at n=2048; p50/p99 latency batched vs plain",
            "value": served["solves_per_s"], "unit": "solves/s", "n_gpus": 1, "steps": 1, "warmup": 0,
            "ms_per_step": round(served["span_s"] * 1e3, 3), "higher_is_better": True, "scaling": "weak",

@@ -93,6 +93,10 @@ typedef struct ot_stats {
 /* Collect the per-phase device times (t_*_ns) in ot_stats; off by default
  * because reading the device clock adds latency to every level. */
 #define OT_FLAG_PHASE_TIMERS 1
+/* Keep 64-bit column keys even where the cost range lets the solver use its
+ * compact 32-bit keys (the same results, more instructions; for tests and
+ * comparisons). */
+#define OT_FLAG_WIDE_KEYS 2
 
 /* Solver options; pass NULL for the defaults (all zero). */
 typedef struct ot_options {
@@ -361,8 +365,8 @@ int ot_assign_sparse_batch_dev(int32_t count, const ot_sparse_desc *ddesc, int32
  * integer grid; its cost matrix C_ij = round(sqrt((x_i - x'_j)^2 + (y_i - y'_j)^2))
  * (exact integer rounding, ties cannot occur) is built on the device, so only
  * the points cross PCIe.  A server thread admits queued requests in arrival
- * order while the device bytes of the admitted ones (4 n^2 + 64 n per
- * request) stay within hbm_budget_bytes and a slot is free, and publishes each
+ * order while the device bytes of the admitted ones (8 n^2 + 64 n per
+ * request: the cost matrix and its transpose) stay within hbm_budget_bytes and a slot is free, and publishes each
  * into one queue in pinned host memory.  One persistent kernel serves every
  * size (one workgroup of 512 threads per request and per CU): its workgroups
  * take requests from the queue while the server keeps appending to it, build

@@ -79,7 +79,7 @@ extern "C" int ot_assign_dev_noalloc(const int32_t *dC, int32_t n, int32_t ld, c
     for (int k = 0; k < 3; ++k)
       if (opt->reserved[k] != 0) return OT_EINVAL;
     // one workgroup on the exact costs: no exchange state, no scaled copy
-    if (opt->max_paths < 0 || (opt->flags & ~OT_FLAG_PHASE_TIMERS) != 0 || opt->scale > 1 || opt->scale < 0 ||
+    if (opt->max_paths < 0 || (opt->flags & ~(OT_FLAG_PHASE_TIMERS | OT_FLAG_WIDE_KEYS)) != 0 || opt->scale > 1 || opt->scale < 0 ||
         opt->wgs > 1 || opt->wgs < 0)
       return OT_EINVAL;
     if (opt->block != 0) {

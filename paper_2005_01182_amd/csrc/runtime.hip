@@ -191,7 +191,7 @@ static int check_options(const ot_options *opt, int n, Opts *o) {
   if (opt) {
     for (int k = 0; k < 3; ++k)
       if (opt->reserved[k] != 0) return OT_EINVAL;
-    if (opt->max_paths < 0 || (opt->flags & ~OT_FLAG_PHASE_TIMERS) != 0 || opt->scale < 0 || opt->wgs < 0 ||
+    if (opt->max_paths < 0 || (opt->flags & ~(OT_FLAG_PHASE_TIMERS | OT_FLAG_WIDE_KEYS)) != 0 || opt->scale < 0 || opt->wgs < 0 ||
         opt->wgs > kMaxWgs)
       return OT_EINVAL;
     o->max_paths = opt->max_paths;

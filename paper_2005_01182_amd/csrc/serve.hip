@@ -3,9 +3,9 @@
 // Requests (n source and n target grid points) queue on the host.  A server
 // thread admits them in arrival order while a request slot is free and the
 // device bytes of the admitted ones stay within the budget: it reserves the
-// request's cost-matrix region in the device arena, copies its points into
-// the slot's pinned, device-mapped host buffer, writes the queue entry and
-// raises the queue's tail.  One persistent kernel (serve_kernel.hip) serves
+// request's region in the device arena (its cost matrix and the matrix's
+// transpose), copies its points into the slot's pinned, device-mapped host
+// buffer, writes the queue entry and raises the queue's tail.  One persistent kernel (serve_kernel.hip) serves
 // every size: its workgroups take entries while the host keeps appending,
 // build each request's matrix on the device from its points, solve it and
 // write plan, duals and cost straight into mapped host memory before
@@ -48,7 +48,9 @@ constexpr int kGenerations = 4;
 // With nothing outstanding for this long, the host asks the kernel to end.
 constexpr double kIdleQuitSeconds = 0.002;
 
-int64_t request_bytes(int n) { return 4ll * n * n + 64ll * n; }
+// device bytes of an admitted request: its cost matrix and the matrix's
+// transpose (8 n^2), and its share of the per-slot vectors
+int64_t request_bytes(int n) { return 8ll * n * n + 64ll * n; }
 
 struct Req {
   uint64_t id = 0;
@@ -237,7 +239,7 @@ bool admit(ot_server *s) {
     Req *r = *it;
     if (s->free_slots.empty() || s->inflight >= s->cfg.max_inflight) break;
     if (s->inflight_bytes + r->bytes > s->cfg.hbm_budget_bytes) { ++it; continue; }
-    const int64_t abytes = 4ll * r->n * r->n;
+    const int64_t abytes = 8ll * r->n * r->n;  // C, then its transpose
     const int64_t off = s->arena->alloc(abytes);
     if (off < 0) { ++it; continue; }
     r->off = off;

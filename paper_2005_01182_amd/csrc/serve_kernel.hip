@@ -151,13 +151,27 @@ __global__ __launch_bounds__(kServeBlock) void k_serve(ServeArgs A) {
     __syncthreads();
 #pragma unroll
     for (int w = 0; w < kServeBlock / 64; ++w) { lo = min(lo, s_lo[w]); hi = max(hi, s_hi[w]); }
+    // ---- its transpose, CT_ji = C_ij (one wavefront per column of C): a stale
+    // column's refresh then reads one contiguous row instead of one memory
+    // line per entry, which at full load is most of the HBM traffic
+    int32_t *CT = C + (size_t)n * (size_t)n;
+    for (int j = wid; j < n; j += kServeBlock / 64) {
+      const int64_t tx = pts[2 * n + 2 * j], ty = pts[2 * n + 2 * j + 1];
+      int32_t *row = CT + (size_t)j * (size_t)n;
+      for (int i = lane; i < n; i += 64) {
+        const int64_t dx = pts[2 * i] - tx, dy = pts[2 * i + 1] - ty;
+        row[i] = grid_isqrt_round(dx * dx + dy * dy);
+      }
+    }
+    __threadfence();
+    __syncthreads();
     // compact keys when the cost range allows them (same results, fewer instructions)
     const bool compact = (int64_t)hi - (int64_t)lo < kCompactRange && n <= kCompactMaxN;
     Problem P;
     P.C = C;
     P.n = n;
     P.ld = n;
-    P.CT = nullptr;
+    P.CT = CT;
     P.Cout = nullptr;
     P.ldo = n;
     P.dscale = 1;

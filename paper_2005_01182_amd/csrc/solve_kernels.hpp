@@ -26,7 +26,9 @@ template <int BLOCK>
 __device__ __forceinline__ bool compact_keys_fit(const Problem &P, char *smem) {
   constexpr int NW = BLOCK / 64;
   const int nr = (P.nr > 0 && P.nr < P.n) ? P.nr : P.n;
-  if (!P.init_u || !P.init_rmax || P.n > kCompactMaxN || (P.max_paths > 0 && P.max_paths < nr)) return false;
+  if (!P.init_u || !P.init_rmax || P.n > kCompactMaxN || (P.max_paths > 0 && P.max_paths < nr) ||
+      (P.flags & OT_FLAG_WIDE_KEYS))
+    return false;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   int64_t mn = INT64_MAX;
   int mx = (int)0x80000000;

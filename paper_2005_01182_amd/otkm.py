@@ -53,6 +53,7 @@ class ot_options(ctypes.Structure):
 
 
 OT_FLAG_PHASE_TIMERS = 1
+OT_FLAG_WIDE_KEYS = 2
 
 
 class ot_serve_cfg(ctypes.Structure):
@@ -172,11 +173,11 @@ def device_info() -> dict:
             "mem_gb": props.total_memory / 2**30}
 
 
-def _options(max_paths=0, block=0, timers=False, scale=1, wgs=0):
+def _options(max_paths=0, block=0, timers=False, scale=1, wgs=0, wide_keys=False):
     o = ot_options()
     o.max_paths = int(max_paths)
     o.block = int(block)
-    o.flags = OT_FLAG_PHASE_TIMERS if timers else 0
+    o.flags = (OT_FLAG_PHASE_TIMERS if timers else 0) | (OT_FLAG_WIDE_KEYS if wide_keys else 0)
     o.scale = int(scale)
     o.wgs = int(wgs)
     return o
@@ -184,7 +185,7 @@ def _options(max_paths=0, block=0, timers=False, scale=1, wgs=0):
 
 # ----------------------------------------------------------------------------- host calls
 def ot_assign(C, max_paths: int = 0, block: int = 0, with_stats: bool = False, timers: bool = False,
-              scale: int = 1, wgs: int = 0):
+              scale: int = 1, wgs: int = 0, wide_keys: bool = False):
     """Assignment of a square int32 cost matrix (exact; with scale > 1, optimal for floor(C / scale)).
 
     Returns (plan, cost, u, v) or (plan, cost, u, v, stats_dict).  With scale > 1
@@ -200,7 +201,7 @@ def ot_assign(C, max_paths: int = 0, block: int = 0, with_stats: bool = False, t
     v = np.empty(n, np.int64)
     cost = ctypes.c_int64(0)
     st = ot_stats()
-    opt = _options(max_paths, block, timers, scale, wgs)
+    opt = _options(max_paths, block, timers, scale, wgs, wide_keys)
     rc = load().ot_assign_ex(_p(C), n, ctypes.byref(opt), _p(plan), ctypes.byref(cost), _p(u), _p(v),
                              ctypes.byref(st))
     _check(rc, "ot_assign")
@@ -209,7 +210,7 @@ def ot_assign(C, max_paths: int = 0, block: int = 0, with_stats: bool = False, t
 
 
 def ot_assign_rect(C, max_paths: int = 0, block: int = 0, with_stats: bool = False, timers: bool = False,
-                   wgs: int = 0):
+                   wgs: int = 0, wide_keys: bool = False):
     """Rectangular assignment of an n x m int32 cost matrix (n != m allowed): the
     smaller side matched completely, the larger side at most once.
 
@@ -226,7 +227,7 @@ def ot_assign_rect(C, max_paths: int = 0, block: int = 0, with_stats: bool = Fal
     v = np.empty(m, np.int64)
     cost = ctypes.c_int64(0)
     st = ot_stats()
-    opt = _options(max_paths, block, timers, wgs=wgs)
+    opt = _options(max_paths, block, timers, wgs=wgs, wide_keys=wide_keys)
     rc = load().ot_assign_rect(_p(C), n, m, ctypes.byref(opt), _p(plan), ctypes.byref(cost), _p(u), _p(v),
                                ctypes.byref(st))
     _check(rc, "ot_assign_rect")
@@ -406,11 +407,11 @@ def stats_tensor(count=1, device="cuda"):
 
 
 def ot_assign_dev(C, plan, cost, u=None, v=None, stats=None, max_paths=0, block=0, stream=None, ld=None,
-                  timers=False, scale=1, wgs=0):
+                  timers=False, scale=1, wgs=0, wide_keys=False):
     """Queue an assignment on device tensors (asynchronous on `stream`)."""
     n = int(C.shape[0])
     ld = int(ld if ld is not None else C.stride(0))
-    opt = _options(max_paths, block, timers, scale, wgs)
+    opt = _options(max_paths, block, timers, scale, wgs, wide_keys)
     rc = load().ot_assign_dev(_tp(C), n, ld, ctypes.byref(opt), _tp(plan), _tp(cost), _tp(u), _tp(v),
                               _tp(stats), _stream(stream))
     _check(rc, "ot_assign_dev")

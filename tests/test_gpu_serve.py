@@ -58,7 +58,7 @@ def test_served_results_equal_alone(otkm_gpu):
 def test_admission_respects_budget(otkm_gpu):
     rng = np.random.default_rng(2)
     n = 900
-    per = 4 * n * n + 64 * n
+    per = 8 * n * n + 64 * n  # the matrix, its transpose and the per-request vectors
     budget = 2 * per + 1000
     reqs = [points(rng, n) for _ in range(6)]
     with otkm_gpu.Server(hbm_budget_bytes=budget, max_n=1024) as srv:
