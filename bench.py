@@ -565,10 +565,10 @@ def bench_sparse(args):
         out["metric"] = "solves/s, sparse k-NN assignment"
         out["roofline"] = roofline(float(np.mean(b)), float(np.mean(per)) / 1e3)
         out["latency_ms"] = {"p50": pct(per, 50), "p99": pct(per, 99)}
-        out["solver_counters"] = {"levels": int(stats[0, F["levels"]]), "rounds": int(stats[0, F["aug_events"]]),
+        out["solver_counters"] = {"levels": int(stats[0, F["levels"]]), "aug_events": int(stats[0, F["aug_events"]]),
                                   "level_rises": int(stats[0, F["dual_adjusts"]]),
                                   "rows_swept": int(stats[0, F["rows_swept"]]),
-                                  "edges_swept": int(stats[0, F["gathers"]]), "alg_bytes_per_solve": int(b[0])}
+                                  "edges_read": int(stats[0, F["gathers"]]), "alg_bytes_per_solve": int(b[0])}
         if not args.skip_cpu:
             import oracle
             ref = oracle.assign_sparse(*g)

@@ -332,12 +332,15 @@ int ot_assign_sparse(const int64_t *ptr, const int32_t *idx, const int32_t *cost
                      int32_t *plan, int64_t *total, int64_t *u, int64_t *v, ot_stats *stats);
 
 /* The same on device buffers, asynchronous on stream (NULL: the library's
- * stream).  The device checks the column range (OT_EINVAL in dstats->status)
- * and reports OT_EINFEASIBLE there; ptr must be a valid offset array.  A
- * column given twice in a row counts at its cheapest copy.  du, dv, dstats
- * may be NULL. */
+ * stream).  nnz is the length of idx and cost, at least ptr[n] (it sizes the
+ * library's workspace for the graph by columns, which the solve builds first;
+ * at most 2^31 - 1, else OT_ETOOBIG).  The device checks the column range and
+ * ptr[n] - ptr[0] <= nnz (OT_EINVAL in dstats->status) and reports
+ * OT_EINFEASIBLE there;
+ * ptr must be a valid offset array.  A column given twice in a row counts at
+ * its cheapest copy.  du, dv, dstats may be NULL. */
 int ot_assign_sparse_dev(const int64_t *dptr, const int32_t *didx, const int32_t *dcost, int32_t n, int32_t m,
-                         int32_t *dplan, int64_t *dtotal, int64_t *du, int64_t *dv, ot_stats *dstats,
+                         int64_t nnz, int32_t *dplan, int64_t *dtotal, int64_t *du, int64_t *dv, ot_stats *dstats,
                          void *stream);
 
 /* One sparse instance of a batch: every pointer is a device pointer. */

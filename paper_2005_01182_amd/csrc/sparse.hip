@@ -15,11 +15,11 @@
 namespace otkm {
 namespace {
 
-// one instance, one workgroup
+// one instance, one workgroup, the forest kept across augmentations
 template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_sparse_one(SparseProblem P) {
   extern __shared__ __align__(16) char smem[];
-  SparseEngine<BLOCK> E;
+  SparseEngine<BLOCK, true> E;
   E.run(P, smem);
 }
 
@@ -131,6 +131,9 @@ int ot_assign_sparse(const int64_t *ptr, const int32_t *idx, const int32_t *cost
   auto *dv = (int64_t *)pool_get(205, 8 * (size_t)m, &err);
   auto *dtot = (int64_t *)pool_get(206, 8, &err);
   auto *dst = (ot_stats *)pool_get(207, sizeof(ot_stats), &err);
+  auto *dcolptr = (int32_t *)pool_get(208, 4 * ((size_t)m + 1), &err);
+  auto *dcrow = (int32_t *)pool_get(209, 4 * E, &err);
+  auto *dccost = (int32_t *)pool_get(210, 4 * E, &err);
   if (err) return err;
   hipError_t e = hipSuccess;
   auto chk = [&](hipError_t x) { if (e == hipSuccess) e = x; };
@@ -142,6 +145,7 @@ int ot_assign_sparse(const int64_t *ptr, const int32_t *idx, const int32_t *cost
   SparseProblem P;
   P.ptr = dptr; P.idx = didx; P.cost = dcost; P.n = n; P.m = m;
   P.plan = dplan; P.total = dtot; P.u = du; P.v = dv; P.stats = dst;
+  P.colptr = dcolptr; P.crow = dcrow; P.ccost = dccost; P.cap = (int64_t)E;
   if (e == hipSuccess) chk(launch_sparse_one(P, s));
   ot_stats hs{};
   chk(hipMemcpyAsync(&hs, dst, sizeof(ot_stats), hipMemcpyDeviceToHost, s));
@@ -158,18 +162,25 @@ int ot_assign_sparse(const int64_t *ptr, const int32_t *idx, const int32_t *cost
 }
 
 int ot_assign_sparse_dev(const int64_t *dptr, const int32_t *didx, const int32_t *dcost, int32_t n, int32_t m,
-                         int32_t *dplan, int64_t *dtotal, int64_t *du, int64_t *dv, ot_stats *dstats, void *stream) {
-  if (!dptr || !dplan || !dtotal || n <= 0 || m < n) return OT_EINVAL;
-  if (m > OT_MAX_N) return OT_ETOOBIG;
-  {
-    std::lock_guard<std::mutex> lk(lib_mutex());
-    const int rc = init_locked();
-    if (rc) return rc;
-  }
+                         int64_t nnz, int32_t *dplan, int64_t *dtotal, int64_t *du, int64_t *dv, ot_stats *dstats,
+                         void *stream) {
+  if (!dptr || !dplan || !dtotal || n <= 0 || m < n || nnz < 0) return OT_EINVAL;
+  if (nnz > 0 && (!didx || !dcost)) return OT_EINVAL;
+  if (m > OT_MAX_N || nnz > (int64_t)INT32_MAX) return OT_ETOOBIG;  // column offsets are 32-bit
+  std::lock_guard<std::mutex> lk(lib_mutex());
+  int rc = init_locked();
+  if (rc) return rc;
   hipStream_t s = stream ? (hipStream_t)stream : lib_stream();
+  int err = OT_OK;
+  const size_t E = (size_t)std::max<int64_t>(nnz, 1);
+  auto *dcolptr = (int32_t *)stream_ws(s, 200, 4 * ((size_t)m + 1), &err);
+  auto *dcrow = (int32_t *)stream_ws(s, 201, 4 * E, &err);
+  auto *dccost = (int32_t *)stream_ws(s, 202, 4 * E, &err);
+  if (err) return err;
   SparseProblem P;
   P.ptr = dptr; P.idx = didx; P.cost = dcost; P.n = n; P.m = m;
   P.plan = dplan; P.total = dtotal; P.u = du; P.v = dv; P.stats = dstats;
+  P.colptr = dcolptr; P.crow = dcrow; P.ccost = dccost; P.cap = nnz;
   return map_hip(launch_sparse_one(P, s));
 }
 
@@ -182,7 +193,7 @@ int ot_assign_sparse_batch_dev(int32_t count, const ot_sparse_desc *ddesc, int32
   if (rc) return rc;
   hipStream_t s = stream ? (hipStream_t)stream : lib_stream();
   int err = OT_OK;
-  auto *head = (int32_t *)stream_ws(s, 200, 256, &err);
+  auto *head = (int32_t *)stream_ws(s, 203, 256, &err);
   if (err) return err;
   hipError_t e = launch_fill_i32(head, 0, 1, s);
   if (e != hipSuccess) return map_hip(e);

@@ -118,7 +118,7 @@ def load():
         lib.ot_transport_bins.argtypes = [_VP, _VP, _VP, _I32, _I32, _VP, _VP, _VP, _VP, _VP]
         lib.ot_transport_bins_dev.argtypes = [_VP, _VP, _VP, _I32, _I32, _I32, _VP, _VP, _VP, _VP, _VP, _VP]
         lib.ot_assign_sparse.argtypes = [_VP, _VP, _VP, _I32, _I32, _VP, _VP, _VP, _VP, _VP]
-        lib.ot_assign_sparse_dev.argtypes = [_VP, _VP, _VP, _I32, _I32, _VP, _VP, _VP, _VP, _VP, _VP]
+        lib.ot_assign_sparse_dev.argtypes = [_VP, _VP, _VP, _I32, _I32, ctypes.c_int64, _VP, _VP, _VP, _VP, _VP, _VP]
         lib.ot_assign_sparse_batch_dev.argtypes = [_I32, _VP, _I32, _VP]
         lib.ot_assign_batch.argtypes = [_I32, _VP, _VP, _VP, _VP, _VP, _VP, _VP]
         lib.ot_assign_dev.argtypes = [_VP, _I32, _I32, _VP, _VP, _VP, _VP, _VP, _VP, _VP]
@@ -472,8 +472,9 @@ def ot_transport_dev(C, r, c, S, X, cost, u, v, stats=None, stream=None):
 
 def ot_assign_sparse_dev(ptr, idx, cost, n, m, plan, total, u=None, v=None, stats=None, stream=None):
     """Queue a sparse assignment on device tensors (asynchronous on `stream`)."""
-    rc = load().ot_assign_sparse_dev(_tp(ptr), _tp(idx), _tp(cost), int(n), int(m), _tp(plan), _tp(total), _tp(u),
-                                     _tp(v), _tp(stats), _stream(stream))
+    nnz = int(idx.numel())
+    rc = load().ot_assign_sparse_dev(_tp(ptr), _tp(idx), _tp(cost), int(n), int(m), nnz, _tp(plan), _tp(total),
+                                     _tp(u), _tp(v), _tp(stats), _stream(stream))
     _check(rc, "ot_assign_sparse_dev")
 
 

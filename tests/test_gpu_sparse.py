@@ -138,6 +138,29 @@ def test_device_call_with_repeated_columns(otkm_gpu):
     assert oracle.certify_sparse(ptr, idx, cst, n, m, plan.cpu().numpy(), u.cpu().numpy(), v.cpu().numpy()) == 0
 
 
+def test_device_call_nnz_below_graph(otkm_gpu):
+    """nnz sizes the workspace of the graph by columns: a graph with more
+    entries than nnz says is rejected on the device (the buffers themselves
+    are whole, so every read stays in bounds)."""
+    import torch
+    ptr, idx, cst, n, m = wl.knn_assignment(100, 100, k=6, seed=3)
+    plan = torch.full((n,), -1, dtype=torch.int32, device="cuda")
+    total = torch.zeros(1, dtype=torch.int64, device="cuda")
+    st = otkm_gpu.stats_tensor(1)
+    dp, di, dc = _dev(ptr), _dev(idx), _dev(cst)
+    T = otkm_gpu._tp
+    rc = otkm_gpu.load().ot_assign_sparse_dev(T(dp), T(di), T(dc), n, m, int(ptr[-1]) - 1, T(plan), T(total), None,
+                                              None, T(st[0]), None)
+    assert rc == 0
+    torch.cuda.synchronize()
+    assert int(st[0, 7]) == otkm_gpu.OT_EINVAL
+    # the same call with the true length solves it
+    otkm_gpu.ot_assign_sparse_dev(dp, di, dc, n, m, plan, total, stats=st[0])
+    torch.cuda.synchronize()
+    assert int(st[0, 7]) == 0
+    assert int(total.item()) == oracle.assign_sparse(ptr, idx, cst, n, m)[1]
+
+
 def test_batch_against_oracle(otkm_gpu):
     import torch
     rng = np.random.default_rng(12)
