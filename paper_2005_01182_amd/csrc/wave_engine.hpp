@@ -17,7 +17,11 @@
 //   * the cost matrix sits in LDS (rows padded to n + 1 words, so a row and a
 //     column both read without bank conflicts): a sweep row is one LDS read
 //     per lane, and a stale column is recomputed by all 64 lanes at once (one
-//     row each) with a butterfly top-2 merge.
+//     row each) with two wavefront minima: the best key, then the best key of
+//     the rows outside the best key's tree;
+//   * keys are 32-bit (value << 12 | row) when the cost range is below 2^18
+//     and every free row is a root, as in the workgroup engine, else 64-bit;
+//     the order of keys, and so every choice, is the same either way.
 #pragma once
 
 #include "engine.hpp"
@@ -29,11 +33,27 @@ constexpr int kWaveMaxN = 64;
 // LDS bytes of the wave engine for an n x n instance.
 __host__ __device__ inline size_t wave_lds_bytes(int n) { return (size_t)n * (size_t)(n + 1) * 4; }
 
-struct WaveEngine {
+template <bool COMPACT>
+struct WaveCore {
+  using Key = typename KeyOf<COMPACT>::T;
+  static constexpr int KB = KeyOf<COMPACT>::kBits;
+  static constexpr Key KINF = (Key)~(Key)0;
+  // compact keys hold values below 2^20 (3 x the cost range at most); with
+  // 64-bit keys only the level is bounded (by the cost range, below 2^31)
+  static constexpr int64_t kValMax = (1ll << 20) - 1;
+  static constexpr int64_t kLevelMax = COMPACT ? kValMax : 0x7ffffffell;
+  static __device__ __forceinline__ Key kpk(int64_t val, int row) { return ((Key)val << KB) | (Key)(uint32_t)row; }
+  static __device__ __forceinline__ int64_t kv(Key k) { return (int64_t)(k >> KB); }
+  static __device__ __forceinline__ int kr(Key k) { return (int)(k & (((Key)1 << KB) - 1)); }
+  static __device__ __forceinline__ Key wmin(Key x) {
+    if constexpr (COMPACT) return wave_min_u32(x);
+    else return wave_min_u64(x);
+  }
+
   int n, lane;
   bool cl;  // this lane holds a column and a row of the instance
   // column state (lane j)
-  uint64_t k1, k2;
+  Key k1, k2;
   int t1, t2, ctree, par, mcol, dcol;
   int32_t vj;
   bool vis, stl;
@@ -67,8 +87,8 @@ struct WaveEngine {
         const int tr = __builtin_amdgcn_readlane(rtree, r[q]);
         const int64_t val = (int64_t)c[q] - hr - vj;
         if (cl) {
-          bad |= val < 0;  // a negative reduced cost would mean infeasible duals
-          const uint64_t key = pack(val < 0 ? 0 : val, r[q]);
+          bad |= val < 0 || (COMPACT && val > kValMax);  // a negative reduced cost would mean infeasible duals
+          const Key key = kpk(val < 0 ? 0 : val, r[q]);
           const bool lt = key < k1;
           top2_push(k1, t1, k2, t2, key, tr);
           if (lt) stl = false;  // the best key now comes from a live tree
@@ -77,74 +97,49 @@ struct WaveEngine {
     }
   }
 
-  // Exact top-2 of column j over the forest rows, every lane taking one row;
-  // the result is uniform.
-  __device__ __forceinline__ void column_top2(const int32_t *Cs, int S, int j, uint64_t &a1, int &ta1, uint64_t &a2,
-                                              int &ta2) {
+  // Exact top-2 of column j over the forest rows, every lane taking one row:
+  // the best key, then the best key among rows of other trees.  The result
+  // is uniform.
+  __device__ __forceinline__ void column_top2(const int32_t *Cs, int S, int j, Key &a1, int &ta1, Key &a2, int &ta2) {
     const int32_t vjj = __builtin_amdgcn_readlane(vj, j);
     const bool in = cl && ((forest >> lane) & 1ull);
     const int32_t c = in ? Cs[lane * S + j] : 0;
-    a1 = kInf; a2 = kInf; ta1 = -1; ta2 = -1;
+    Key a = KINF;
     if (in) {
       const int64_t val = (int64_t)c - h - vjj;
-      bad |= val < 0;
-      a1 = pack(val < 0 ? 0 : val, lane);
-      ta1 = rtree;
+      bad |= val < 0 || (COMPACT && val > kValMax);
+      a = kpk(val < 0 ? 0 : val, lane);
     }
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-      const uint64_t b1 = __shfl_xor(a1, off, 64), b2 = __shfl_xor(a2, off, 64);
-      const int tb1 = __shfl_xor(ta1, off, 64), tb2 = __shfl_xor(ta2, off, 64);
-      top2_merge(a1, ta1, a2, ta2, b1, tb1, b2, tb2);
-    }
+    a1 = wmin(a);
+    ta1 = a1 == KINF ? -1 : __builtin_amdgcn_readlane(rtree, kr(a1));
+    a2 = wmin(in && rtree != ta1 ? a : KINF);
+    ta2 = a2 == KINF ? -1 : __builtin_amdgcn_readlane(rtree, kr(a2));
   }
 
-  __device__ __forceinline__ void run(const Problem &P, char *smem) {
+  // Solve with C in LDS (row i at Cs[i * (n + 1)]) and mn = row minimum u_i
+  // in lane i.
+  __device__ __forceinline__ void solve(const Problem &P, const int32_t *Cs, int mn) {
     n = P.n;
     lane = threadIdx.x & 63;
     cl = lane < n;
     const int S = n + 1;
-    int32_t *Cs = (int32_t *)smem;
-    // ---- C into LDS (row i at Cs[i * S])
-    for (int i0 = 0; i0 < n; i0 += 8) {
-      int32_t c[8];
-#pragma unroll
-      for (int q = 0; q < 8; ++q) c[q] = (i0 + q < n && cl) ? P.C[(size_t)(i0 + q) * (size_t)P.ld + lane] : 0;
-#pragma unroll
-      for (int q = 0; q < 8; ++q)
-        if (i0 + q < n && cl) Cs[(i0 + q) * S + lane] = c[q];
-    }
-    __syncthreads();
-    // ---- u_i = min_j C_ij (lane i) and the cost range
-    int mn = 0x7fffffff, mx = (int)0x80000000;
-    if (cl)
-      for (int k = 0; k < n; ++k) {
-        const int32_t c = Cs[lane * S + k];
-        mn = min(mn, c);
-        mx = max(mx, c);
-      }
-    const int gmin = wave_min_i32(cl ? mn : 0x7fffffff), gmax = wave_max_i32(cl ? mx : (int)0x80000000);
-    if ((int64_t)gmax - (int64_t)gmin > 0x7fffffffll) {
-      if (P.stats && lane == 0) { ot_stats s = {}; s.status = OT_ERANGE; *P.stats = s; }
-      return;
-    }
     h = cl ? (int64_t)mn : 0;
     // ---- v_j = min_i (C_ij - u_i) and the two best rows of column j
-    uint64_t b1 = kInf, b2 = kInf;
+    Key b1 = KINF, b2 = KINF;
     for (int i = 0; i < n; ++i) {
       const int64_t ui = (int64_t)readlane64((uint64_t)h, i);
       const int32_t c = cl ? Cs[i * S + lane] : 0;
-      const uint64_t key = pack((int64_t)c - ui, i);
+      const Key key = kpk((int64_t)c - ui, i);
       if (key < b1) { b2 = b1; b1 = key; }
       else if (key < b2) b2 = key;
     }
     const int K = (P.max_paths <= 0 || P.max_paths > n) ? n : P.max_paths;
-    vj = cl ? (int32_t)kval(b1) : 0;
-    k1 = kInf; k2 = kInf; t1 = -1; t2 = -1;
+    vj = cl ? (int32_t)kv(b1) : 0;
+    k1 = KINF; k2 = KINF; t1 = -1; t2 = -1;
     if (cl && K == n) {
-      k1 = pack(kval(b1) - vj, krow(b1));
-      t1 = krow(b1);
-      if (b2 != kInf) { k2 = pack(kval(b2) - vj, krow(b2)); t2 = krow(b2); }
+      k1 = kpk(kv(b1) - vj, kr(b1));
+      t1 = kr(b1);
+      if (b2 != KINF) { k2 = kpk(kv(b2) - vj, kr(b2)); t2 = kr(b2); }
     }
     vis = false; stl = false; bad = false; dcol = 0; ctree = -1; par = -1; mcol = -1;
     mrow = -1; bend = kNoEnd;
@@ -168,17 +163,19 @@ struct WaveEngine {
       sweep(Cs, S, front);
       front = 0;
       // (2) smallest key over unreached columns (stale keys are lower bounds)
-      const bool open = cl && !vis && k1 != kInf;
-      uint64_t mv = wave_min_u64(open && !stl ? k1 : kInf) , ms = wave_min_u64(open && stl ? k1 : kInf);
-      if (ms != kInf && (mv == kInf || kval(ms) <= kval(mv))) {
-        const int64_t lim = mv == kInf ? INT64_MAX : kval(mv);
-        uint64_t R = __builtin_amdgcn_ballot_w64(open && stl && kval(k1) <= lim);
+      const bool open = cl && !vis && k1 != KINF;
+      Key mv = wmin(open && !stl ? k1 : KINF);
+      // stale keys are rare: their minimum only when there is one
+      const Key ms = __builtin_amdgcn_ballot_w64(open && stl) ? wmin(open && stl ? k1 : KINF) : KINF;
+      if (ms != KINF && (mv == KINF || kv(ms) <= kv(mv))) {
+        const int64_t lim = mv == KINF ? INT64_MAX : kv(mv);
+        uint64_t R = __builtin_amdgcn_ballot_w64(open && stl && kv(k1) <= lim);
         const int g = __builtin_popcountll(R);
         ++st_refresh;
         st_rcols += g;
         if (g > gcap) {
           // too many: one sweep of every forest row fixes all keys
-          if (cl) { k1 = kInf; k2 = kInf; t1 = -1; t2 = -1; }
+          if (cl) { k1 = KINF; k2 = KINF; t1 = -1; t2 = -1; }
           stl = false;
           ++st_resw;
           st_rows += __builtin_popcountll(forest);
@@ -188,24 +185,24 @@ struct WaveEngine {
           while (R) {
             const int j = bit_of(R);
             R &= R - 1;
-            uint64_t a1, a2;
+            Key a1, a2;
             int ta1, ta2;
             column_top2(Cs, S, j, a1, ta1, a2, ta2);
             if (lane == j) { k1 = a1; t1 = ta1; k2 = a2; t2 = ta2; stl = false; }
           }
         }
-        const bool open2 = cl && !vis && k1 != kInf;
-        mv = wave_min_u64(open2 && !stl ? k1 : kInf);
+        const bool open2 = cl && !vis && k1 != KINF;
+        mv = wmin(open2 && !stl ? k1 : KINF);
       }
-      if (mv == kInf) { err = OT_EINTERNAL; break; }
-      const int64_t level = kval(mv);
+      if (mv == KINF) { err = OT_EINTERNAL; break; }
+      const int64_t level = kv(mv);
       if (level > D) { D = level; ++st_dual; }
-      if (++st_levels > watchdog || D > 0x7ffffffell) { err = OT_EINTERNAL; break; }
+      if (++st_levels > watchdog || D > kLevelMax) { err = OT_EINTERNAL; break; }
 
       // (3) settle every unreached column at the current level
-      const bool settle = cl && !vis && !stl && k1 != kInf && kval(k1) == D;
+      const bool settle = cl && !vis && !stl && k1 != KINF && kv(k1) == D;
       const uint64_t Sm = __builtin_amdgcn_ballot_w64(settle);
-      if (settle) { vis = true; dcol = (int32_t)D; ctree = t1; par = krow(k1); }
+      if (settle) { vis = true; dcol = (int32_t)D; ctree = t1; par = kr(k1); }
       // matched rows of settled columns join their column's tree
       const int src = (cl && mrow >= 0) ? mrow : lane;
       const int ttree = __builtin_amdgcn_ds_bpermute(src * 4, t1);
@@ -257,16 +254,16 @@ struct WaveEngine {
           if (vis && !alive_tree(ctree)) {
             const int64_t d = D - dcol;
             vj -= (int32_t)d;
-            const uint64_t sh = (uint64_t)d << kRowBits;
-            if (k1 != kInf) k1 += sh;
-            if (k2 != kInf) k2 += sh;
+            const Key sh = (Key)d << KB;
+            if (k1 != KINF) k1 += sh;
+            if (k2 != KINF) k2 += sh;
             vis = false;
             ctree = -1;
           }
           if (t1 >= 0 && !alive_tree(t1)) { k1 = k2; t1 = t2; t2 = -1; }
           else if (t2 >= 0 && !alive_tree(t2)) t2 = -1;
-          if (nalive == 0) { k1 = kInf; k2 = kInf; t1 = -1; t2 = -1; }
-          stl = !(k1 == kInf || alive_tree(t1));
+          if (nalive == 0) { k1 = KINF; k2 = KINF; t1 = -1; t2 = -1; }
+          stl = !(k1 == KINF || alive_tree(t1));
         }
         // (6) with a tree cap, start new trees from the next free rows
         const int need = min(K - nalive, n - cursor);
@@ -302,6 +299,48 @@ struct WaveEngine {
       s.rows_swept = st_rows; s.gathers = st_gath; s.resweeps = st_resw; s.status = err;
       s.refreshes = st_refresh; s.refresh_cols = st_rcols;
       *P.stats = s;
+    }
+  }
+};
+
+struct WaveEngine {
+  __device__ __forceinline__ void run(const Problem &P, char *smem) {
+    const int n = P.n, lane = threadIdx.x & 63;
+    const bool cl = lane < n;
+    const int S = n + 1;
+    int32_t *Cs = (int32_t *)smem;
+    // ---- C into LDS (row i at Cs[i * S])
+    for (int i0 = 0; i0 < n; i0 += 8) {
+      int32_t c[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) c[q] = (i0 + q < n && cl) ? P.C[(size_t)(i0 + q) * (size_t)P.ld + lane] : 0;
+#pragma unroll
+      for (int q = 0; q < 8; ++q)
+        if (i0 + q < n && cl) Cs[(i0 + q) * S + lane] = c[q];
+    }
+    __syncthreads();
+    // ---- u_i = min_j C_ij (lane i) and the cost range
+    int mn = 0x7fffffff, mx = (int)0x80000000;
+    if (cl)
+      for (int k = 0; k < n; ++k) {
+        const int32_t c = Cs[lane * S + k];
+        mn = min(mn, c);
+        mx = max(mx, c);
+      }
+    const int gmin = wave_min_i32(cl ? mn : 0x7fffffff), gmax = wave_max_i32(cl ? mx : (int)0x80000000);
+    const int64_t range = (int64_t)gmax - (int64_t)gmin;
+    if (range > 0x7fffffffll) {
+      if (P.stats && lane == 0) { ot_stats s = {}; s.status = OT_ERANGE; *P.stats = s; }
+      return;
+    }
+    // compact keys: a key value stays below 3 x the range when every free row is a root
+    const bool all_roots = P.max_paths <= 0 || P.max_paths >= n;
+    if (range < kCompactRange && all_roots && !(P.flags & OT_FLAG_WIDE_KEYS)) {
+      WaveCore<true> W;
+      W.solve(P, Cs, mn);
+    } else {
+      WaveCore<false> W;
+      W.solve(P, Cs, mn);
     }
   }
 };

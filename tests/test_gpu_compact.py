@@ -53,6 +53,22 @@ def test_compact_equals_wide(otkm_gpu, wgs):
             assert a[1] == oracle.assign(C)[1]
 
 
+def test_compact_equals_wide_one_wavefront(otkm_gpu):
+    # n <= 64 runs on one wavefront, which picks its key width from the range it reads
+    rng = np.random.default_rng(23)
+    for n, hi in ((1, 0), (2, 5), (17, 1000), (40, 2), (63, 40000), (64, 1000), (64, 2 ** 18 - 1), (64, 2 ** 18)):
+        C = rng.integers(0, hi, (n, n), endpoint=True).astype(np.int32)
+        C[0, 0], C[-1, -1] = 0, hi
+        say("one wavefront n=%d range=%d" % (n, hi))
+        for mp in (0, 3):
+            a = otkm_gpu.ot_assign(C, with_stats=True, max_paths=mp)
+            b = otkm_gpu.ot_assign(C, with_stats=True, max_paths=mp, wide_keys=True)
+            assert a[4]["status"] == 0
+            same(a, b)
+            assert oracle.certify_assign(C, a[0], a[2], a[3]) == 0
+            assert a[1] == oracle.assign(C)[1]
+
+
 def test_compact_on_several_workgroups(otkm_gpu):
     C = wl.geometric_assignment(3000, seed=4)
     a = otkm_gpu.ot_assign(C, with_stats=True, wgs=4)

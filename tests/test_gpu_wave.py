@@ -38,6 +38,7 @@ def cases():
 @pytest.mark.parametrize("max_paths", [0, 1, 3])
 def test_wave_engine_equals_workgroup_engine(otkm_gpu, max_paths):
     for name, n, C in cases():
+        say(name, n, "max_paths", max_paths)
         a = otkm_gpu.ot_assign(C, max_paths=max_paths, with_stats=True)            # one wavefront
         b = otkm_gpu.ot_assign(C, max_paths=max_paths, block=256, with_stats=True)  # workgroup engine
         assert a[4]["status"] == 0 and b[4]["status"] == 0, (name, n)
