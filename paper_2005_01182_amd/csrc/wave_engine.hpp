@@ -31,7 +31,8 @@ namespace otkm {
 constexpr int kWaveMaxN = 64;
 
 // LDS bytes of the wave engine for an n x n instance.
-__host__ __device__ inline size_t wave_lds_bytes(int n) { return (size_t)n * (size_t)(n + 1) * 4; }
+// C with rows padded to n + 1 words, then a 64-word row map used when paths flip.
+__host__ __device__ inline size_t wave_lds_bytes(int n) { return ((size_t)n * (size_t)(n + 1) + 64) * 4; }
 
 template <bool COMPACT>
 struct WaveCore {
@@ -52,6 +53,7 @@ struct WaveCore {
 
   int n, lane;
   bool cl;  // this lane holds a column and a row of the instance
+  int32_t *rmap;  // [64] in LDS: the new column of each row on a flipped path
   // column state (lane j)
   Key k1, k2;
   int t1, t2, ctree, par, mcol, dcol;
@@ -67,71 +69,125 @@ struct WaveCore {
   static __device__ __forceinline__ int bit_of(uint64_t m) { return __builtin_ctzll(m); }
   __device__ __forceinline__ bool alive_tree(int t) const { return t >= 0 && ((alive >> t) & 1ull); }
 
-  // Fold rows `rows` (a uniform mask) into the column keys.
+  // c - h_r - v_j for row r's entry c of this lane's column (the reduced cost
+  // plus the level at which r joined).  With compact keys the cost range R is
+  // below 2^18 and the result lies in [-R, 5R], so 32-bit wrapping arithmetic
+  // gives it exactly.
+  __device__ __forceinline__ int64_t reduced(int32_t c, int r, int32_t vjj) const {
+    if constexpr (COMPACT) {
+      const uint32_t hr = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(uint64_t)h, r);
+      return (int32_t)((uint32_t)c - hr - (uint32_t)vjj);
+    } else {
+      return (int64_t)c - (int64_t)readlane64((uint64_t)h, r) - vjj;
+    }
+  }
+
+  // Fold rows `rows` (a uniform mask) into the column keys.  Every lane reads
+  // (lanes past n read column 0 and keep no key), so the four reads of a
+  // batch are issued back to back.
   __device__ __forceinline__ void sweep(const int32_t *Cs, int S, uint64_t rows) {
+    const int lc = cl ? lane : 0;
     while (rows) {
-      // four rows' LDS reads in flight at a time
       int r[4];
-      int32_t c[4];
       int cnt = 0;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        r[q] = rows ? bit_of(rows) : -1;
+        r[q] = rows ? bit_of(rows) : 0;
         if (rows) { rows &= rows - 1; ++cnt; }
-        c[q] = (r[q] >= 0 && cl) ? Cs[r[q] * S + lane] : 0;
       }
+      int32_t c[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) c[q] = Cs[r[q] * S + lc];
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         if (q >= cnt) break;
-        const int64_t hr = (int64_t)readlane64((uint64_t)h, r[q]);
         const int tr = __builtin_amdgcn_readlane(rtree, r[q]);
-        const int64_t val = (int64_t)c[q] - hr - vj;
-        if (cl) {
-          bad |= val < 0 || (COMPACT && val > kValMax);  // a negative reduced cost would mean infeasible duals
-          const Key key = kpk(val < 0 ? 0 : val, r[q]);
-          const bool lt = key < k1;
-          top2_push(k1, t1, k2, t2, key, tr);
-          if (lt) stl = false;  // the best key now comes from a live tree
-        }
+        const int64_t val = reduced(c[q], r[q], vj);
+        bad |= cl && (val < 0 || (COMPACT && val > kValMax));  // a negative reduced cost: infeasible duals
+        const Key key = cl ? kpk(val < 0 ? 0 : val, r[q]) : KINF;
+        stl = stl && !(key < k1);  // the best key now comes from a live tree
+        top2_push(k1, t1, k2, t2, key, tr);
       }
     }
   }
 
-  // Exact top-2 of column j over the forest rows, every lane taking one row:
-  // the best key, then the best key among rows of other trees.  The result
-  // is uniform.
-  __device__ __forceinline__ void column_top2(const int32_t *Cs, int S, int j, Key &a1, int &ta1, Key &a2, int &ta2) {
-    const int32_t vjj = __builtin_amdgcn_readlane(vj, j);
+  // Exact top-2 of G columns js[] over the forest rows, every lane taking one
+  // row: the best key, then the best key among rows of other trees.  The G
+  // columns' reductions are independent, so their latencies overlap.  The
+  // results are uniform.
+  template <int G>
+  __device__ __forceinline__ void columns_top2(const int32_t *Cs, int S, const int *js, Key *a1, int *ta1, Key *a2,
+                                               int *ta2) {
     const bool in = cl && ((forest >> lane) & 1ull);
-    const int32_t c = in ? Cs[lane * S + j] : 0;
-    Key a = KINF;
-    if (in) {
-      const int64_t val = (int64_t)c - h - vjj;
-      bad |= val < 0 || (COMPACT && val > kValMax);
-      a = kpk(val < 0 ? 0 : val, lane);
+    const int li = in ? lane : 0;
+    Key a[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      const int32_t vjj = __builtin_amdgcn_readlane(vj, js[g]);
+      const int32_t c = Cs[li * S + js[g]];
+      int64_t val;
+      if constexpr (COMPACT) val = (int32_t)((uint32_t)c - (uint32_t)(uint64_t)h - (uint32_t)vjj);
+      else val = (int64_t)c - h - vjj;
+      bad |= in && (val < 0 || (COMPACT && val > kValMax));
+      a[g] = in ? kpk(val < 0 ? 0 : val, lane) : KINF;
     }
-    a1 = wmin(a);
-    ta1 = a1 == KINF ? -1 : __builtin_amdgcn_readlane(rtree, kr(a1));
-    a2 = wmin(in && rtree != ta1 ? a : KINF);
-    ta2 = a2 == KINF ? -1 : __builtin_amdgcn_readlane(rtree, kr(a2));
+#pragma unroll
+    for (int g = 0; g < G; ++g) a1[g] = wmin(a[g]);
+#pragma unroll
+    for (int g = 0; g < G; ++g) ta1[g] = a1[g] == KINF ? -1 : __builtin_amdgcn_readlane(rtree, kr(a1[g]));
+#pragma unroll
+    for (int g = 0; g < G; ++g) a2[g] = wmin(in && rtree != ta1[g] ? a[g] : KINF);
+#pragma unroll
+    for (int g = 0; g < G; ++g) ta2[g] = a2[g] == KINF ? -1 : __builtin_amdgcn_readlane(rtree, kr(a2[g]));
+  }
+
+  // Refresh the stale columns in mask R (two at a time).
+  __device__ __forceinline__ void refresh(const int32_t *Cs, int S, uint64_t R) {
+    while (R) {
+      int js[2];
+      js[0] = bit_of(R);
+      R &= R - 1;
+      Key a1[2], a2[2];
+      int ta1[2], ta2[2];
+      if (R) {
+        js[1] = bit_of(R);
+        R &= R - 1;
+        columns_top2<2>(Cs, S, js, a1, ta1, a2, ta2);
+      } else {
+        columns_top2<1>(Cs, S, js, a1, ta1, a2, ta2);
+        js[1] = js[0]; a1[1] = a1[0]; ta1[1] = ta1[0]; a2[1] = a2[0]; ta2[1] = ta2[0];
+      }
+#pragma unroll
+      for (int g = 0; g < 2; ++g)
+        if (lane == js[g]) { k1 = a1[g]; t1 = ta1[g]; k2 = a2[g]; t2 = ta2[g]; stl = false; }
+    }
   }
 
   // Solve with C in LDS (row i at Cs[i * (n + 1)]) and mn = row minimum u_i
   // in lane i.
-  __device__ __forceinline__ void solve(const Problem &P, const int32_t *Cs, int mn) {
+  __device__ __forceinline__ void solve(const Problem &P, int32_t *Cs, int mn) {
     n = P.n;
     lane = threadIdx.x & 63;
     cl = lane < n;
     const int S = n + 1;
+    rmap = Cs + n * S;
     h = cl ? (int64_t)mn : 0;
     // ---- v_j = min_i (C_ij - u_i) and the two best rows of column j
     Key b1 = KINF, b2 = KINF;
-    for (int i = 0; i < n; ++i) {
-      const int64_t ui = (int64_t)readlane64((uint64_t)h, i);
-      const int32_t c = cl ? Cs[i * S + lane] : 0;
-      const Key key = kpk((int64_t)c - ui, i);
-      if (key < b1) { b2 = b1; b1 = key; }
-      else if (key < b2) b2 = key;
+    const int lc = cl ? lane : 0;
+    for (int i0 = 0; i0 < n; i0 += 4) {
+      int32_t c[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) c[q] = Cs[min(i0 + q, n - 1) * S + lc];  // four reads in flight
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        if (i0 + q >= n) break;
+        const int ui = __builtin_amdgcn_readlane(mn, i0 + q);
+        const Key key = kpk((int64_t)c[q] - ui, i0 + q);
+        const bool lt1 = key < b1, lt2 = key < b2;
+        b2 = lt1 ? b1 : (lt2 ? key : b2);
+        b1 = lt1 ? key : b1;
+      }
     }
     const int K = (P.max_paths <= 0 || P.max_paths > n) ? n : P.max_paths;
     vj = cl ? (int32_t)kv(b1) : 0;
@@ -149,19 +205,27 @@ struct WaveCore {
     forest = roots;
     front = K == n ? 0 : roots;  // with every row a root the keys above already hold the first sweep
 
-    int64_t st_levels = 0, st_dual = 0, st_aug = 0, st_paths = 0, st_rows = 2 * (int64_t)n, st_gath = 0;
-    int64_t st_resw = 0, st_refresh = 0, st_rcols = 0;
+    // counters fit 32 bits at n <= 64 (levels are at most 66^2 + 64), and
+    // keeping them narrow keeps the loop's scalar registers from spilling
+    int st_levels = 0, st_dual = 0, st_aug = 0, st_paths = 0, st_rows = 2 * n, st_gath = 0;
+    int st_resw = 0, st_refresh = 0, st_rcols = 0;
     int err = 0;
     int nfree = n, nalive = K, cursor = K;
     int64_t D = 0;
-    const int64_t watchdog = (int64_t)(n + 2) * (int64_t)(n + 2) + 64;
+    const int watchdog = (n + 2) * (n + 2) + 64;
     const int gcap = gather_cap(n);
+    const bool timers = (P.flags & OT_FLAG_PHASE_TIMERS) != 0;
+    // phase times in wall clock ticks (10 ns), 32-bit differences
+    uint32_t tm_sweep = 0, tm_select = 0, tm_settle = 0, tm_aug = 0, tm_refresh = 0;
 
     while (nfree > 0) {
       // (1) fold the rows that joined last step into the keys
+      const uint32_t tA = timers ? (uint32_t)now_ticks() : 0;
       st_rows += __builtin_popcountll(front);
       sweep(Cs, S, front);
       front = 0;
+      const uint32_t tB = timers ? (uint32_t)now_ticks() : 0;
+      tm_sweep += tB - tA;
       // (2) smallest key over unreached columns (stale keys are lower bounds)
       const bool open = cl && !vis && k1 != KINF;
       Key mv = wmin(open && !stl ? k1 : KINF);
@@ -171,6 +235,7 @@ struct WaveCore {
         const int64_t lim = mv == KINF ? INT64_MAX : kv(mv);
         uint64_t R = __builtin_amdgcn_ballot_w64(open && stl && kv(k1) <= lim);
         const int g = __builtin_popcountll(R);
+        const uint32_t tR = timers ? (uint32_t)now_ticks() : 0;
         ++st_refresh;
         st_rcols += g;
         if (g > gcap) {
@@ -181,16 +246,10 @@ struct WaveCore {
           st_rows += __builtin_popcountll(forest);
           sweep(Cs, S, forest);
         } else {
-          st_gath += (int64_t)g * __builtin_popcountll(forest);
-          while (R) {
-            const int j = bit_of(R);
-            R &= R - 1;
-            Key a1, a2;
-            int ta1, ta2;
-            column_top2(Cs, S, j, a1, ta1, a2, ta2);
-            if (lane == j) { k1 = a1; t1 = ta1; k2 = a2; t2 = ta2; stl = false; }
-          }
+          st_gath += g * __builtin_popcountll(forest);
+          refresh(Cs, S, R);
         }
+        if (timers) tm_refresh += (uint32_t)now_ticks() - tR;
         const bool open2 = cl && !vis && k1 != KINF;
         mv = wmin(open2 && !stl ? k1 : KINF);
       }
@@ -198,6 +257,8 @@ struct WaveCore {
       const int64_t level = kv(mv);
       if (level > D) { D = level; ++st_dual; }
       if (++st_levels > watchdog || D > kLevelMax) { err = OT_EINTERNAL; break; }
+      const uint32_t tC = timers ? (uint32_t)now_ticks() : 0;
+      tm_select += tC - tB;
 
       // (3) settle every unreached column at the current level
       const bool settle = cl && !vis && !stl && k1 != KINF && kv(k1) == D;
@@ -222,9 +283,16 @@ struct WaveCore {
           if (lane == tr) bend = j;
         }
       }
+      const uint32_t tD = timers ? (uint32_t)now_ticks() : 0;
+      tm_settle += tD - tC;
       if (augm) {
-        // (4) flip one path per such tree (trees are disjoint)
+        // (4) flip one path per such tree (trees are disjoint).  The walks
+        // only read (par, and the matches as they were before this step), so
+        // each step is two lane reads with no write in between; the flips
+        // are applied after all walks: every path column takes its parent
+        // row, and that row takes the column (through the row map in LDS).
         const int naug = __builtin_popcountll(augm);
+        uint64_t pcols = 0, prows = 0;
         for (uint64_t A = augm; A; A &= A - 1) {
           const int tr = bit_of(A);
           int j = __builtin_amdgcn_readlane(bend, tr);
@@ -232,15 +300,17 @@ struct WaveCore {
             if (steps > n || (unsigned)j >= (unsigned)n) { err = OT_EINTERNAL; break; }
             const int p = __builtin_amdgcn_readlane(par, j);
             if ((unsigned)p >= (unsigned)n) { err = OT_EINTERNAL; break; }
-            const int before = __builtin_amdgcn_readlane(mrow, p);
-            if (lane == p) mrow = j;
-            if (lane == j) mcol = p;
+            pcols |= 1ull << j;
+            prows |= 1ull << p;
+            if (lane == 0) rmap[p] = j;
             if (p == tr) break;
-            j = before;
+            j = __builtin_amdgcn_readlane(mrow, p);
           }
-          if (lane == tr) bend = kNoEnd;
         }
         if (err) break;
+        if ((pcols >> lane) & 1ull) mcol = par;
+        if ((prows >> lane) & 1ull) mrow = rmap[lane];
+        if ((augm >> lane) & 1ull) bend = kNoEnd;
         alive &= ~augm;
         ++st_aug;
         st_paths += naug;
@@ -276,19 +346,19 @@ struct WaveCore {
           cursor += need;
           nalive += need;
         }
+        if (timers) tm_aug += (uint32_t)now_ticks() - tD;
       }
     }
     if (err == 0 && __builtin_amdgcn_ballot_w64(bad) != 0) err = OT_EINTERNAL;
 
     if (err == 0) {
-      const int32_t *Cr = P.Cout ? P.Cout : P.C;
-      const size_t ldr = P.Cout ? (size_t)P.ldo : (size_t)P.ld;
       int64_t part = 0;
       if (cl) {
         P.plan[lane] = mrow;
         if (P.u) P.u[lane] = h * P.dscale;
         if (P.v) P.v[lane] = (int64_t)vj * P.dscale;
-        part = (mrow >= 0 && mrow < n) ? (int64_t)Cr[(size_t)lane * ldr + mrow] : 0;
+        if (mrow >= 0 && mrow < n)  // the total over C is read from its copy in LDS
+          part = P.Cout ? (int64_t)P.Cout[(size_t)lane * (size_t)P.ldo + mrow] : (int64_t)Cs[lane * S + mrow];
       }
       part = wave_sum_i64(part);
       if (lane == 0) *P.cost = part;
@@ -298,6 +368,9 @@ struct WaveCore {
       s.levels = st_levels; s.dual_adjusts = st_dual; s.aug_events = st_aug; s.paths = st_paths;
       s.rows_swept = st_rows; s.gathers = st_gath; s.resweeps = st_resw; s.status = err;
       s.refreshes = st_refresh; s.refresh_cols = st_rcols;
+      s.t_sweep_ns = 10 * (int64_t)tm_sweep; s.t_select_ns = 10 * (int64_t)tm_select;
+      s.t_settle_ns = 10 * (int64_t)tm_settle; s.t_augment_ns = 10 * (int64_t)tm_aug;
+      s.t_refresh_ns = 10 * (int64_t)tm_refresh;
       *P.stats = s;
     }
   }
@@ -310,12 +383,17 @@ struct WaveEngine {
     const int S = n + 1;
     int32_t *Cs = (int32_t *)smem;
     // ---- C into LDS (row i at Cs[i * S])
-    for (int i0 = 0; i0 < n; i0 += 8) {
-      int32_t c[8];
+    // sixteen rows' loads in flight at a time (every lane loads: rows and
+    // columns past n read entry (0, 0) and store nothing)
+    for (int i0 = 0; i0 < n; i0 += 16) {
+      int32_t c[16];
 #pragma unroll
-      for (int q = 0; q < 8; ++q) c[q] = (i0 + q < n && cl) ? P.C[(size_t)(i0 + q) * (size_t)P.ld + lane] : 0;
+      for (int q = 0; q < 16; ++q) {
+        const bool in = i0 + q < n && cl;
+        c[q] = P.C[in ? (size_t)(i0 + q) * (size_t)P.ld + lane : 0];
+      }
 #pragma unroll
-      for (int q = 0; q < 8; ++q)
+      for (int q = 0; q < 16; ++q)
         if (i0 + q < n && cl) Cs[(i0 + q) * S + lane] = c[q];
     }
     __syncthreads();
