@@ -480,6 +480,85 @@ struct Engine {
     }
   }
 
+  // Merge a chunk's top-2 (b1, tb1, b2, tb2) into column k's (k1, t1, k2,
+  // t2): the smaller best wins, and the second is the better of the loser's
+  // best (when it is from another tree) or its second, and the winner's
+  // second.  Returns whether the best changed (it is then from a live tree).
+  __device__ __forceinline__ bool merge_top2(int k, Key b1, int tb1, Key b2, int tb2) {
+    const bool sw = b1 < k1[k];
+    const Key x1 = sw ? b1 : k1[k], x2 = sw ? b2 : k2[k];
+    const int tx1 = sw ? tb1 : t1[k], tx2 = sw ? tb2 : t2[k];
+    const Key y1 = sw ? k1[k] : b1, y2 = sw ? k2[k] : b2;
+    const int ty1 = sw ? t1[k] : tb1, ty2 = sw ? t2[k] : tb2;
+    const bool d = ty1 != tx1;
+    const Key cc = d ? y1 : y2;
+    const int tc = d ? ty1 : ty2;
+    const bool lt = cc < x2;
+    k1[k] = x1; t1[k] = tx1;
+    k2[k] = lt ? cc : x2; t2[k] = lt ? tc : tx2;
+    return sw;
+  }
+
+  // Compact keys: each candidate of the chunk is one packed 32-bit key
+  // (value << KB | row), so a column's best over the chunk is a chain of
+  // minima, and the tree of the winner is read back from rtree (a live row
+  // of the chunk is a forest row, and rtree holds the tree of its record).
+  // The best from another tree is the minimum over the candidates whose
+  // tree differs.  The columns go in phases so that the CPT tree reads of a
+  // phase are in flight together.  The results equal the generic fold's.
+  template <int UU>
+  __device__ __forceinline__ int chunk_fold_compact(const Chunk<UU> &X) {
+    int rs[UU], ts[UU];
+    uint32_t nh[UU];
+    int used = 0;
+#pragma unroll
+    for (int q = 0; q < UU; ++q) {
+      rs[q] = __builtin_amdgcn_readfirstlane(X.r[q]);
+      ts[q] = __builtin_amdgcn_readfirstlane(X.t[q]);
+      nh[q] = 0u - (uint32_t)__builtin_amdgcn_readfirstlane((int)X.h32[q]);
+      used += ts[q] >= 0;
+    }
+    if (used == 0) return 0;
+    const int rmax = rows() - 1;
+    Key kk[UU][CPT], b1[CPT], b2[CPT];
+    int tb1[CPT], tb2[CPT];
+#pragma unroll
+    for (int k = 0; k < CPT; ++k) {
+      const uint32_t nvj = 0u - (uint32_t)vj[k];
+      Key m = KINF;
+#pragma unroll
+      for (int q = 0; q < UU; ++q) {
+        // exact: every key value is below 2^20 with compact keys
+        const uint32_t v = (uint32_t)X.c[q][k] + nh[q] + nvj;
+        kk[q][k] = ts[q] >= 0 ? ((v << KB) | (uint32_t)rs[q]) : KINF;
+        m = min(m, kk[q][k]);
+      }
+      b1[k] = m;
+    }
+    // the low bits of a live candidate are its row (clamped for lanes past n)
+#pragma unroll
+    for (int k = 0; k < CPT; ++k) tb1[k] = rtree[min(kr(b1[k]), rmax)];
+#pragma unroll
+    for (int k = 0; k < CPT; ++k) {
+      Key m = KINF;
+#pragma unroll
+      for (int q = 0; q < UU; ++q) m = min(m, ts[q] != tb1[k] ? kk[q][k] : KINF);
+      b2[k] = m;
+    }
+#pragma unroll
+    for (int k = 0; k < CPT; ++k) tb2[k] = rtree[min(kr(b2[k]), rmax)];
+    uint32_t clr = 0;
+#pragma unroll
+    for (int k = 0; k < CPT; ++k) {
+      const bool in = col(k) < n;
+      const Key c1 = in ? b1[k] : KINF, c2 = in ? b2[k] : KINF;
+      const int u1 = in ? tb1[k] : -1, u2 = c2 == KINF ? -1 : tb2[k];
+      clr |= merge_top2(k, c1, u1, c2, u2) ? (1u << k) : 0u;  // best key now from a live tree
+    }
+    stl &= ~clr;
+    return used;
+  }
+
   // Fold a loaded chunk into every owned column's top-2 keys; returns the rows used.
   template <bool NARROW, int UU>
   __device__ __forceinline__ int chunk_fold(const Chunk<UU> &X) {
@@ -492,6 +571,7 @@ struct Engine {
       const int32_t(*c)[CPT] = X.c;
 #pragma unroll
       for (int q = 0; q < U; ++q) used += t[q] >= 0;
+      if constexpr (COMPACT) return chunk_fold_compact<UU>(X);
       if (NARROW) {
         // Per column: the exact top-2 of this chunk's candidates (the best, then
         // the best from another tree), merged once into the column's top-2.
@@ -591,6 +671,21 @@ struct Engine {
     return chunk_fold<NARROW, UU>(X);
   }
 
+  // Compact keys in the one-instance kernels: up to UL rows per chunk (the
+  // packed-key fold costs little per row, so longer chunks spread each
+  // column's merge over more rows); a frontier of at most UL rows goes in one
+  // chunk of the smallest power-of-two size that holds it.
+  static constexpr int UL = CPT >= 8 ? 4 : 8;
+  template <int S, bool REC>
+  __device__ __forceinline__ int sweep_short(const int32_t *list, int cnt) {
+    if constexpr (S > 1) {
+      if (cnt <= S / 2) return sweep_short<S / 2, REC>(list, cnt);
+    }
+    Chunk<S> X;
+    chunk_load<true, S, REC>(list, 0, cnt, X);
+    return chunk_fold_compact<S>(X);
+  }
+
   // Rows go in chunks of U.  In the one-instance kernel the chunks are
   // pipelined: a short frontier pays one small chunk, a long one about one
   // memory latency in all.
@@ -598,6 +693,19 @@ struct Engine {
   __device__ __forceinline__ int sweep_t(const int32_t *list, int cnt) {
     int used = 0;
     int f = 0;
+    if constexpr (COMPACT && LONG) {
+      if (cnt <= 0) return 0;
+      if (cnt <= UL) return sweep_short<UL, REC>(list, cnt);
+      Chunk<UL> a;
+      chunk_load<true, UL, REC>(list, 0, cnt, a);
+      for (f = UL; f < cnt; f += UL) {
+        Chunk<UL> b;
+        chunk_load<true, UL, REC>(list, f, cnt, b);
+        used += chunk_fold_compact<UL>(a);
+        a = b;
+      }
+      return used + chunk_fold_compact<UL>(a);
+    }
 #ifndef OTKM_SWEEP32
 #define OTKM_SWEEP32 0
 #endif
