@@ -100,7 +100,7 @@ struct BinEngine : Engine<BLOCK, CPT, true, false, true> {
     mrow = (int32_t *)(smem + L.mrow);   // row -> the column it joined through (rpar)
     mcol = (int32_t *)(smem + L.mcol);   // column -> demand left
     rtree = (int32_t *)(smem + L.rtree);
-    par = (int32_t *)(smem + L.par);
+    par = (int16_t *)(smem + L.par);
     fst = (int32_t *)(smem + L.fst);
     fr = (int2 *)(smem + L.fr);
     alive = (uint8_t *)(smem + L.alive);
@@ -148,7 +148,7 @@ struct BinEngine : Engine<BLOCK, CPT, true, false, true> {
       rtree[i] = ri > 0 ? i : -1;
       alive[i] = ri > 0 ? 1 : 0;
     }
-    for (int j = tid; j < nc; j += BLOCK) { rd[j] = P.c[j]; cflow[j] = 0; par[j] = -1; }
+    for (int j = tid; j < nc; j += BLOCK) { rd[j] = P.c[j]; cflow[j] = 0; par[j] = (int16_t)-1; }
     for (int j = tid; j < B; j += BLOCK) bend[j] = kNoEnd;
     gmin = wave_min_i32(gmin);
     gmax = wave_max_i32(gmax);
@@ -242,7 +242,7 @@ struct BinEngine : Engine<BLOCK, CPT, true, false, true> {
         vis |= 1u << k;
         dcol[k] = (int32_t)D;
         ctree[k] = tr;
-        par[j] = krow(k1[k]);
+        par[j] = (int16_t)krow(k1[k]);
         if (rd[j] > 0) {
           if (atomicMin(&bend[tr], j) == kNoEnd) auglist[atomicAdd(&ctl[NAUG], 1)] = tr;
         } else if (cflow[j] > 0) {

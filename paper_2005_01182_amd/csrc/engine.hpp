@@ -73,7 +73,9 @@ struct LdsLayout {
 };
 
 // Byte offsets of every LDS array for an instance of size n (host and device).
-__host__ __device__ inline LdsLayout lds_layout(int n) {
+// grid: the engine runs one instance over several workgroups, whose settle
+// exchange stages the other workgroups' entries in red (128 words instead of 80).
+__host__ __device__ inline LdsLayout lds_layout(int n, bool grid = false) {
   LdsLayout L;
   const size_t N = (size_t)n, G = (size_t)gather_cap(n);
   size_t o = 0;
@@ -81,7 +83,7 @@ __host__ __device__ inline LdsLayout lds_layout(int n) {
   L.mrow = o;  o = align16(o + 4 * N);
   L.mcol = o;  o = align16(o + 4 * N);
   L.rtree = o; o = align16(o + 4 * N);
-  L.par = o;   o = align16(o + 4 * N);
+  L.par = o;   o = align16(o + 2 * N);  // 16-bit row ids (n <= OT_MAX_N)
   L.fst = o;   o = align16(o + 4 * N);
   L.fr = o;    o = align16(o + 8 * N);
   L.alive = o; o = align16(o + N);
@@ -91,7 +93,9 @@ __host__ __device__ inline LdsLayout lds_layout(int n) {
   L.gk2 = o;   o = align16(o + 8 * G);
   L.gt1 = o;   o = align16(o + 4 * G);
   L.gt2 = o;   o = align16(o + 4 * G);
-  L.red = o;   o = align16(o + 8 * 128);
+  // slots [0, 8), per-wave words [16, 32), refresh partials [32, 32 + 3 NW);
+  // the grid exchange: [16, 112) entries, [112, 121) counts
+  L.red = o;   o = align16(o + 8 * (grid ? 128 : 80));
   L.ctl = o;   o = align16(o + 4 * NCTL);
   L.total = o;
   return L;
@@ -271,7 +275,8 @@ struct Engine {
   }
   // LDS
   int64_t *hrow;
-  int32_t *mrow, *mcol, *rtree, *par, *fst, *gcol, *gt1, *gt2, *ctl;
+  int32_t *mrow, *mcol, *rtree, *fst, *gcol, *gt1, *gt2, *ctl;
+  int16_t *par;  // parent row of each reached column
   int2 *fr;  // frontier records of the next sweep: (row | tree << 16, low 32 bits of h)
   uint8_t *alive;
   int64_t *gv;
@@ -917,8 +922,8 @@ struct Engine {
     // top-2 summaries meet in LDS and one thread per column merges them.
     const int wpc = g >= NW ? 1 : NW / g;
     const int per_round = NW / wpc;
-    uint64_t *pk1 = red + 64, *pk2 = red + 64 + NW;
-    int32_t *pt = (int32_t *)(red + 64 + 2 * NW);
+    uint64_t *pk1 = red + 32, *pk2 = red + 32 + NW;
+    int32_t *pt = (int32_t *)(red + 32 + 2 * NW);
     for (int base = 0; base < g; base += per_round) {
       const int s = base + wid / wpc;
       const int slice = wid % wpc;
@@ -1001,12 +1006,12 @@ struct Engine {
                                                 0x00020000);
     }
     err_local = 0;
-    const LdsLayout L = lds_layout(n);
+    const LdsLayout L = lds_layout(n, GRID);
     hrow = (int64_t *)(smem + L.hrow);
     mrow = (int32_t *)(smem + L.mrow);
     mcol = (int32_t *)(smem + L.mcol);
     rtree = (int32_t *)(smem + L.rtree);
-    par = (int32_t *)(smem + L.par);
+    par = (int16_t *)(smem + L.par);
     fst = (int32_t *)(smem + L.fst);
     fr = (int2 *)(smem + L.fr);
     alive = (uint8_t *)(smem + L.alive);
@@ -1302,7 +1307,7 @@ struct Engine {
           }
           const int j = (int)((e >> 24) & 0xfff), p = (int)((e >> 12) & 0xfff), tr = (int)(e & 0xfff);
           if (j >= n || p >= nr || tr >= nr) { fail(OT_EINTERNAL); continue; }
-          par[j] = p;
+          par[j] = (int16_t)p;
           const int mc = mcol[j];
           if (mc < 0) {
             if (atomicMin(&bend[tr], j) == kNoEnd) {
@@ -1327,7 +1332,7 @@ struct Engine {
         vis |= 1u << k;
         dcol[k] = (int32_t)D;
         ctree[k] = tr;
-        par[j] = p;
+        par[j] = (int16_t)p;
         const int mc = mcol[j];
         if (mc < 0) {
           if (atomicMin(&bend[tr], j) == kNoEnd) {

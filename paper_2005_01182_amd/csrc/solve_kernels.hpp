@@ -205,7 +205,7 @@ static hipError_t one(const Problem &P, const int32_t *gate, hipStream_t s) {
 
 template <int B, int CPT>
 static hipError_t grid(const Problem &P, int wgs, hipStream_t s) {
-  const size_t lds = lds_layout(P.n).total;
+  const size_t lds = lds_layout(P.n, true).total;
   hipError_t e = allow_lds<k_assign_grid<B, CPT>>(lds);
   if (e != hipSuccess) return e;
   // every tag word must start below the first level
