@@ -82,32 +82,30 @@ struct WaveCore {
     }
   }
 
-  // Fold rows `rows` (a uniform mask) into the column keys.  Every lane reads
-  // (lanes past n read column 0 and keep no key), so the four reads of a
-  // batch are issued back to back.
+  // Fold row r's entries (c in this lane's column) into the column keys.
+  __device__ __forceinline__ void fold_row(int32_t c, int r) {
+    const int tr = __builtin_amdgcn_readlane(rtree, r);
+    const int64_t val = reduced(c, r, vj);
+    bad |= cl && (val < 0 || (COMPACT && val > kValMax));  // a negative reduced cost: infeasible duals
+    const Key key = cl ? kpk(val < 0 ? 0 : val, r) : KINF;
+    stl = stl && !(key < k1);  // the best key now comes from a live tree
+    top2_push(k1, t1, k2, t2, key, tr);
+  }
+
+  // Fold rows `rows` (a uniform mask) into the column keys, two rows at a
+  // time with both LDS reads issued first (lanes past n read column 0 and keep
+  // no key).  An odd last row is paired with itself: a candidate folded twice
+  // changes nothing.
   __device__ __forceinline__ void sweep(const int32_t *Cs, int S, uint64_t rows) {
     const int lc = cl ? lane : 0;
     while (rows) {
-      int r[4];
-      int cnt = 0;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        r[q] = rows ? bit_of(rows) : 0;
-        if (rows) { rows &= rows - 1; ++cnt; }
-      }
-      int32_t c[4];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) c[q] = Cs[r[q] * S + lc];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        if (q >= cnt) break;
-        const int tr = __builtin_amdgcn_readlane(rtree, r[q]);
-        const int64_t val = reduced(c[q], r[q], vj);
-        bad |= cl && (val < 0 || (COMPACT && val > kValMax));  // a negative reduced cost: infeasible duals
-        const Key key = cl ? kpk(val < 0 ? 0 : val, r[q]) : KINF;
-        stl = stl && !(key < k1);  // the best key now comes from a live tree
-        top2_push(k1, t1, k2, t2, key, tr);
-      }
+      const int r0 = bit_of(rows);
+      rows &= rows - 1;
+      const int r1 = rows ? bit_of(rows) : r0;
+      rows &= rows - 1;
+      const int32_t c0 = Cs[r0 * S + lc], c1 = Cs[r1 * S + lc];
+      fold_row(c0, r0);
+      fold_row(c1, r1);
     }
   }
 
