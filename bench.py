@@ -676,16 +676,22 @@ def bench_batch(args):
         idx = idx[np.argsort(-sizes[idx], kind="stable")].astype(np.int32)
         classes.append((block, int(sizes[idx].max()), d(idx)))
     stream = torch.cuda.Stream()
-    # optional transposes for single-column refreshes, made inside every launch
-    dCT = torch.empty_like(dC) if args.ct else None
+    # transposes for single-column refreshes, made inside every launch: by the
+    # launch's flag pass (fused) or by a kernel of their own (kernel)
+    ct_kernel, ct_fused = args.transposes == "kernel", args.transposes == "fused"
+    dCT = torch.empty_like(dC) if args.transposes != "none" else None
     max_all = int(sizes.max())
 
     def launch():
-        if dCT is not None:
+        if ct_kernel:
             ot.ot_transpose_batch_dev(count, max_all, dC, dcoff, dn, dCT, stream=stream)
         for block, max_n, order in classes:
-            ot.ot_assign_batch_dev(count, max_n, dC, dcoff, dn, dvoff, plan, cost, u, v, st, order=order,
-                                   block=block, stream=stream, CT=dCT)
+            if ct_fused and not (block == 64 and max_n <= 64):
+                ot.ot_assign_batch_ct_dev(count, max_n, dC, dCT, dcoff, dn, dvoff, plan, cost, u, v, st, order=order,
+                                          block=block, stream=stream)
+            else:
+                ot.ot_assign_batch_dev(count, max_n, dC, dcoff, dn, dvoff, plan, cost, u, v, st, order=order,
+                                       block=block, stream=stream, CT=dCT if ct_kernel else None)
 
     with torch.cuda.stream(stream):
         launch()  # eager run sizes the workspaces
@@ -709,7 +715,9 @@ def bench_batch(args):
     if int(np.abs(stats[:, F["status"]]).max()) != 0:
         raise SystemExit("batch status nonzero")
     b = alg_bytes(stats, sizes)
-    transpose_bytes = 0 if dCT is None else 8 * int((ns * ns).sum())  # read + write of every matrix
+    # the transposes: a read and a write of every matrix (kernel), or only the
+    # write (fused: the flag pass reads every matrix in either case)
+    transpose_bytes = 8 * int((ns * ns).sum()) if ct_kernel else (4 * int((ns * ns).sum()) if ct_fused else 0)
     value = count * args.steps / (total / 1e3)
     out = base_line(args, value, "solves/s", total / args.steps,
                     {"workload": "batched embedding assignments: %d problems, n ~ U{16..512}, 300-d N(0,1) "
@@ -718,11 +726,12 @@ def bench_batch(args):
                      "problems": count, "sum_n2": int((ns * ns).sum()),
                      "schedule": {"wave_max_n": t64, "wg256_max_n": t256},
                      "classes": [[blk, mx, int(o.numel())] for blk, mx, o in classes],
-                     "launch": "hipGraph replay of %sone persistent kernel per size class" %
-                               ("the batched transpose and " if dCT is not None else "")})
+                     "transposes": args.transposes,
+                     "launch": "hipGraph replay of %sthe flag pass and one persistent kernel per size class" %
+                               ("the batched transpose, " if ct_kernel else "")})
     out["roofline"] = roofline(float(b.sum()) + transpose_bytes, float(np.mean(per)) / 1e3)
-    # one size class and no transposes: the launch is one dispatch of the persistent kernel
-    if len(classes) == 1 and dCT is None:
+    # the committed counter summary covers every kernel of the default launch
+    if args.transposes == "fused":
         out["roofline"]["traffic"] = traffic_for("embedding%d" % count, kernel="k_assign_batch")
     out["batch_latency_ms"] = {"p50": pct(per, 50), "p99": pct(per, 99)}
     # plain comparison: one launch per instance, sequential on one stream, over a prefix of the batch
@@ -855,8 +864,10 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--block", type=int, default=0, help="workgroup width override (0 = library default)")
     ap.add_argument("--tune", action="store_true", help="batch mode: run the size-class autotuner first")
-    ap.add_argument("--ct", action="store_true", help="batch mode: transpose the matrices inside every launch "
-                                                      "(refreshes then read rows of the transposes)")
+    ap.add_argument("--transposes", default="fused", choices=["fused", "kernel", "none"],
+                    help="batch mode: transposes for single-column refreshes, written by the launch's flag pass "
+                         "(fused, ot_assign_batch_ct_dev), by a kernel of their own in every launch (kernel), or "
+                         "none (refreshes gather down C)")
     ap.add_argument("--phase-timers", action="store_true", help="one extra solve with device phase timers")
     ap.add_argument("--cold", action="store_true",
                     help="geometric/small: read 512 MiB before every timed solve (C starts out of the MALL)")

@@ -280,13 +280,28 @@ int ot_assign_rect_dev(const int32_t *dC, int32_t n, int32_t m, int32_t ld, cons
  * and offsets as dC, filled by ot_transpose_batch_dev) the recomputation of a
  * single stale column reads one contiguous row of the transpose; with NULL it
  * gathers one entry per row of C, which fetches a whole memory line each.
- * (On MI355X the transposes cut the embedding batch's HBM traffic from 3.5x
- * to 1.3x its algorithmic bytes but not its time, which its level chains
- * bound; NULL is the faster choice there.) */
+ * (ot_assign_batch_ct_dev makes the transposes inside the launch's pass
+ * over the matrices instead, which on MI355X is the faster choice for the
+ * embedding batch.) */
 int ot_assign_batch_dev(int32_t count, int32_t max_n, const int32_t *dC, const int32_t *dCT,
                         const int64_t *coff, const int32_t *n, const int64_t *voff,
                         const int32_t *order, int32_t nq, int32_t block, int32_t *dplan,
                         int64_t *dcost, int64_t *du, int64_t *dv, ot_stats *dstats, void *stream);
+
+/* ot_assign_batch_dev with the transposes made by the launch itself: dCT is
+ * a device workspace as large as dC (same offsets, caller-owned, contents on
+ * entry ignored).  The launch's pass over every matrix (the one that picks
+ * the key width) also writes the matrix's transpose into dCT + coff[k], and
+ * single stale columns are then recomputed from rows of those transposes,
+ * which costs one pass of writes and removes the per-entry memory lines of
+ * the gathers down C.  Instances solved on one wavefront (block 64 with
+ * max_n <= 64) neither need nor write their transposes.  dCT == NULL:
+ * OT_EINVAL.  Same queue, graph-capture and output semantics as
+ * ot_assign_batch_dev. */
+int ot_assign_batch_ct_dev(int32_t count, int32_t max_n, const int32_t *dC, int32_t *dCT,
+                           const int64_t *coff, const int32_t *n, const int64_t *voff,
+                           const int32_t *order, int32_t nq, int32_t block, int32_t *dplan,
+                           int64_t *dcost, int64_t *du, int64_t *dv, ot_stats *dstats, void *stream);
 
 /* dCT + coff[k] = transpose of dC + coff[k] (n[k] x n[k]) for every instance
  * with 1 <= n[k] <= max_n (others are skipped); asynchronous on `stream`,

@@ -29,8 +29,39 @@ __global__ __launch_bounds__(256) void k_batch_flags(BatchArgs A) {
   __shared__ int s_lo[4], s_hi[4];
   int lo = 0x7fffffff, hi = (int)0x80000000;
   const bool sized = n >= 1 && n <= kCompactMaxN && n <= A.max_n && A.max_paths <= 0;
-  if (sized) {
-    const int32_t *C = A.C + A.coff[k];
+  const int32_t *C = A.C + A.coff[k];
+  if (A.ctw && n >= 1 && n <= A.max_n) {
+    // 64 x 64 tiles through LDS: each wavefront reads 16 rows of a tile
+    // (64 consecutive entries per row) and writes 16 rows of its transpose;
+    // the range is taken from the entries as they are read
+    __shared__ int32_t tile[64][65];
+    int32_t *T = A.ctw + A.coff[k];
+    const int nt = (n + 63) / 64;
+    for (int ti = 0; ti < nt; ++ti)
+      for (int tj = 0; tj < nt; ++tj) {
+        const int j = tj * 64 + lane;
+        int32_t x[16];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int i = ti * 64 + wid * 16 + r;
+          x[r] = (i < n && j < n) ? C[(size_t)i * n + j] : 0;
+        }
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int i = ti * 64 + wid * 16 + r;
+          if (i < n && j < n) { lo = min(lo, x[r]); hi = max(hi, x[r]); }
+          tile[wid * 16 + r][lane] = x[r];
+        }
+        __syncthreads();
+        const int i = ti * 64 + lane;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int jj = tj * 64 + wid * 16 + r;  // row jj of the transpose, column i
+          if (jj < n && i < n) T[(size_t)jj * n + i] = tile[lane][wid * 16 + r];
+        }
+        __syncthreads();
+      }
+  } else if (sized) {
     const int64_t total = (int64_t)n * n;
     int64_t q = threadIdx.x;
     for (; q + 768 < total; q += 1024) {

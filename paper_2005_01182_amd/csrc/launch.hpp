@@ -31,6 +31,10 @@ struct BatchArgs {
   // rest, one after the other on the stream.
   uint8_t *kflags = nullptr;
   int32_t *head2 = nullptr;
+  // Optional, with kflags: the flag pass, which reads every matrix anyway,
+  // also writes its transpose here (same offsets as C), and the solve kernels
+  // then read these transposes to refresh single stale columns.
+  int32_t *ctw = nullptr;
 };
 
 struct TransportArgs {

@@ -547,9 +547,12 @@ int ot_transpose_batch_dev(int32_t count, int32_t max_n, const int32_t *dC, cons
   return map_hip(launch_transpose_batch(dC, coff, n, count, max_n, dCT, s));
 }
 
-int ot_assign_batch_dev(int32_t count, int32_t max_n, const int32_t *dC, const int32_t *dCT, const int64_t *coff,
-                        const int32_t *n, const int64_t *voff, const int32_t *order, int32_t nq, int32_t block,
-                        int32_t *dplan, int64_t *dcost, int64_t *du, int64_t *dv, ot_stats *dstats, void *stream) {
+// ot_assign_batch_dev and ot_assign_batch_ct_dev: ctw, when given, receives
+// the transposes (written by the launch's flag pass) and replaces dCT.
+static int assign_batch_dev(int32_t count, int32_t max_n, const int32_t *dC, const int32_t *dCT, int32_t *ctw,
+                            const int64_t *coff, const int32_t *n, const int64_t *voff, const int32_t *order,
+                            int32_t nq, int32_t block, int32_t *dplan, int64_t *dcost, int64_t *du, int64_t *dv,
+                            ot_stats *dstats, void *stream) {
   if (count < 0 || !dC || !coff || !n || !voff || !dplan || !dcost || max_n <= 0) return OT_EINVAL;
   if (!order) nq = count;
   if (nq < 0 || nq > count) return OT_EINVAL;
@@ -576,7 +579,24 @@ int ot_assign_batch_dev(int32_t count, int32_t max_n, const int32_t *dC, const i
   A.count = count; A.nq = nq; A.max_n = max_n; A.max_paths = 0;
   A.plan = dplan; A.cost = dcost; A.u = du; A.v = dv; A.stats = dstats; A.ws = dws; A.head = head; A.done = nullptr; A.tag = 0;
   A.kflags = kflags; A.head2 = head + 32;  // another 128-byte line of the same buffer
+  A.ctw = ctw;
   return map_hip(launch_assign_batch(A, block, grid, s));
+}
+
+int ot_assign_batch_dev(int32_t count, int32_t max_n, const int32_t *dC, const int32_t *dCT, const int64_t *coff,
+                        const int32_t *n, const int64_t *voff, const int32_t *order, int32_t nq, int32_t block,
+                        int32_t *dplan, int64_t *dcost, int64_t *du, int64_t *dv, ot_stats *dstats, void *stream) {
+  return assign_batch_dev(count, max_n, dC, dCT, nullptr, coff, n, voff, order, nq, block, dplan, dcost, du, dv,
+                          dstats, stream);
+}
+
+int ot_assign_batch_ct_dev(int32_t count, int32_t max_n, const int32_t *dC, int32_t *dCT, const int64_t *coff,
+                           const int32_t *n, const int64_t *voff, const int32_t *order, int32_t nq, int32_t block,
+                           int32_t *dplan, int64_t *dcost, int64_t *du, int64_t *dv, ot_stats *dstats,
+                           void *stream) {
+  if (!dCT) return OT_EINVAL;
+  return assign_batch_dev(count, max_n, dC, nullptr, dCT, coff, n, voff, order, nq, block, dplan, dcost, du, dv,
+                          dstats, stream);
 }
 
 int ot_assign_batch(int32_t count, const int32_t *const *C, const int32_t *n, int32_t *const *plan, int64_t *cost,

@@ -222,13 +222,19 @@ static hipError_t batch(const BatchArgs &A, int grid, hipStream_t s) {
   hipError_t e;
   if constexpr (!(B == 64 && CPT == 1)) {
     if (A.kflags && A.head2) {
-      // flags, then the compact-key kernel, then the 64-bit-key kernel on the rest
+      // flags (and the transposes, when asked for), then the compact-key
+      // kernel, then the 64-bit-key kernel on the rest
       hipLaunchKernelGGL(k_batch_flags, dim3(A.nq), dim3(256), 0, s, A);
       if ((e = hipGetLastError()) != hipSuccess) return e;
       if ((e = launch_fill_i32(A.head2, 0, 1, s)) != hipSuccess) return e;
+      BatchArgs S = A;
+      if (A.ctw) S.CT = A.ctw;
       if ((e = allow_lds<k_assign_batch<B, CPT, true>>(lds)) != hipSuccess) return e;
-      hipLaunchKernelGGL((k_assign_batch<B, CPT, true>), dim3(grid), dim3(B), lds, s, A);
+      hipLaunchKernelGGL((k_assign_batch<B, CPT, true>), dim3(grid), dim3(B), lds, s, S);
       if ((e = hipGetLastError()) != hipSuccess) return e;
+      if ((e = allow_lds<k_assign_batch<B, CPT>>(lds)) != hipSuccess) return e;
+      hipLaunchKernelGGL((k_assign_batch<B, CPT>), dim3(grid), dim3(B), lds, s, S);
+      return hipGetLastError();
     }
   }
   if ((e = allow_lds<k_assign_batch<B, CPT>>(lds)) != hipSuccess) return e;

@@ -26,7 +26,8 @@ OT_MAX_N = 4096
 EXPORTS = [
     "ot_strerror", "ot_init", "ot_assign", "ot_assign_ex", "ot_assign_rect", "ot_scale_for", "ot_transport",
     "ot_assign_batch", "ot_transport_bins", "ot_transport_bins_dev",
-    "ot_assign_dev", "ot_assign_dev_noalloc", "ot_assign_rect_dev", "ot_assign_batch_dev", "ot_transpose_batch_dev", "ot_transport_dev",
+    "ot_assign_dev", "ot_assign_dev_noalloc", "ot_assign_rect_dev", "ot_assign_batch_dev", "ot_assign_batch_ct_dev",
+    "ot_transpose_batch_dev", "ot_transport_dev",
     "ot_schedule_get", "ot_schedule_set", "ot_schedule_tune", "ot_schedule_rule",
     "ot_split_get", "ot_split_set", "ot_split_tune", "ot_split_rule",
     "ot_grid_cost_dev", "ot_serve_open", "ot_serve_submit", "ot_serve_poll", "ot_serve_stats", "ot_serve_close",
@@ -127,6 +128,8 @@ def load():
         lib.ot_transpose_batch_dev.argtypes = [_I32, _I32, _VP, _VP, _VP, _VP, _VP]
         lib.ot_assign_batch_dev.argtypes = [_I32, _I32, _VP, _VP, _VP, _VP, _VP, _VP, _I32, _I32, _VP, _VP, _VP, _VP, _VP,
                                             _VP]
+        lib.ot_assign_batch_ct_dev.argtypes = [_I32, _I32, _VP, _VP, _VP, _VP, _VP, _VP, _I32, _I32, _VP, _VP, _VP, _VP,
+                                               _VP, _VP]
         lib.ot_transport_dev.argtypes = [_VP, _VP, _VP, _I32, _I32, _I32, _VP, _VP, _VP, _VP, _VP, _VP]
         lib.ot_schedule_get.argtypes = [_VP, _VP]
         lib.ot_schedule_set.argtypes = [_I32, _I32]
@@ -454,6 +457,18 @@ def ot_assign_batch_dev(count, max_n, C, coff, n, voff, plan, cost, u=None, v=No
                                     _tp(order), int(nq or 0), int(block), _tp(plan), _tp(cost), _tp(u), _tp(v),
                                     _tp(stats), _stream(stream))
     _check(rc, "ot_assign_batch_dev")
+
+
+def ot_assign_batch_ct_dev(count, max_n, C, CT, coff, n, voff, plan, cost, u=None, v=None, stats=None, order=None,
+                           block=0, stream=None, nq=None):
+    """ot_assign_batch_dev with the transposes written by the launch into the
+    workspace `CT` (same size as C) and read back to recompute stale columns."""
+    if order is not None and nq is None:
+        nq = int(order.numel())
+    rc = load().ot_assign_batch_ct_dev(int(count), int(max_n), _tp(C), _tp(CT), _tp(coff), _tp(n), _tp(voff),
+                                       _tp(order), int(nq or 0), int(block), _tp(plan), _tp(cost), _tp(u), _tp(v),
+                                       _tp(stats), _stream(stream))
+    _check(rc, "ot_assign_batch_ct_dev")
 
 
 def ot_transpose_batch_dev(count, max_n, C, coff, n, CT, stream=None):

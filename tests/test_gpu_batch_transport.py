@@ -155,6 +155,59 @@ def test_batch_dev_with_transposes_matches_without(otkm_gpu):
         assert int(outs[1][1][k]) == oracle.assign(Cs[k])[1]
 
 
+def test_batch_ct_dev_writes_transposes_and_matches(otkm_gpu):
+    # ot_assign_batch_ct_dev: the launch's flag pass writes every matrix's
+    # transpose into the workspace and the refreshes read it; the outputs equal
+    # those of ot_assign_batch_dev, eagerly and on graph replays
+    import torch
+    sizes = np.concatenate([wl.embedding_sizes(72, lo=16, hi=512, seed=9), [1, 2, 63, 64, 65, 127, 129, 511, 512]])
+    Cs = [wl.embedding_problem(int(n), 9, k) for k, n in enumerate(sizes)]
+    ns, dC, dcoff, dn, dvoff, dorder, vtot = _pack_device(Cs)
+    count, max_n = len(Cs), int(ns.max())
+    s = torch.cuda.Stream()
+
+    def outputs():
+        return (torch.empty(vtot, dtype=torch.int32, device="cuda"), torch.empty(count, dtype=torch.int64, device="cuda"),
+                torch.empty(vtot, dtype=torch.int64, device="cuda"), torch.empty(vtot, dtype=torch.int64, device="cuda"),
+                otkm_gpu.stats_tensor(count))
+    ref = outputs()
+    with torch.cuda.stream(s):
+        otkm_gpu.ot_assign_batch_dev(count, max_n, dC, dcoff, dn, dvoff, *ref[:4], ref[4], order=dorder, stream=s)
+    s.synchronize()
+    assert int(ref[4][:, 7].abs().max()) == 0
+    got = outputs()
+    dCT = torch.full_like(dC, -1)
+
+    def launch():
+        otkm_gpu.ot_assign_batch_ct_dev(count, max_n, dC, dCT, dcoff, dn, dvoff, *got[:4], got[4], order=dorder,
+                                        stream=s)
+    with torch.cuda.stream(s):
+        launch()
+    s.synchronize()
+    assert int(got[4][:, 7].abs().max()) == 0
+    for k in range(count):
+        o, n = int(dcoff[k]), int(ns[k])
+        assert torch.equal(dCT[o:o + n * n].view(n, n).cpu(), torch.from_numpy(Cs[k].T.copy())), k
+    for a, b in zip(ref[:4], got[:4]):
+        assert torch.equal(a, b)
+    assert torch.equal(ref[4][:, 0], got[4][:, 0])  # same level counts
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        launch()
+    for rep in range(2):
+        for t in got[:4]:
+            t.fill_(-1)
+        dCT.fill_(-1)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        say("fused transposes, replay", rep)
+        for a, b in zip(ref[:4], got[:4]):
+            assert torch.equal(a, b)
+    for k in range(0, count, 10):
+        assert int(got[1][k]) == oracle.assign(Cs[k])[1]
+
+
 def test_transport_pixel_config(otkm_gpu):
     C, r, c = wl.pixel_histogram_pair()
     say("transport 784x784, S=1024")
