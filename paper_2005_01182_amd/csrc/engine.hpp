@@ -888,6 +888,41 @@ struct Engine {
     ctl[es] = 0;
   }
 
+  // One round of a stale column's gather: GU forest rows per lane (list
+  // entries f0, f0 + stride, ...), their trees and duals, and their entries
+  // of the column (loads possibly still in flight).
+  struct GatherSet {
+    int i[GU], t[GU];
+    int64_t h[GU];
+    int32_t c[GU];
+  };
+  __device__ __forceinline__ void gather_load(GatherSet &X, const int32_t *colp, size_t cstride, int f0, int stride,
+                                              int nf) {
+#pragma unroll
+    for (int q = 0; q < GU; ++q) {
+      const int f = f0 + q * stride;
+      X.i[q] = f < nf ? fst[f] : 0;
+      if ((unsigned)X.i[q] >= (unsigned)rows()) { fail(OT_EINTERNAL); X.i[q] = 0; }
+      X.t[q] = f < nf ? rtree[X.i[q]] : -1;
+      X.h[q] = hrow[X.i[q]];
+    }
+#pragma unroll
+    for (int q = 0; q < GU; ++q) X.c[q] = colp[(size_t)X.i[q] * cstride];
+  }
+  __device__ __forceinline__ void gather_fold(const GatherSet &X, int64_t v, Key &a1, int &ta1, Key &a2, int &ta2) {
+#pragma unroll
+    for (int q = 0; q < GU; ++q) {
+      if (X.t[q] < 0) continue;
+      int64_t val = (int64_t)X.c[q] - X.h[q] - v;
+      if (val < 0) { fail(OT_EINTERNAL); val = 0; }
+      top2_push(a1, ta1, a2, ta2, kpack(val, X.i[q]), X.t[q]);
+    }
+  }
+  static __device__ __forceinline__ Key wmin_key(Key x) {
+    if constexpr (COMPACT) return wave_min_u32(x);
+    else return wave_min_u64(x);
+  }
+
   // Recompute stale keys that could be the next minimum.  Returns cost
   // entries read; sets `resweep` when a full re-sweep of the forest was used.
   __device__ __forceinline__ int64_t refresh_stale(uint64_t mv, bool &resweep, int &swept) {
@@ -937,33 +972,41 @@ struct Engine {
         Key a1 = KINF, a2 = KINF;
         int ta1 = -1, ta2 = -1;
         const int stride = 64 * wpc;
-        for (int f0 = slice * 64 + lane; f0 < nf; f0 += GU * stride) {
-          int i[GU], t[GU];
-          int64_t h[GU];
-          int32_t c[GU];
-#pragma unroll
-          for (int q = 0; q < GU; ++q) {
-            const int f = f0 + q * stride;
-            i[q] = f < nf ? fst[f] : 0;
-            if ((unsigned)i[q] >= (unsigned)rows()) { fail(OT_EINTERNAL); i[q] = 0; }
-            t[q] = f < nf ? rtree[i[q]] : -1;
-            h[q] = hrow[i[q]];
+        // GU forest rows per lane at a time; the next GU rows' reads are issued
+        // before the current ones are folded, so a long forest list pays about
+        // one memory latency instead of one per round
+        // (one-instance kernels; the batched kernels keep one round in flight
+        // to spare registers)
+        const int f00 = slice * 64 + lane;
+        if constexpr (LONG) {
+          if (f00 - lane < nf) {
+            GatherSet a;
+            gather_load(a, colp, cstride, f00, stride, nf);
+            for (int f0 = f00 + GU * stride; f0 - lane < nf; f0 += GU * stride) {
+              GatherSet b;
+              gather_load(b, colp, cstride, f0, stride, nf);
+              gather_fold(a, v, a1, ta1, a2, ta2);
+              a = b;
+            }
+            gather_fold(a, v, a1, ta1, a2, ta2);
           }
-#pragma unroll
-          for (int q = 0; q < GU; ++q) c[q] = colp[(size_t)i[q] * cstride];
-#pragma unroll
-          for (int q = 0; q < GU; ++q) {
-            if (t[q] < 0) continue;
-            int64_t val = (int64_t)c[q] - h[q] - v;
-            if (val < 0) { fail(OT_EINTERNAL); val = 0; }
-            top2_push(a1, ta1, a2, ta2, kpack(val, i[q]), t[q]);
+        } else {
+          for (int f0 = f00; f0 - lane < nf; f0 += GU * stride) {
+            GatherSet a;
+            gather_load(a, colp, cstride, f0, stride, nf);
+            gather_fold(a, v, a1, ta1, a2, ta2);
           }
         }
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) {
-          Key b1 = __shfl_xor(a1, off, 64), b2 = __shfl_xor(a2, off, 64);
-          int tb1 = __shfl_xor(ta1, off, 64), tb2 = __shfl_xor(ta2, off, 64);
-          top2_merge(a1, ta1, a2, ta2, b1, tb1, b2, tb2);
+        // the wavefront's top-2: its best key, then the best over the lanes of
+        // the candidates outside the best key's tree (a lane's own best when
+        // that is from another tree, else its second); the trees of the two
+        // winners are read back from rtree
+        {
+          const Key w1 = wmin_key(a1);
+          const int tw1 = w1 == KINF ? -1 : rtree[kr(w1)];
+          const Key w2 = wmin_key(ta1 != tw1 ? a1 : a2);
+          const int tw2 = w2 == KINF ? -1 : rtree[kr(w2)];
+          a1 = w1; ta1 = tw1; a2 = w2; ta2 = tw2;
         }
         if (lane == 0) {
           if (wpc == 1) { gk1[s] = a1; gt1[s] = ta1; gk2[s] = a2; gt2[s] = ta2; }
