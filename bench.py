@@ -583,6 +583,11 @@ def bench_sparse(args):
                                                oracle_cost_equal=True)
         return out
     count = args.sparse_count
+    if count > 1024:
+        # the launch takes at most one instance per resident workgroup
+        # (ot_assign_sparse_batch_dev refuses more)
+        raise SystemExit("--sparse-count above 1024 is not run: a batch whose workgroups each took several "
+                         "instances faulted the GPU once, and that mode stays off until its cause is known")
     log("generating %d sparse k-NN instances" % count)
     graphs = wl.knn_batch(count, k=k, seed=0)
     max_m = max(g[4] for g in graphs)

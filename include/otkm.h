@@ -373,7 +373,11 @@ typedef struct ot_sparse_desc {
 /* Many sparse instances in one persistent launch (one workgroup per instance
  * at a time), asynchronous on stream.  ddesc [count] lives in device memory;
  * max_m bounds every instance's m (it sizes the on-chip state; an instance
- * above it reports OT_EINVAL).  Per-instance status in its stats. */
+ * above it reports OT_EINVAL).  Per-instance status in its stats.  count may
+ * not exceed the workgroups resident at once for max_m (1,792 at max_m = 512
+ * on MI355X; OT_ETOOBIG above): a launch whose workgroups took several
+ * instances each faulted the GPU, and that mode stays off until the cause is
+ * known. */
 int ot_assign_sparse_batch_dev(int32_t count, const ot_sparse_desc *ddesc, int32_t max_m, void *stream);
 
 /* ------------------------------------------------------------------------ */

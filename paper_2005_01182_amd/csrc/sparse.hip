@@ -23,34 +23,31 @@ __global__ __launch_bounds__(BLOCK) void k_sparse_one(SparseProblem P) {
   E.run(P, smem);
 }
 
-// many instances: each workgroup takes the next descriptor until none is left
+// many instances: each workgroup takes one descriptor from the queue and
+// solves it (the launch has one workgroup per instance)
 template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_sparse_batch(const ot_sparse_desc *desc, int count, int max_m,
                                                          int32_t *head) {
   extern __shared__ __align__(16) char smem[];
   __shared__ int s_k;
-  for (;;) {
-    if (threadIdx.x == 0) s_k = atomicAdd(head, 1);
-    __syncthreads();
-    const int k = s_k;
-    __syncthreads();
-    if (k >= count) break;  // every workgroup reaches this exit once the queue drains
-    const ot_sparse_desc d = desc[k];
-    if (d.n < 1 || d.m < d.n || d.m > max_m || !d.ptr || !d.plan || !d.total) {
-      if (threadIdx.x == 0 && d.stats) {
-        ot_stats s = {};
-        s.status = OT_EINVAL;
-        *d.stats = s;
-      }
-      continue;
+  if (threadIdx.x == 0) s_k = atomicAdd(head, 1);
+  __syncthreads();
+  const int k = s_k;
+  if (k >= count) return;  // uniform across the workgroup
+  const ot_sparse_desc d = desc[k];
+  if (d.n < 1 || d.m < d.n || d.m > max_m || !d.ptr || !d.plan || !d.total) {
+    if (threadIdx.x == 0 && d.stats) {
+      ot_stats s = {};
+      s.status = OT_EINVAL;
+      *d.stats = s;
     }
-    SparseProblem P;
-    P.ptr = d.ptr; P.idx = d.idx; P.cost = d.cost; P.n = d.n; P.m = d.m;
-    P.plan = d.plan; P.total = d.total; P.u = d.u; P.v = d.v; P.stats = d.stats;
-    SparseEngine<BLOCK> E;
-    E.run(P, smem);
-    __syncthreads();
+    return;
   }
+  SparseProblem P;
+  P.ptr = d.ptr; P.idx = d.idx; P.cost = d.cost; P.n = d.n; P.m = d.m;
+  P.plan = d.plan; P.total = d.total; P.u = d.u; P.v = d.v; P.stats = d.stats;
+  SparseEngine<BLOCK> E;
+  E.run(P, smem);
 }
 
 int block_for(int m) { return m <= 256 ? 64 : 256; }
@@ -73,16 +70,22 @@ hipError_t launch_sparse_one(const SparseProblem &P, hipStream_t s) {
   return hipGetLastError();
 }
 
+// Workgroups of the batch kernel resident at once for instances of at most
+// max_m columns (0 on error).
+template <int BLOCK>
+int sparse_batch_slots(int max_m) {
+  const size_t lds = sparse_lds(max_m, max_m).total;
+  if (set_lds<k_sparse_batch<BLOCK>>(lds) != hipSuccess) return 0;
+  int occ = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void *)k_sparse_batch<BLOCK>, BLOCK, lds) != hipSuccess)
+    return 0;
+  return std::max(1, occ) * device_cus();
+}
+
 template <int BLOCK>
 hipError_t launch_sparse_batch_t(const ot_sparse_desc *desc, int count, int max_m, int32_t *head, hipStream_t s) {
   const size_t lds = sparse_lds(max_m, max_m).total;
-  hipError_t e;
-  if ((e = set_lds<k_sparse_batch<BLOCK>>(lds)) != hipSuccess) return e;
-  int occ = 0;
-  if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void *)k_sparse_batch<BLOCK>, BLOCK, lds)) !=
-      hipSuccess)
-    return e;
-  const int grid = std::max(1, std::min(count, std::max(1, occ) * device_cus()));
+  const int grid = std::max(1, count);  // the caller has checked count against the resident slots
   hipLaunchKernelGGL(k_sparse_batch<BLOCK>, dim3(grid), dim3(BLOCK), lds, s, desc, count, max_m, head);
   return hipGetLastError();
 }
@@ -192,6 +195,13 @@ int ot_assign_sparse_batch_dev(int32_t count, const ot_sparse_desc *ddesc, int32
   int rc = init_locked();
   if (rc) return rc;
   hipStream_t s = stream ? (hipStream_t)stream : lib_stream();
+  // at most one instance per resident workgroup: a launch whose workgroups
+  // would take further instances from the queue faulted the GPU once on
+  // MI355X (4096 k-NN instances, n <= 512) and is refused until its cause is
+  // found
+  const int slots = block_for(max_m) == 64 ? sparse_batch_slots<64>(max_m) : sparse_batch_slots<256>(max_m);
+  if (slots <= 0) return OT_EINTERNAL;
+  if (count > slots) return OT_ETOOBIG;
   int err = OT_OK;
   auto *head = (int32_t *)stream_ws(s, 203, 256, &err);
   if (err) return err;

@@ -190,6 +190,16 @@ def test_batch_against_oracle(otkm_gpu):
     assert int(outs[-1][4][0, 7]) == otkm_gpu.OT_EINVAL
 
 
+def test_batch_refuses_more_instances_than_resident_workgroups(otkm_gpu):
+    # a launch takes one instance per resident workgroup; a larger count is
+    # refused on the host before anything is launched
+    import torch
+    descs = torch.zeros(72 * 4, dtype=torch.uint8, device="cuda")
+    with pytest.raises(otkm_gpu.OtError) as e:
+        otkm_gpu.ot_assign_sparse_batch_dev(descs, 1 << 20, 512)
+    assert e.value.code == otkm_gpu.OT_ETOOBIG
+
+
 def test_full_size_knn_4096(otkm_gpu):
     g = wl.knn_assignment(4096, k=16, seed=1)
     say("sparse knn 4096 x 4096, k = 16")
