@@ -687,16 +687,27 @@ def bench_batch(args):
     dCT = torch.empty_like(dC) if args.transposes != "none" else None
     max_all = int(sizes.max())
 
+    # each size class on a stream of its own, forked from and joined back into
+    # the launch's stream (the graph runs the classes side by side, so a small
+    # class fills the CUs the last instances of a large one leave idle)
+    side = [stream] * len(classes) if args.serial_classes else [torch.cuda.Stream() for _ in classes]
+
     def launch():
         if ct_kernel:
             ot.ot_transpose_batch_dev(count, max_all, dC, dcoff, dn, dCT, stream=stream)
-        for block, max_n, order in classes:
-            if ct_fused and not (block == 64 and max_n <= 64):
-                ot.ot_assign_batch_ct_dev(count, max_n, dC, dCT, dcoff, dn, dvoff, plan, cost, u, v, st, order=order,
-                                          block=block, stream=stream)
-            else:
-                ot.ot_assign_batch_dev(count, max_n, dC, dcoff, dn, dvoff, plan, cost, u, v, st, order=order,
-                                       block=block, stream=stream, CT=dCT if ct_kernel else None)
+        for (block, max_n, order), sk in zip(classes, side):
+            if sk is not stream:
+                sk.wait_stream(stream)
+            with torch.cuda.stream(sk):
+                if ct_fused and not (block == 64 and max_n <= 64):
+                    ot.ot_assign_batch_ct_dev(count, max_n, dC, dCT, dcoff, dn, dvoff, plan, cost, u, v, st,
+                                              order=order, block=block, stream=sk)
+                else:
+                    ot.ot_assign_batch_dev(count, max_n, dC, dcoff, dn, dvoff, plan, cost, u, v, st, order=order,
+                                           block=block, stream=sk, CT=dCT if ct_kernel else None)
+        for sk in side:
+            if sk is not stream:
+                stream.wait_stream(sk)
 
     with torch.cuda.stream(stream):
         launch()  # eager run sizes the workspaces
@@ -732,8 +743,9 @@ def bench_batch(args):
                      "schedule": {"wave_max_n": t64, "wg256_max_n": t256},
                      "classes": [[blk, mx, int(o.numel())] for blk, mx, o in classes],
                      "transposes": args.transposes,
-                     "launch": "hipGraph replay of %sthe flag pass and one persistent kernel per size class" %
-                               ("the batched transpose, " if ct_kernel else "")})
+                     "launch": "hipGraph replay of %sthe flag pass and one persistent kernel per size class%s" %
+                               ("the batched transpose, " if ct_kernel else "",
+                                ", one after another" if args.serial_classes else ", the classes on parallel streams")})
     out["roofline"] = roofline(float(b.sum()) + transpose_bytes, float(np.mean(per)) / 1e3)
     # the committed counter summary covers every kernel of the default launch
     if args.transposes == "fused":
@@ -873,6 +885,8 @@ def main():
                     help="batch mode: transposes for single-column refreshes, written by the launch's flag pass "
                          "(fused, ot_assign_batch_ct_dev), by a kernel of their own in every launch (kernel), or "
                          "none (refreshes gather down C)")
+    ap.add_argument("--serial-classes", action="store_true",
+                    help="batch mode: launch the size classes one after another on one stream")
     ap.add_argument("--phase-timers", action="store_true", help="one extra solve with device phase timers")
     ap.add_argument("--cold", action="store_true",
                     help="geometric/small: read 512 MiB before every timed solve (C starts out of the MALL)")
