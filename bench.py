@@ -779,9 +779,10 @@ def bench_batch(args):
         workers = max(1, min(16, host_info()["host_threads"]))
         log("cpu baseline: oracle pool of %d processes, then single-threaded" % workers)
         prate, pdone, pcosts = cpu_pool_rate(Cs, args.cpu_budget, workers)
+        # the single-threaded leg times the first problems again, as many as the budget allows
         t0 = time.perf_counter()
         sdone = 0
-        for k in range(pdone, count):
+        for k in range(count):
             if oracle.assign(Cs[k])[1] != int(gpu_cost[k]):
                 raise SystemExit("GPU cost of problem %d differs from the oracle's" % k)
             sdone += 1
@@ -793,9 +794,9 @@ def bench_batch(args):
         out["cpu_baseline"] = cpu_baseline(prate, "solves/s", workers,
                                            "problems 0..%d of the batch (sizes as drawn), the single-threaded C "
                                            "oracle in a pool of %d processes" % (pdone - 1, workers),
-                                           oracle_cost_equal=pdone + sdone,
+                                           oracle_cost_equal=max(pdone, sdone),
                                            single_thread={"value": round(srate, 4), "cores": 1,
-                                                          "sample": "problems %d..%d" % (pdone, pdone + sdone - 1)})
+                                                          "sample": "problems 0..%d" % (sdone - 1)})
     return out
 
 
