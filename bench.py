@@ -205,6 +205,26 @@ def solve_series(ot, torch, dC, n, steps, warmup, max_paths, stream, block=0, ti
     return per, stats, t_start.elapsed_time(t_end), int(cost.item())
 
 
+def solve_throughput(ot, torch, dC, n, steps, stream, block=0, expect_cost=None):
+    """Total ms of `steps` back-to-back solves on `stream`, timed by one pair of
+    events around all of them."""
+    plan = torch.empty(n, dtype=torch.int32, device="cuda")
+    cost = torch.empty(1, dtype=torch.int64, device="cuda")
+    st = ot.stats_tensor(steps)
+    torch.cuda.synchronize()
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0.record(stream)
+    for k in range(steps):
+        ot.ot_assign_dev(dC, plan, cost, stats=st[k], stream=stream, block=block)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    if int(st[:, F["status"]].abs().max()) != 0:
+        raise SystemExit("solver reported a nonzero status in the throughput series")
+    if expect_cost is not None and int(cost.item()) != expect_cost:
+        raise SystemExit("throughput series cost %d differs from %d" % (int(cost.item()), expect_cost))
+    return t0.elapsed_time(t1)
+
+
 def bench_assign(args, C, workload, cpu_samples, tag):
     import torch
 
@@ -218,6 +238,10 @@ def bench_assign(args, C, workload, cpu_samples, tag):
                                            flush=flush)
     if flush is not None:
         total = float(np.sum(per))  # the flushes between solves are not part of the work
+    else:
+        # throughput from a second series with no events between the solves
+        # (the per-solve events above give the latencies)
+        total = solve_throughput(ot, torch, dC, n, args.steps, stream, block=args.block, expect_cost=cost)
     b = alg_bytes(stats, [n] * len(stats))
     out = base_line(args, args.steps / (total / 1e3), "solves/s", total / args.steps,
                     {"workload": workload, "n": n, "method": "batched KM (trees from every free row)",
