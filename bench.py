@@ -697,8 +697,15 @@ def bench_batch(args):
         ot.ot_schedule_tune(4)
     t64, t256 = ot.ot_schedule_get()
     classes = []   # (block, max_n, order tensor) longest first within each class
-    # one wavefront's class splits at n = 64, where the whole instance fits its registers
+    # one wavefront's class splits at n = 64, where the whole instance fits its
+    # registers; with --classes cpt every width's range splits again where the
+    # columns per lane double, so each instance runs with the fewest that hold it
+    ranges = []
     for lo, hi, block in ((0, min(64, t64), 64), (min(64, t64), t64, 64), (t64, t256, 256), (t256, 1 << 30, 512)):
+        cuts = [block * c for c in (1, 2, 4, 8) if lo < block * c < hi] if args.classes == "cpt" else []
+        edges = [lo] + cuts + [hi]
+        ranges += [(a, b, block) for a, b in zip(edges[:-1], edges[1:])]
+    for lo, hi, block in ranges:
         idx = np.nonzero((sizes > lo) & (sizes <= hi))[0]
         if len(idx) == 0:
             continue
@@ -910,6 +917,9 @@ def main():
                     help="batch mode: transposes for single-column refreshes, written by the launch's flag pass "
                          "(fused, ot_assign_batch_ct_dev), by a kernel of their own in every launch (kernel), or "
                          "none (refreshes gather down C)")
+    ap.add_argument("--classes", choices=("width", "cpt"), default="width",
+                    help="batch mode: size classes by width only (longest first across all sizes of a width), or "
+                         "split again by columns per lane (cpt)")
     ap.add_argument("--serial-classes", action="store_true",
                     help="batch mode: launch the size classes one after another on one stream")
     ap.add_argument("--phase-timers", action="store_true", help="one extra solve with device phase timers")
