@@ -695,6 +695,8 @@ def bench_batch(args):
     if args.tune:
         log("autotuning the size-class schedule")
         ot.ot_schedule_tune(4)
+    elif args.schedule:
+        ot.ot_schedule_set(*[int(x) for x in args.schedule.split(",")])
     t64, t256 = ot.ot_schedule_get()
     classes = []   # (block, max_n, order tensor) longest first within each class
     # one wavefront's class splits at n = 64, where the whole instance fits its
@@ -917,6 +919,9 @@ def main():
                     help="batch mode: transposes for single-column refreshes, written by the launch's flag pass "
                          "(fused, ot_assign_batch_ct_dev), by a kernel of their own in every launch (kernel), or "
                          "none (refreshes gather down C)")
+    ap.add_argument("--schedule", default="",
+                    help="batch mode: size-class thresholds T64,T256 (one wavefront up to T64, 256 lanes up to "
+                         "T256); empty = the library's")
     ap.add_argument("--classes", choices=("width", "cpt"), default="width",
                     help="batch mode: size classes by width only (longest first across all sizes of a width), or "
                          "split again by columns per lane (cpt)")
