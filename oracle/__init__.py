@@ -23,6 +23,9 @@ Functions (all exact, int64 results):
                              along the edges of a CSR cost graph; raises ``Infeasible``
                              when no matching covers every row
 * ``certify_sparse(ptr, idx, cst, n, m, plan, u, v)`` -> 0 if the sparse LP certificate holds
+* ``auction(C, eps0, theta, eps_final)`` -> (plan, price, cost, bids)  auction with
+                             epsilon-scaling (Section 2.3.3), rewards -C * (n + 1), one
+                             bidder at a time; exact at eps_final = 1
 """
 from __future__ import annotations
 
@@ -70,10 +73,11 @@ def _load():
             lib.oracle_transport_ssp.argtypes = [_I32P, _I32P, _I32P, i32, i32, _I32P, _I64P, _I64P, i64p]
             lib.oracle_assign_sparse.argtypes = [_I64P, _I32P, _I32P, i32, i32, _I32P, _I64P, _I64P, i64p]
             lib.oracle_certify_sparse.argtypes = [_I64P, _I32P, _I32P, i32, i32, _I32P, _I64P, _I64P]
+            lib.oracle_auction.argtypes = [_I32P, i32, ctypes.c_int64, i32, ctypes.c_int64, _I32P, _I64P, i64p, i64p]
             for f in (lib.oracle_assign, lib.oracle_brute_force, lib.oracle_certify_assign,
                       lib.oracle_assign_rect, lib.oracle_certify_rect,
                       lib.oracle_transport, lib.oracle_certify_transport, lib.oracle_transport_ssp,
-                      lib.oracle_assign_sparse, lib.oracle_certify_sparse):
+                      lib.oracle_assign_sparse, lib.oracle_certify_sparse, lib.oracle_auction):
                 f.restype = ctypes.c_int
             _lib = lib
     return _lib
@@ -274,3 +278,20 @@ def certify_sparse(ptr, idx, cst, n: int, m: int, plan, u, v) -> int:
     if plan.shape != (n,) or u.shape != (n,) or v.shape != (m,):
         return 1
     return int(_load().oracle_certify_sparse(ptr, idx, cst, n, m, plan, u, v))
+
+
+def auction(C, eps0: int, theta: int, eps_final: int = 1):
+    """Auction with epsilon-scaling (Section 2.3.3): returns (plan int32[n],
+    price int64[n] in units of 1/(n+1) of a cost, cost int, bids int).  The
+    slack runs eps0, eps0 / theta, ... down to eps_final (same units)."""
+    C = _square(C)
+    n = C.shape[0]
+    plan = np.empty(n, np.int32)
+    price = np.empty(n, np.int64)
+    cost = ctypes.c_int64(0)
+    bids = ctypes.c_int64(0)
+    rc = _load().oracle_auction(C, n, int(eps0), int(theta), int(eps_final), plan, price, ctypes.byref(cost),
+                                ctypes.byref(bids))
+    if rc:
+        raise RuntimeError("oracle_auction failed: %d" % rc)
+    return plan, price, int(cost.value), int(bids.value)

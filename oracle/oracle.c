@@ -24,6 +24,10 @@
  * Rectangular matrices (n != m, unit masses) are solved by the same
  * shortest-augmenting-path method over the longer side (oracle_assign_rect).
  *
+ * oracle_auction is the auction algorithm with epsilon-scaling (Section
+ * 2.3.3), one bidder at a time, in exact integer arithmetic; its pins are the
+ * KM oracle's optimal cost, brute force and the paper's n * eps bound.
+ *
  * All arithmetic is exact in int64.  Every function returns 0 on success or a
  * negative code for invalid input.
  */
@@ -705,4 +709,80 @@ int oracle_certify_sparse(const int64_t *ptr, const int32_t *idx, const int32_t 
     for (int32_t i = 0; i < n; ++i) dual += u[i];
     for (int32_t j = 0; j < m; ++j) dual += v[j];
     return primal == dual ? 0 : 5;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Auction with epsilon-scaling (Section 2.3.3; Bertsekas 1989)              */
+/* ------------------------------------------------------------------------- */
+/*
+ * Rows are bidders, columns are objects, the reward of row i for column j is
+ * R_ij = -C_ij.  Arithmetic is exact integer: rewards are multiplied by
+ * (n + 1), so a slack of eps = 1 on that scale is eps < 1/n on the costs,
+ * where the paper notes that the auction's result is exact for integer
+ * weights (a result within n * eps of the optimum).  eps_final > 1 gives a
+ * plan within floor(n * eps_final / (n + 1)) of the optimal cost.
+ *
+ * Each phase (eps = eps0, then eps / theta, ..., down to eps_final) starts
+ * with every row unassigned and the prices of the previous phase.  Bidding
+ * is one bidder at a time (Gauss-Seidel), first in first out: the bidder
+ * finds its best value v1 = R_ij1 - p_j1 and the best value v2 over the
+ * other columns, raises p_j1 by v1 - v2 + eps, takes j1 and evicts j1's
+ * previous owner, who queues again.  Ties among best columns go to the
+ * smaller column index.  n = 1: v2 is taken as v1 (the raise is eps).
+ *
+ * Outputs: plan[i] = column of row i, price[j] (scaled units), *cost =
+ * sum_i C[i][plan[i]], *bids = total bids.  Returns 0, ORC_EINVAL, or
+ * ORC_ENOMEM.
+ */
+int oracle_auction(const int32_t *C, int32_t n, int64_t eps0, int32_t theta, int64_t eps_final,
+                   int32_t *plan, int64_t *price, int64_t *cost, int64_t *bids)
+{
+    if (!C || !plan || !price || !cost || n <= 0 || eps_final < 1 || eps0 < eps_final || theta < 2)
+        return ORC_EINVAL;
+    const int64_t scale = (int64_t)n + 1;
+    int32_t *owner = malloc(sizeof(int32_t) * (size_t)n);
+    int32_t *queue = malloc(sizeof(int32_t) * (size_t)n);
+    if (!owner || !queue) { free(owner); free(queue); return ORC_ENOMEM; }
+    for (int32_t j = 0; j < n; ++j) price[j] = 0;
+    int64_t nb = 0;
+    int64_t eps = eps0;
+    for (;;) {
+        for (int32_t i = 0; i < n; ++i) { plan[i] = -1; owner[i] = -1; queue[i] = i; }
+        /* circular FIFO of unassigned rows: at most n are queued at once */
+        int32_t head = 0, count = n;
+        while (count > 0) {
+            const int32_t i = queue[head];
+            head = (head + 1) % n;
+            --count;
+            const int32_t *row = C + (size_t)i * (size_t)n;
+            int32_t j1 = 0;
+            int64_t v1 = -(int64_t)row[0] * scale - price[0], v2 = INT64_MIN;
+            for (int32_t j = 1; j < n; ++j) {
+                const int64_t val = -(int64_t)row[j] * scale - price[j];
+                if (val > v1) { v2 = v1; v1 = val; j1 = j; }
+                else if (val > v2) v2 = val;
+            }
+            if (n == 1) v2 = v1;
+            price[j1] += v1 - v2 + eps;
+            const int32_t prev = owner[j1];
+            owner[j1] = i;
+            plan[i] = j1;
+            ++nb;
+            if (prev >= 0) {
+                plan[prev] = -1;
+                queue[(head + count) % n] = prev;
+                ++count;
+            }
+        }
+        if (eps == eps_final) break;
+        eps = eps / theta;
+        if (eps < eps_final) eps = eps_final;
+    }
+    int64_t total = 0;
+    for (int32_t i = 0; i < n; ++i) total += C[(size_t)i * (size_t)n + (size_t)plan[i]];
+    *cost = total;
+    if (bids) *bids = nb;
+    free(owner);
+    free(queue);
+    return 0;
 }
