@@ -413,6 +413,66 @@ def bench_rect(args):
     return out
 
 
+def bench_auction(args):
+    """Auction with epsilon-scaling (Section 2.3.3) on the geometric instance:
+    exact (final slack below 1/n of a cost), one workgroup, parallel bidding."""
+    import torch
+
+    from paper_2005_01182_amd import otkm as ot
+    from paper_2005_01182_amd import workloads as wl
+    n = args.n or 2048
+    C = np.asarray(wl.geometric_assignment(n, seed=0), np.int32)
+    theta = args.theta
+    eps0 = ot.auction_eps0(C, theta)
+    dC = torch.from_numpy(C).cuda()
+    stream = torch.cuda.Stream()
+    plan = torch.empty(n, dtype=torch.int32, device="cuda")
+    cost = torch.empty(1, dtype=torch.int64, device="cuda")
+    price = torch.empty(n, dtype=torch.int64, device="cuda")
+    st = ot.stats_tensor(args.steps + args.warmup)
+    log("auction n=%d theta=%d eps0=%d: warmup %d, steps %d" % (n, theta, eps0, args.warmup, args.steps))
+    for w in range(args.warmup):
+        ot.ot_auction_dev(dC, eps0, theta, 1, plan, cost, price, st[w], stream=stream)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0.record(stream)
+    for k in range(args.steps):
+        ev[k][0].record(stream)
+        ot.ot_auction_dev(dC, eps0, theta, 1, plan, cost, price, st[args.warmup + k], stream=stream)
+        ev[k][1].record(stream)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    per = [a.elapsed_time(b) for a, b in ev]
+    total = t0.elapsed_time(t1)
+    stats = st[args.warmup:].cpu().numpy()
+    if int(np.abs(stats[:, F["status"]]).max()) != 0:
+        raise SystemExit("auction status %s" % stats[:, F["status"]])
+    b = alg_bytes(stats, [n] * len(stats))  # every bid reads its row of C once
+    out = base_line(args, args.steps / (total / 1e3), "solves/s", total / args.steps,
+                    {"workload": "geometric assignment: circle vs square perimeter, sigma 0.02, "
+                                 "C = rint(1e4 * distance) int32, n = %d, seed 0" % n,
+                     "n": n, "method": "auction with epsilon-scaling, Jacobi bidding, rewards -C (n + 1), "
+                                       "eps %d / %d^k down to 1" % (eps0, theta),
+                     "optimal_cost": int(cost.item())})
+    out["metric"] = "solves/s, auction with epsilon-scaling"
+    out["roofline"] = roofline(float(np.mean(b)), float(np.mean(per)) / 1e3)
+    out["latency_ms"] = {"p50": pct(per, 50), "p99": pct(per, 99)}
+    out["solver_counters"] = {"rounds": int(stats[0, F["levels"]]), "phases": int(stats[0, F["aug_events"]]),
+                              "bids": int(stats[0, F["rows_swept"]]), "alg_bytes_per_solve": int(b[0])}
+    if not args.skip_cpu:
+        import oracle
+        fn = lambda M: oracle.auction(M, eps0, theta, 1)
+        if fn(C)[2] != int(cost.item()):
+            raise SystemExit("GPU cost differs from the oracle's")
+        rate, done = cpu_rate(fn, [C] * 50, args.cpu_budget)
+        out["cpu_baseline"] = cpu_baseline(rate, "solves/s", 1,
+                                           "%d solve(s) of the same instance by the single-threaded C oracle "
+                                           "(auction, one bidder at a time, the same slacks)" % done,
+                                           oracle_cost_equal=True)
+    return out
+
+
 def bench_small(args):
     from paper_2005_01182_amd import workloads as wl
     C = wl.uniform_assignment(64, seed=0)
@@ -906,8 +966,9 @@ def main():
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
     ap.add_argument("--mode", default="geometric", choices=["geometric", "small", "transport", "batch", "serve",
-                                                             "copy", "scaled", "rect", "bins", "sparse"])
-    ap.add_argument("--n", type=int, default=None, help="geometric / scaled: n (2048); sparse: n (4096)")
+                                                             "copy", "scaled", "rect", "bins", "sparse", "auction"])
+    ap.add_argument("--n", type=int, default=None,
+                    help="geometric / scaled / auction: n (2048); sparse: n (4096)")
     ap.add_argument("--count", type=int, default=4096, help="batch mode: number of problems")
     ap.add_argument("--plain-steps", type=int, default=3)
     ap.add_argument("--plain-count", type=int, default=256, help="batch mode: instances in the per-launch comparison")
@@ -919,6 +980,7 @@ def main():
                     help="batch mode: transposes for single-column refreshes, written by the launch's flag pass "
                          "(fused, ot_assign_batch_ct_dev), by a kernel of their own in every launch (kernel), or "
                          "none (refreshes gather down C)")
+    ap.add_argument("--theta", type=int, default=8, help="auction mode: slack reduction factor per phase")
     ap.add_argument("--schedule", default="",
                     help="batch mode: size-class thresholds T64,T256 (one wavefront up to T64, 256 lanes up to "
                          "T256); empty = the library's")
@@ -964,7 +1026,8 @@ def main():
     else:
         out = {"geometric": bench_geometric, "small": bench_small, "transport": bench_transport,
                "batch": bench_batch, "copy": bench_copy, "scaled": bench_scaled,
-               "rect": bench_rect, "bins": bench_bins, "sparse": bench_sparse}[args.mode](args)
+               "rect": bench_rect, "bins": bench_bins, "sparse": bench_sparse,
+               "auction": bench_auction}[args.mode](args)
     print(json.dumps(out), flush=True)
 
 

@@ -381,6 +381,35 @@ typedef struct ot_sparse_desc {
 int ot_assign_sparse_batch_dev(int32_t count, const ot_sparse_desc *ddesc, int32_t max_m, void *stream);
 
 /* ------------------------------------------------------------------------ */
+/* Auction with epsilon-scaling (Section 2.3.3)                              */
+/* ------------------------------------------------------------------------ */
+/* The auction algorithm on a dense n x n int32 cost matrix (row-major),
+ * rows bidding for columns with rewards -C_ij.  Prices and slacks are in
+ * units of 1/(n + 1) of a cost, so all arithmetic is exact: the slack runs
+ * eps0, eps0 / theta, eps0 / theta^2, ... (integer division, never below
+ * eps_final) and each value starts a phase with every row unassigned and
+ * the prices kept.  eps_final = 1 is a slack below 1/n of a cost, where the
+ * result is an optimal assignment (Section 2.3.3: the plan is within n * eps
+ * of the optimum, and the costs are integers); a larger eps_final gives a
+ * plan within floor(n * eps_final / (n + 1)) of the optimal cost.  Bidding
+ * is parallel (every unassigned row bids in each round), one workgroup per
+ * instance with all state on chip.
+ * plan[n]: column of each row; cost: sum of C over the plan; price[n] (may
+ * be NULL): the final column prices, in the scaled units above.  stats (may
+ * be NULL): levels = bidding rounds, aug_events = phases, rows_swept = bids,
+ * paths = n, status.
+ * Errors: OT_EINVAL (NULL C / plan / cost, n < 1, theta < 2, eps_final < 1,
+ * eps0 < eps_final, ld < n), OT_ETOOBIG (n > OT_MAX_N), OT_ERANGE (eps0 >=
+ * 2^50, or a price reaching 2^51: reported in status), OT_EINTERNAL (more
+ * than 2^22 rounds).  ot_auction copies C from host memory and waits;
+ * ot_auction_dev takes device pointers (row stride ld), runs on stream
+ * (NULL = the library's stream), allocates nothing and returns at once. */
+int ot_auction(const int32_t *C, int32_t n, int64_t eps0, int32_t theta, int64_t eps_final, int32_t *plan,
+               int64_t *cost, int64_t *price, ot_stats *stats);
+int ot_auction_dev(const int32_t *dC, int32_t n, int32_t ld, int64_t eps0, int32_t theta, int64_t eps_final,
+                   int32_t *dplan, int64_t *dcost, int64_t *dprice, ot_stats *dstats, void *stream);
+
+/* ------------------------------------------------------------------------ */
 /* Serving: continuous batching of assignment requests                       */
 /* ------------------------------------------------------------------------ */
 /* Each request is an assignment between n source and n target points on the

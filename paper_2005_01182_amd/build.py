@@ -14,7 +14,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libotkm.so")
 SOURCES = ["solve_one_lo.hip", "solve_one_hi.hip", "solve_batch_lo.hip", "solve_batch_hi.hip", "solve_grid.hip",
-           "kernels.hip", "runtime.hip", "autotune.hip", "serve.hip", "serve_kernel.hip", "noalloc.hip", "bins.hip", "sparse.hip"]
+           "kernels.hip", "runtime.hip", "autotune.hip", "serve.hip", "serve_kernel.hip", "noalloc.hip", "bins.hip", "sparse.hip", "auction.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 

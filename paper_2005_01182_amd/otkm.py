@@ -32,6 +32,7 @@ EXPORTS = [
     "ot_split_get", "ot_split_set", "ot_split_tune", "ot_split_rule",
     "ot_grid_cost_dev", "ot_serve_open", "ot_serve_submit", "ot_serve_poll", "ot_serve_stats", "ot_serve_close",
     "ot_assign_sparse", "ot_assign_sparse_dev", "ot_assign_sparse_batch_dev",
+    "ot_auction", "ot_auction_dev",
 ]
 
 
@@ -121,6 +122,9 @@ def load():
         lib.ot_assign_sparse.argtypes = [_VP, _VP, _VP, _I32, _I32, _VP, _VP, _VP, _VP, _VP]
         lib.ot_assign_sparse_dev.argtypes = [_VP, _VP, _VP, _I32, _I32, ctypes.c_int64, _VP, _VP, _VP, _VP, _VP, _VP]
         lib.ot_assign_sparse_batch_dev.argtypes = [_I32, _VP, _I32, _VP]
+        lib.ot_auction.argtypes = [_VP, _I32, ctypes.c_int64, _I32, ctypes.c_int64, _VP, _VP, _VP, _VP]
+        lib.ot_auction_dev.argtypes = [_VP, _I32, _I32, ctypes.c_int64, _I32, ctypes.c_int64, _VP, _VP, _VP, _VP,
+                                       _VP]
         lib.ot_assign_batch.argtypes = [_I32, _VP, _VP, _VP, _VP, _VP, _VP, _VP]
         lib.ot_assign_dev.argtypes = [_VP, _I32, _I32, _VP, _VP, _VP, _VP, _VP, _VP, _VP]
         lib.ot_assign_dev_noalloc.argtypes = [_VP, _I32, _I32, _VP, _VP, _VP, _VP, _VP, _VP, _VP]
@@ -235,6 +239,35 @@ def ot_assign_rect(C, max_paths: int = 0, block: int = 0, with_stats: bool = Fal
                                ctypes.byref(st))
     _check(rc, "ot_assign_rect")
     out = (plan, int(cost.value), u, v)
+    return out + (st.as_dict(),) if with_stats else out
+
+
+def auction_eps0(C, theta: int) -> int:
+    """A starting slack for ot_auction: the cost range in the scaled units
+    (times n + 1) divided by theta, at least 1."""
+    C = np.asarray(C)
+    n = int(C.shape[0])
+    return max(1, (int(C.max()) - int(C.min())) * (n + 1) // int(theta))
+
+
+def ot_auction(C, eps0: int = 0, theta: int = 8, eps_final: int = 1, with_stats: bool = False):
+    """Auction with epsilon-scaling on a square int32 cost matrix (exact at
+    eps_final = 1).  eps0 = 0 takes auction_eps0(C, theta).  Returns
+    (plan, cost, price) or (plan, cost, price, stats_dict)."""
+    C = np.ascontiguousarray(C, dtype=np.int32)
+    if C.ndim != 2 or C.shape[0] != C.shape[1]:
+        raise ValueError("square cost matrix required")
+    n = C.shape[0]
+    if eps0 <= 0:
+        eps0 = max(int(eps_final), auction_eps0(C, theta))
+    plan = np.empty(n, np.int32)
+    price = np.empty(n, np.int64)
+    cost = ctypes.c_int64(0)
+    st = ot_stats()
+    rc = load().ot_auction(_p(C), n, int(eps0), int(theta), int(eps_final), _p(plan), ctypes.byref(cost), _p(price),
+                           ctypes.byref(st))
+    _check(rc, "ot_auction")
+    out = (plan, int(cost.value), price)
     return out + (st.as_dict(),) if with_stats else out
 
 
@@ -491,6 +524,14 @@ def ot_assign_sparse_dev(ptr, idx, cost, n, m, plan, total, u=None, v=None, stat
     rc = load().ot_assign_sparse_dev(_tp(ptr), _tp(idx), _tp(cost), int(n), int(m), nnz, _tp(plan), _tp(total),
                                      _tp(u), _tp(v), _tp(stats), _stream(stream))
     _check(rc, "ot_assign_sparse_dev")
+
+
+def ot_auction_dev(C, eps0, theta, eps_final, plan, cost, price=None, stats=None, stream=None):
+    """Queue an auction solve on a device cost tensor (asynchronous on `stream`)."""
+    n = int(C.shape[0])
+    rc = load().ot_auction_dev(_tp(C), n, int(C.stride(0)), int(eps0), int(theta), int(eps_final), _tp(plan),
+                               _tp(cost), _tp(price), _tp(stats), _stream(stream))
+    _check(rc, "ot_auction_dev")
 
 
 def sparse_descs(items, device="cuda"):

@@ -1,0 +1,157 @@
+"""GPU parity of the auction with epsilon-scaling (Section 2.3.3).
+
+At eps_final = 1 (a slack below 1/n of a cost) the GPU's total must equal the
+optimal cost of the KM oracle and of the oracle's own auction; the plan is a
+permutation with that total, and the GPU's final prices satisfy
+epsilon-complementary slackness, which with integer costs certifies the plan
+as optimal at any size.  Plans may differ from the oracle's where several
+plans are optimal (the GPU bids in parallel rounds, the oracle one bidder at a
+time), so the plan itself is checked, not compared.  Larger eps_final values
+must stay within the paper's n * eps bound.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2005_01182_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def eps_cs(C, plan, price, eps):
+    n = C.shape[0]
+    val = -C.astype(np.int64) * (n + 1) - price[None, :]
+    got = val[np.arange(n), plan]
+    return bool(np.all(got >= val.max(axis=1) - eps))
+
+
+def check(ot, C, theta=8, eps_final=1, opt=None):
+    n = C.shape[0]
+    plan, cost, price, st = ot.ot_auction(C, 0, theta, eps_final, with_stats=True)
+    assert st["status"] == 0 and st["paths"] == n
+    assert sorted(plan.tolist()) == list(range(n))
+    assert cost == int(C[np.arange(n), plan].sum())
+    assert eps_cs(C, plan, price, eps_final)
+    if opt is not None:
+        if eps_final == 1:
+            assert cost == opt
+        else:
+            assert opt <= cost <= opt + (n * eps_final) // (n + 1)
+    return plan, cost, price, st
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 63, 64, 65, 100, 513, 1000])
+@pytest.mark.parametrize("kind", ["uniform", "ties", "negative"])
+def test_auction_equals_oracle(otkm_gpu, n, kind):
+    say("auction", kind, n)
+    rng = np.random.default_rng(500 + n + 7 * len(kind))
+    lo, hi = {"uniform": (0, 1000), "ties": (0, 3), "negative": (-5000, 5000)}[kind]
+    C = rng.integers(lo, hi, (n, n)).astype(np.int32)
+    _, opt, _, _ = oracle.assign(C)
+    theta = 8
+    _, _, ocost, _ = oracle.auction(C, max(1, otkm_gpu.auction_eps0(C, theta)), theta, 1)
+    assert ocost == opt
+    check(otkm_gpu, C, theta, 1, opt)
+
+
+@pytest.mark.parametrize("theta", [2, 4, 16])
+def test_auction_scaling_factors(otkm_gpu, theta):
+    say("auction theta", theta)
+    C = np.random.default_rng(theta).integers(0, 10000, (300, 300)).astype(np.int32)
+    _, opt, _, _ = oracle.assign(C)
+    check(otkm_gpu, C, theta, 1, opt)
+
+
+def test_auction_slack_bound(otkm_gpu):
+    say("auction eps_final > 1")
+    rng = np.random.default_rng(9)
+    for n in (10, 77, 260):
+        C = rng.integers(0, 100, (n, n)).astype(np.int32)
+        _, opt, _, _ = oracle.assign(C)
+        for ef in (n + 1, 5 * (n + 1)):
+            check(otkm_gpu, C, 4, ef, opt)
+
+
+def test_auction_full_int32_range(otkm_gpu):
+    say("auction full int32 range")
+    C = np.random.default_rng(4).integers(-2**31, 2**31 - 1, (150, 150), dtype=np.int64).astype(np.int32)
+    _, opt, _, _ = oracle.assign(C)
+    check(otkm_gpu, C, 8, 1, opt)
+
+
+def test_auction_closed_form(otkm_gpu):
+    say("auction closed form")
+    n = 129
+    perm = np.random.default_rng(2).permutation(n)
+    C = np.full((n, n), 7, np.int32)
+    C[np.arange(n), perm] = 0
+    plan, cost, _, _ = check(otkm_gpu, C, 8, 1, 0)
+    assert np.array_equal(plan, perm)
+
+
+def test_auction_device_call_strided_and_repeated(otkm_gpu):
+    """The device call on a view with row stride ld > n, twice in a row with a
+    smaller instance second (the on-chip state starts afresh)."""
+    import torch
+    say("auction device call")
+    rng = np.random.default_rng(21)
+    for n in (700, 90):
+        W = rng.integers(0, 5000, (n, n + 13)).astype(np.int32)
+        C = np.ascontiguousarray(W[:, :n])
+        _, opt, _, _ = oracle.assign(C)
+        dW = torch.from_numpy(W).cuda()
+        plan = torch.empty(n, dtype=torch.int32, device="cuda")
+        cost = torch.empty(1, dtype=torch.int64, device="cuda")
+        price = torch.empty(n, dtype=torch.int64, device="cuda")
+        st = otkm_gpu.stats_tensor(1)
+        otkm_gpu.ot_auction_dev(dW[:, :n], otkm_gpu.auction_eps0(C, 8), 8, 1, plan, cost, price, st[0])
+        torch.cuda.synchronize()
+        assert int(st[0, 7]) == 0
+        assert int(cost.item()) == opt
+        p = plan.cpu().numpy()
+        assert sorted(p.tolist()) == list(range(n))
+        assert eps_cs(C, p, price.cpu().numpy(), 1)
+
+
+def test_auction_geometric_full_size(otkm_gpu):
+    """The headline instance (geometric, n = 2048): the optimal cost of the
+    KM oracle."""
+    say("auction geometric 2048")
+    C = np.asarray(wl.geometric_assignment(2048, 0), np.int32)
+    _, opt, _, _ = oracle.assign(C)
+    _, _, _, st = check(otkm_gpu, C, 8, 1, opt)
+    say("rounds", st["levels"], "phases", st["aug_events"], "bids", st["rows_swept"])
+
+
+def test_auction_largest_size(otkm_gpu):
+    """n = OT_MAX_N = 4096 (147.7 KB of on-chip state): a permutation whose
+    prices certify it (epsilon-complementary slackness below 1/n)."""
+    say("auction 4096")
+    C = np.random.default_rng(31).integers(0, 1000, (4096, 4096)).astype(np.int32)
+    check(otkm_gpu, C, 8, 1)
+
+
+def test_auction_rejects(otkm_gpu):
+    say("auction argument errors")
+    lib = otkm_gpu.load()
+    C = np.zeros((8, 8), np.int32)
+    plan = np.empty(8, np.int32)
+    import ctypes
+    cost = ctypes.c_int64(0)
+    P = otkm_gpu._p
+    cases = [(8, 10, 1, 1, otkm_gpu.OT_EINVAL),      # theta < 2
+             (8, 0, 4, 1, otkm_gpu.OT_EINVAL),       # eps0 < eps_final
+             (8, 10, 4, 0, otkm_gpu.OT_EINVAL),      # eps_final < 1
+             (0, 10, 4, 1, otkm_gpu.OT_EINVAL),      # n < 1
+             (4097, 10, 4, 1, otkm_gpu.OT_ETOOBIG),  # n > OT_MAX_N
+             (8, 1 << 50, 4, 1, otkm_gpu.OT_ERANGE)]
+    for n, eps0, theta, ef, want in cases:
+        rc = lib.ot_auction(P(C), n, eps0, theta, ef, P(plan), ctypes.byref(cost), None, None)
+        assert rc == want, (n, eps0, theta, ef, rc)
