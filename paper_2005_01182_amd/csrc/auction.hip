@@ -47,16 +47,53 @@ struct AuctionArgs {
 
 __host__ __device__ inline size_t auction_lds_bytes(int n) { return (size_t)n * 36 + 256; }
 
+// Wavefront reductions (all 64 lanes active): rotations inside each 16-lane
+// row (DPP), then the four row results through scalar reads; uniform result.
+template <int CTRL>
+__device__ __forceinline__ int64_t dpp_i64(int64_t x) {
+  const int lo = __builtin_amdgcn_mov_dpp((int)(uint32_t)(uint64_t)x, CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(uint32_t)((uint64_t)x >> 32), CTRL, 0xf, 0xf, false);
+  return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+__device__ __forceinline__ int64_t lane_i64(int64_t x, int l) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(uint64_t)x, l);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)x >> 32), l);
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
 __device__ __forceinline__ int64_t wave_max_i64(int64_t x) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) x = max(x, (int64_t)__shfl_xor((long long)x, off, 64));
-  return x;
+  x = max(x, dpp_i64<0x121>(x));  // row_ror:1
+  x = max(x, dpp_i64<0x122>(x));  // row_ror:2
+  x = max(x, dpp_i64<0x124>(x));  // row_ror:4
+  x = max(x, dpp_i64<0x128>(x));  // row_ror:8
+  return max(max(lane_i64(x, 0), lane_i64(x, 16)), max(lane_i64(x, 32), lane_i64(x, 48)));
 }
 __device__ __forceinline__ int wave_min_int(int x) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) x = min(x, __shfl_xor(x, off, 64));
-  return x;
+  x = min(x, __builtin_amdgcn_update_dpp(INT_MAX, x, 0x121, 0xf, 0xf, false));
+  x = min(x, __builtin_amdgcn_update_dpp(INT_MAX, x, 0x122, 0xf, 0xf, false));
+  x = min(x, __builtin_amdgcn_update_dpp(INT_MAX, x, 0x124, 0xf, 0xf, false));
+  x = min(x, __builtin_amdgcn_update_dpp(INT_MAX, x, 0x128, 0xf, 0xf, false));
+  return min(min(__builtin_amdgcn_readlane(x, 0), __builtin_amdgcn_readlane(x, 16)),
+             min(__builtin_amdgcn_readlane(x, 32), __builtin_amdgcn_readlane(x, 48)));
 }
+
+// One lane's running best value (column j1) and best value over its other
+// columns; columns arrive in increasing order, so a tie keeps the smaller.
+struct Top2 {
+  int64_t b1 = INT64_MIN, b2 = INT64_MIN;
+  int j1 = INT_MAX;
+  __device__ __forceinline__ void push(int64_t val, int j) {
+    if (val > b1) { b2 = b1; b1 = val; j1 = j; }
+    else if (val > b2) b2 = val;
+  }
+  // merge another lane-local summary (a tie goes to the smaller column)
+  __device__ __forceinline__ void merge(const Top2 &o) {
+    if (o.b1 > b1 || (o.b1 == b1 && o.j1 < j1)) {
+      b2 = max(o.b2, b1); b1 = o.b1; j1 = o.j1;
+    } else {
+      b2 = max(b2, o.b1);
+    }
+  }
+};
 
 __global__ __launch_bounds__(kAucBlock) void k_auction(AuctionArgs A) {
   extern __shared__ __align__(16) char smem[];
@@ -95,8 +132,7 @@ __global__ __launch_bounds__(kAucBlock) void k_auction(AuctionArgs A) {
       for (int e = wid; e < cnt; e += kAucWaves) {
         const int i = lc[e];
         const int32_t *row = A.C + (size_t)i * (size_t)A.ld;
-        int64_t b1 = INT64_MIN, b2 = INT64_MIN;
-        int j1 = INT_MAX;
+        Top2 ta, tb;  // two independent chains: even and odd loads
         // the whole row's loads (up to 2048 columns) are issued before any is
         // used, so a bid pays one memory latency
         for (int j0 = 0; j0 < n; j0 += kAucLoads * 64) {
@@ -111,11 +147,14 @@ __global__ __launch_bounds__(kAucBlock) void k_auction(AuctionArgs A) {
             const int j = j0 + q * 64 + lane;
             if (j < n) {
               const int64_t val = -(int64_t)c[q] * scale - price[j];
-              if (val > b1) { b2 = b1; b1 = val; j1 = j; }  // columns in increasing order per lane
-              else if (val > b2) b2 = val;
+              if (q & 1) tb.push(val, j);
+              else ta.push(val, j);
             }
           }
         }
+        ta.merge(tb);
+        const int64_t b1 = ta.b1, b2 = ta.b2;
+        const int j1 = ta.j1;
         // the best value, its smallest column, and the best value elsewhere
         const int64_t v1 = wave_max_i64(b1);
         const int jb = wave_min_int(b1 == v1 ? j1 : INT_MAX);
