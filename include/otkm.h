@@ -403,7 +403,8 @@ int ot_assign_sparse_batch_dev(int32_t count, const ot_sparse_desc *ddesc, int32
  * 2^50, or a price reaching 2^51: reported in status), OT_EINTERNAL (more
  * than 2^22 rounds).  ot_auction copies C from host memory and waits;
  * ot_auction_dev takes device pointers (row stride ld), runs on stream
- * (NULL = the library's stream), allocates nothing and returns at once. */
+ * (NULL = the library's stream), allocates no device memory and returns at
+ * once. */
 int ot_auction(const int32_t *C, int32_t n, int64_t eps0, int32_t theta, int64_t eps_final, int32_t *plan,
                int64_t *cost, int64_t *price, ot_stats *stats);
 int ot_auction_dev(const int32_t *dC, int32_t n, int32_t ld, int64_t eps0, int32_t theta, int64_t eps_final,
