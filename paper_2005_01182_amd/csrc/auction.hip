@@ -8,7 +8,7 @@
 //
 // One workgroup of 1024 threads solves one instance with every piece of
 // state in LDS (prices, pending bids, owners, the row -> column map and the
-// lists of unassigned rows: 36n + 256 bytes, 147.7 KB at n = 4096).  Bidding
+// lists of unassigned rows: 36n + 576 bytes, 148.0 KB at n = 4096).  Bidding
 // is Jacobi style, the parallel form the paper points to: in a round every
 // unassigned row bids at once (one wavefront per bidder scans its cost row,
 // coalesced), a bid is one 64-bit LDS atomic maximum of (price << 12 | row)
@@ -45,7 +45,7 @@ struct AuctionArgs {
   ot_stats *stats;        // may be null
 };
 
-__host__ __device__ inline size_t auction_lds_bytes(int n) { return (size_t)n * 36 + 256; }
+__host__ __device__ inline size_t auction_lds_bytes(int n) { return (size_t)n * 36 + 576; }
 
 // Wavefront reductions (all 64 lanes active): rotations inside each 16-lane
 // row (DPP), then the four row results through scalar reads; uniform result.
@@ -95,13 +95,65 @@ struct Top2 {
   }
 };
 
+// One lane's top-2 over the columns [js, je) of a cost row: all its loads
+// (up to 32 a lane) issued before any is used, two independent chains.
+__device__ __forceinline__ Top2 scan_row(const int32_t *row, int js, int je, int n, int lane, const int64_t *price,
+                                         int64_t scale) {
+  Top2 ta, tb;
+  for (int j0 = js; j0 < je; j0 += kAucLoads * 64) {
+    int32_t c[kAucLoads];
+#pragma unroll
+    for (int q = 0; q < kAucLoads; ++q) {
+      const int j = j0 + q * 64 + lane;
+      c[q] = row[j < je ? j : n - 1];
+    }
+#pragma unroll
+    for (int q = 0; q < kAucLoads; ++q) {
+      const int j = j0 + q * 64 + lane;
+      if (j < je) {
+        const int64_t val = -(int64_t)c[q] * scale - price[j];
+        if (q & 1) tb.push(val, j);
+        else ta.push(val, j);
+      }
+    }
+  }
+  ta.merge(tb);
+  return ta;
+}
+
+// The wavefront's best value v1, its smallest column jb, and the best value
+// over the other columns v2 (uniform).
+__device__ __forceinline__ void wave_top2(const Top2 &t, int64_t &v1, int &jb, int64_t &v2) {
+  v1 = wave_max_i64(t.b1);
+  jb = wave_min_int(t.b1 == v1 ? t.j1 : INT_MAX);
+  v2 = wave_max_i64(t.j1 == jb ? t.b2 : t.b1);
+}
+
+// Bid of list entry e (row i) for column jb: the price rises by the gap to
+// the second-best value plus eps, as an atomic maximum of price << 12 | row.
+__device__ __forceinline__ void place_bid(int e, int i, int jb, int64_t v1, int64_t v2, int64_t eps,
+                                          const int64_t *price, unsigned long long *bid, int32_t *bidobj, int *ctl,
+                                          int64_t *red) {
+  const int64_t nb = price[jb] + (v1 - v2) + eps;
+  if (nb >= kAucBidLimit) {
+    atomicOr(&ctl[2], 1);
+    bidobj[e] = -1;
+  } else {
+    atomicMax(&bid[jb], ((unsigned long long)nb << kAucRowBits) | (unsigned long long)i);
+    bidobj[e] = jb;
+  }
+  atomicAdd((unsigned long long *)&red[16], 1ull);
+}
+
 __global__ __launch_bounds__(kAucBlock) void k_auction(AuctionArgs A) {
   extern __shared__ __align__(16) char smem[];
   const int n = A.n;
   int64_t *price = (int64_t *)smem;                                  // [n]
   unsigned long long *bid = (unsigned long long *)(smem + 8 * (size_t)n);  // [n], 0 = none
   int64_t *red = (int64_t *)(smem + 16 * (size_t)n);                 // [24]: cost partials, [16] bids
-  int32_t *owner = (int32_t *)(smem + 16 * (size_t)n + 192);         // [n] row holding column j
+  int64_t *pv1 = red + 24, *pv2 = red + 40;                          // [16] each: slice top-2 values
+  int32_t *pj = (int32_t *)(red + 56);                               // [16]: slice best columns
+  int32_t *owner = (int32_t *)(smem + 16 * (size_t)n + 512);         // [n] row holding column j
   int32_t *rowobj = owner + n;                                       // [n] column held by row i
   int32_t *list0 = rowobj + n;                                       // [n] unassigned rows
   int32_t *list1 = list0 + n;                                        // [n]
@@ -128,48 +180,45 @@ __global__ __launch_bounds__(kAucBlock) void k_auction(AuctionArgs A) {
       int32_t *ln = cur ? list0 : list1;
       // the next round's count: last read before the previous round's end
       if (tid == 0) ctl[cur ^ 1] = 0;
-      // (1) bids: wavefront w takes the entries w, w + 16, ...
-      for (int e = wid; e < cnt; e += kAucWaves) {
-        const int i = lc[e];
-        const int32_t *row = A.C + (size_t)i * (size_t)A.ld;
-        Top2 ta, tb;  // two independent chains: even and odd loads
-        // the whole row's loads (up to 2048 columns) are issued before any is
-        // used, so a bid pays one memory latency
-        for (int j0 = 0; j0 < n; j0 += kAucLoads * 64) {
-          int32_t c[kAucLoads];
-#pragma unroll
-          for (int q = 0; q < kAucLoads; ++q) {
-            const int j = j0 + q * 64 + lane;
-            c[q] = row[j < n ? j : n - 1];
-          }
-#pragma unroll
-          for (int q = 0; q < kAucLoads; ++q) {
-            const int j = j0 + q * 64 + lane;
-            if (j < n) {
-              const int64_t val = -(int64_t)c[q] * scale - price[j];
-              if (q & 1) tb.push(val, j);
-              else ta.push(val, j);
-            }
-          }
+      if (cnt * 2 <= kAucWaves && n > kAucLoads * 64) {
+        // (1a) few bidders on rows longer than one batch of loads: G
+        // wavefronts share each bidder's row (G a power of two, cnt * G <=
+        // 16), each scanning one contiguous slice, and publish their slice's
+        // top-2; then one thread per bidder merges the slices in column order
+        // and bids (measured: 1252 -> 1029 ms at n = 4096; at n <= 2048 the
+        // extra barrier costs more than the shorter scan saves)
+        int G = kAucWaves;
+        while (cnt * G > kAucWaves) G >>= 1;
+        if (wid < cnt * G) {
+          const int e = wid / G, g = wid % G;
+          const int seg = (n + G - 1) / G;
+          const int js = min(n, g * seg), je = min(n, js + seg);
+          const Top2 t = scan_row(A.C + (size_t)lc[e] * (size_t)A.ld, js, je, n, lane, price, scale);
+          int64_t v1, v2;
+          int jb;
+          wave_top2(t, v1, jb, v2);
+          if (lane == 0) { pv1[wid] = v1; pv2[wid] = v2; pj[wid] = jb; }
         }
-        ta.merge(tb);
-        const int64_t b1 = ta.b1, b2 = ta.b2;
-        const int j1 = ta.j1;
-        // the best value, its smallest column, and the best value elsewhere
-        const int64_t v1 = wave_max_i64(b1);
-        const int jb = wave_min_int(b1 == v1 ? j1 : INT_MAX);
-        int64_t v2 = wave_max_i64(j1 == jb ? b2 : b1);
-        if (n == 1) v2 = v1;
-        if (lane == 0) {
-          const int64_t nb = price[jb] + (v1 - v2) + eps;
-          if (nb >= kAucBidLimit) {
-            atomicOr(&ctl[2], 1);
-            bidobj[e] = -1;
-          } else {
-            atomicMax(&bid[jb], ((unsigned long long)nb << kAucRowBits) | (unsigned long long)i);
-            bidobj[e] = jb;
+        __syncthreads();
+        if (tid < cnt) {
+          const int e = tid;
+          int64_t v1 = pv1[e * G], v2 = pv2[e * G];
+          int jb = pj[e * G];
+          for (int g = 1; g < G; ++g) {  // slices in increasing column order: a tie keeps the earlier column
+            const int64_t o1 = pv1[e * G + g], o2 = pv2[e * G + g];
+            if (o1 > v1) { v2 = max(o2, v1); v1 = o1; jb = pj[e * G + g]; }
+            else v2 = max(v2, o1);
           }
-          atomicAdd((unsigned long long *)&red[16], 1ull);
+          place_bid(e, lc[e], jb, v1, n == 1 ? v1 : v2, eps, price, bid, bidobj, ctl, red);
+        }
+      } else {
+        // (1b) bids: wavefront w takes the entries w, w + 16, ...
+        for (int e = wid; e < cnt; e += kAucWaves) {
+          const Top2 t = scan_row(A.C + (size_t)lc[e] * (size_t)A.ld, 0, n, n, lane, price, scale);
+          int64_t v1, v2;
+          int jb;
+          wave_top2(t, v1, jb, v2);
+          if (lane == 0) place_bid(e, lc[e], jb, v1, n == 1 ? v1 : v2, eps, price, bid, bidobj, ctl, red);
         }
       }
       __syncthreads();

@@ -130,6 +130,15 @@ def test_auction_geometric_full_size(otkm_gpu):
     say("rounds", st["levels"], "phases", st["aug_events"], "bids", st["rows_swept"])
 
 
+def test_auction_rows_shared_by_wavefronts(otkm_gpu):
+    """Above n = 2048 the rounds with few bidders split each bidder's row over
+    several wavefronts: the optimal cost of the KM oracle at n = 2500."""
+    say("auction 2500")
+    C = np.random.default_rng(41).integers(0, 3000, (2500, 2500)).astype(np.int32)
+    _, opt, _, _ = oracle.assign(C)
+    check(otkm_gpu, C, 8, 1, opt)
+
+
 def test_auction_largest_size(otkm_gpu):
     """n = OT_MAX_N = 4096 (147.7 KB of on-chip state): a permutation whose
     prices certify it (epsilon-complementary slackness below 1/n)."""
