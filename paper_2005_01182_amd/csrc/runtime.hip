@@ -80,8 +80,10 @@ void *pool_get(int slot, size_t bytes, int *err) {
   if (bytes == 0) bytes = 16;
   if (b.bytes < bytes) {
     if (b.p) {
-      hipStreamSynchronize(g_stream);
-      hipFree(b.p);
+      // queued work may still use the old buffer; an error it left is reported here
+      const hipError_t se = hipStreamSynchronize(g_stream);
+      if (se != hipSuccess) { *err = map_hip(se); return nullptr; }
+      (void)hipFree(b.p);
       b.p = nullptr;
       b.bytes = 0;
     }
@@ -106,8 +108,9 @@ void *stream_ws(hipStream_t s, int slot, size_t bytes, int *err) {
       return nullptr;
     }
     if (b.p) {
-      hipStreamSynchronize(s);
-      hipFree(b.p);
+      const hipError_t se = hipStreamSynchronize(s);
+      if (se != hipSuccess) { *err = map_hip(se); return nullptr; }
+      (void)hipFree(b.p);
       b.p = nullptr;
       b.bytes = 0;
     }
@@ -122,9 +125,11 @@ void *stream_ws(hipStream_t s, int slot, size_t bytes, int *err) {
 void stream_ws_free(hipStream_t s) {
   auto it = g_ws.find(s);
   if (it == g_ws.end()) return;
-  hipStreamSynchronize(s);
+  // the buffers go whatever the stream's last work returned: an error of that
+  // work belongs to the call that queued it
+  (void)hipStreamSynchronize(s);
   for (auto &kv : it->second)
-    if (kv.second.p) hipFree(kv.second.p);
+    if (kv.second.p) (void)hipFree(kv.second.p);
   g_ws.erase(it);
 }
 
