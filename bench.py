@@ -980,7 +980,7 @@ def main():
                     help="batch mode: transposes for single-column refreshes, written by the launch's flag pass "
                          "(fused, ot_assign_batch_ct_dev), by a kernel of their own in every launch (kernel), or "
                          "none (refreshes gather down C)")
-    ap.add_argument("--theta", type=int, default=8, help="auction mode: slack reduction factor per phase")
+    ap.add_argument("--theta", type=int, default=10, help="auction mode: slack reduction factor per phase")
     ap.add_argument("--schedule", default="",
                     help="batch mode: size-class thresholds T64,T256 (one wavefront up to T64, 256 lanes up to "
                          "T256); empty = the library's")
