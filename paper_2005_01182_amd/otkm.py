@@ -250,7 +250,7 @@ def auction_eps0(C, theta: int) -> int:
     return max(1, (int(C.max()) - int(C.min())) * (n + 1) // int(theta))
 
 
-def ot_auction(C, eps0: int = 0, theta: int = 8, eps_final: int = 1, with_stats: bool = False):
+def ot_auction(C, eps0: int = 0, theta: int = 10, eps_final: int = 1, with_stats: bool = False):
     """Auction with epsilon-scaling on a square int32 cost matrix (exact at
     eps_final = 1).  eps0 = 0 takes auction_eps0(C, theta).  Returns
     (plan, cost, price) or (plan, cost, price, stats_dict)."""
